@@ -13,6 +13,7 @@ from .tpfa import (  # noqa: F401
     config2,
     config3,
     config4,
+    config4_sizes,
     config5,
     scaled_config,
     csr_to_dense,

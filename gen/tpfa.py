@@ -65,7 +65,8 @@ def correlated_field(shape, corr_len: float, rng: np.random.Generator) -> np.nda
         bshape[ax] = s
         r2 = r2 + (d * d).reshape(bshape)
     kern = np.exp(-r2 / (corr_len * corr_len))
-    f = np.fft.irfftn(np.fft.rfftn(w) * np.fft.rfftn(kern), s=shape)
+    axes = list(range(len(shape)))
+    f = np.fft.irfftn(np.fft.rfftn(w, axes=axes) * np.fft.rfftn(kern, axes=axes), s=shape, axes=axes)
     f = f - f.mean()
     return f / f.std()
 

@@ -62,6 +62,8 @@ typedef struct {
   int max_coarse;
   int max_levels;
   int check_symmetry;
+  double s_scale; /* S := s_scale * S inside Algorithm 2.1 (1 = the method; 0 = degenerate S = 0) */
+  double b_scale; /* B := b_scale * B inside Algorithm 2.1 and eq. (2.7) (Theorem 2.2 scales B) */
 } or_opts;
 
 typedef struct {
@@ -75,6 +77,7 @@ typedef struct {
   double *chol;        /* lower Cholesky factor of the coarsest matrix, row-major n0 x n0 */
   double *lu;          /* ILU(0) values on the pattern of the finest A                   */
   double *work;        /* scratch vectors                                                 */
+  double s_scale, b_scale;
 } or_hier;
 
 static void csr_free(or_csr* a) {
@@ -582,6 +585,8 @@ void or_default_opts(or_opts* o) {
   o->max_coarse = 256;
   o->max_levels = 25;
   o->check_symmetry = 1;
+  o->s_scale = 1.0;
+  o->b_scale = 1.0;
 }
 
 void or_free(or_hier* h) {
@@ -642,6 +647,8 @@ or_hier* or_setup(int n, const int* rp, const int* ci, const double* v, const or
   if (*status) { or_free(h); return NULL; }
   h->work = (double*)malloc(sizeof(double) * (size_t)n * 8);
   if (!h->work) goto nomem;
+  h->s_scale = o.s_scale;
+  h->b_scale = o.b_scale;
   *status = OR_OK;
   return h;
 nomem:
@@ -790,11 +797,14 @@ static void combined(const or_hier* h, op_fn S, op_fn B, op_fn ST, const double*
   double* r = (double*)malloc(sizeof(double) * (size_t)n);
   double* w = (double*)malloc(sizeof(double) * (size_t)n);
   S(h, f, u);
+  if (h->s_scale != 1.0) for (int i = 0; i < n; ++i) u[i] = h->s_scale * u[i];
   residual(A, f, u, r);
   B(h, r, w);
+  if (h->b_scale != 1.0) for (int i = 0; i < n; ++i) w[i] = h->b_scale * w[i];
   for (int i = 0; i < n; ++i) u[i] = u[i] + w[i];
   residual(A, f, u, r);
   ST(h, r, w);
+  if (h->s_scale != 1.0) for (int i = 0; i < n; ++i) w[i] = h->s_scale * w[i];
   for (int i = 0; i < n; ++i) u[i] = u[i] + w[i];
   free(r);
   free(w);
@@ -825,7 +835,7 @@ int or_apply(const or_hier* h, int which, const double* r, double* z) {
       double* w = (double*)malloc(sizeof(double) * (size_t)n);
       sym_smoother(h, r, z);
       ilu_apply(h, r, w);
-      for (int i = 0; i < n; ++i) z[i] = z[i] + w[i];
+      for (int i = 0; i < n; ++i) z[i] = z[i] + h->b_scale * w[i];
       free(w);
       return OR_OK;
     }

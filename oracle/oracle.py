@@ -30,7 +30,8 @@ _lib = None
 
 class _Opts(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("max_coarse", ctypes.c_int),
-                ("max_levels", ctypes.c_int), ("check_symmetry", ctypes.c_int)]
+                ("max_levels", ctypes.c_int), ("check_symmetry", ctypes.c_int),
+                ("s_scale", ctypes.c_double), ("b_scale", ctypes.c_double)]
 
 
 def build_oracle(force: bool = False) -> Path:
@@ -114,12 +115,13 @@ class Hierarchy:
     """SETUP of the oracle: ILU(0) factors + classical AMG hierarchy."""
 
     def __init__(self, n, row_ptr, col, val, theta=0.25, max_coarse=256, max_levels=25,
-                 check_symmetry=True):
+                 check_symmetry=True, s_scale=1.0, b_scale=1.0):
         lib = _load()
         self._lib = lib
         self.n = int(n)
         rp, ci, v = _csr_args(row_ptr, col, val)
-        o = _Opts(float(theta), int(max_coarse), int(max_levels), int(bool(check_symmetry)))
+        o = _Opts(float(theta), int(max_coarse), int(max_levels), int(bool(check_symmetry)),
+                  float(s_scale), float(b_scale))
         st = ctypes.c_int(0)
         self._h = lib.or_setup(self.n, _ptr(rp), _ptr(ci), _ptr(v), ctypes.byref(o), ctypes.byref(st))
         self.status = st.value
