@@ -1,0 +1,173 @@
+/*
+ * cpc.h — combined-preconditioned conjugate gradients on AMD Instinct MI355X (gfx950).
+ *
+ * Solves A u = f for a sparse symmetric positive definite A (Section 2, eq. 2.1)
+ * by PCG whose preconditioner is the combined operator B_co of Algorithm 2.1:
+ *     u1 = S f,  u2 = u1 + B (f - A u1),  u3 = u2 + S^T (f - A u2),
+ * with S = one classical (Ruge-Stueben) AMG V-cycle with a Gauss-Seidel smoother
+ * on every level (Algorithm 3.2) and B = ILU(0) (Algorithm 3.1 with k = 0),
+ * the assignment of Sections 3 and 5. Work is split as in Section 3.2 into a
+ * SETUP phase (cpc_setup) and a SOLVE phase (cpc_solve).
+ *
+ * Conventions for every call:
+ *   - Every function returns a cpc_status and never aborts or throws. On a status
+ *     other than CPC_OK, cpc_last_error() returns a message (thread-local).
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are memory on the
+ *     GPU the handle was set up on (e.g. a torch tensor's data_ptr()). Device
+ *     vectors are FP64, contiguous, of length n (the finest level's size).
+ *   - Matrices are CSR, 0-based, int32 indices, FP64 values: row_ptr[n+1],
+ *     col_idx[nnz], val[nnz], row_ptr[0] = 0, monotone, columns sorted and unique in
+ *     [0, n) within each row, diagonal present and > 0, numerically symmetric.
+ *   - The handle owns every device buffer it allocates; callers own what they pass.
+ *     All GPU work of a handle is ordered on the stream given to cpc_setup; calls
+ *     that return results to the host synchronise that stream before returning.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef CPC_H
+#define CPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpc_solver* cpc_handle;
+
+typedef enum {
+  CPC_OK = 0,
+  CPC_E_ARG = 1,       /* invalid argument or CSR that breaks the input contract          */
+  CPC_E_NOT_SPD = 2,   /* non-positive diagonal, ILU(0) pivot or coarse Cholesky pivot     */
+  CPC_E_BREAKDOWN = 3, /* PCG breakdown: <p,Ap> <= 0, <r,z> <= 0 or a non-finite value      */
+  CPC_E_MAXIT = 4,     /* no convergence within maxit (x holds the last iterate; this is
+                          the "does not converge" entry of Table 5.2)                       */
+  CPC_E_DEVICE = 5,    /* HIP runtime error or a device-side guard (e.g. a wait limit)      */
+  CPC_E_NOMEM = 6      /* host or device allocation failed                                  */
+} cpc_status;
+
+/* Preconditioners (Table 5.2). */
+typedef enum {
+  CPC_PREC_COMBINED = 0, /* B_co, Algorithm 2.1 (S = V-cycle, B = ILU(0))                   */
+  CPC_PREC_AMG = 1,      /* AMG(GS): two V-cycles, i.e. S~ of Section 2 with S = V-cycle    */
+  CPC_PREC_ILU = 2,      /* ILU(0) alone                                                    */
+  CPC_PREC_ADDITIVE = 3, /* B^ = S~ + B, eq. (2.7) with W_1 = V, Pi_1 = I, A_1^{-1} = B      */
+  CPC_PREC_NONE = 4      /* identity (plain CG)                                             */
+} cpc_prec;
+
+/* Operators applied by cpc_apply_op (each z = M r from a zero initial guess). */
+typedef enum {
+  CPC_OP_COMBINED = 0, /* B_co                                                              */
+  CPC_OP_AMG = 1,      /* two V-cycles (S~)                                                 */
+  CPC_OP_ILU = 2,      /* (LU)^{-1}                                                         */
+  CPC_OP_ADDITIVE = 3, /* S~ + (LU)^{-1}                                                    */
+  CPC_OP_NONE = 4,     /* identity                                                          */
+  CPC_OP_VCYCLE = 5,   /* one V-cycle (Algorithm 3.2)                                       */
+  CPC_OP_FGS = 6,      /* (D+L)^{-1} on the finest level (one forward Gauss-Seidel sweep)   */
+  CPC_OP_BGS = 7       /* (D+U)^{-1} on the finest level (one backward Gauss-Seidel sweep)  */
+} cpc_op;
+
+typedef enum {
+  CPC_FP64 = 0,        /* everything in FP64                                                */
+  CPC_FP32_PRECOND = 1 /* preconditioner data and vectors in FP32 with FP64 row sums; PCG
+                          vectors, outer residuals, reductions and the coarsest solve FP64  */
+} cpc_precision;
+
+typedef struct {
+  int32_t struct_size;    /* sizeof(cpc_options); set by cpc_default_options                */
+  int32_t prec;           /* cpc_prec used by cpc_solve (default CPC_PREC_COMBINED)         */
+  int32_t precision;      /* cpc_precision (default CPC_FP64)                               */
+  int32_t max_coarse;     /* a level with at most this many rows is solved exactly (256)    */
+  int32_t max_levels;     /* at most this many levels (25)                                  */
+  int32_t swap_roles;     /* 0: S = V-cycle, B = ILU(0) (Section 3); 1: S = ILU(0), B = V   */
+  int32_t check_symmetry; /* 1: reject CSR that is not numerically symmetric (O(nnz) check) */
+  int32_t use_graph;      /* 1: replay each PCG iteration as a captured HIP graph           */
+  int32_t check_every;    /* PCG iterations between host reads of the convergence flag (4)  */
+  int32_t rap_on_gpu;     /* 1: Galerkin products on the GPU (default); 0 is not offered     */
+  int32_t sweep_block_rows; /* rows per workgroup block of the triangular sweeps (0 = auto)  */
+  double theta;           /* strength threshold of the classical coarsening (0.25)          */
+} cpc_options;
+
+typedef struct {
+  int32_t iters;          /* PCG iterations of the last solve                               */
+  int32_t status;         /* cpc_status of the last solve                                   */
+  double relres;          /* ||r_k||/||b|| of the recursively updated residual at exit     */
+  double setup_s;         /* wall seconds of cpc_setup                                      */
+  double solve_s;         /* wall seconds of the last cpc_solve (device-synchronised)       */
+  double bytes_per_iter;  /* algorithmic HBM bytes of one PCG iteration (byte model)        */
+  double bytes_initial;   /* algorithmic bytes before the first iteration                   */
+} cpc_stats;
+
+/* Fill *opt with the defaults listed above. */
+void cpc_default_options(cpc_options* opt);
+
+/* SETUP (Section 3.2): validate the host CSR, factor ILU(0) (Algorithm 3.1, k = 0),
+ * build the classical AMG hierarchy (C/F splitting and Ruge-Stueben interpolation
+ * on the host, Galerkin products A_l = P_l^T A_{l+1} P_l on the GPU), factor the
+ * coarsest matrix, build the sweep schedules and upload everything.
+ *   n, row_ptr, col_idx, val : host CSR (copied; may be freed on return).
+ *   opt                      : NULL for defaults.
+ *   hip_stream               : hipStream_t to order all work on (NULL = default stream).
+ *   out                      : receives the handle (NULL on failure).
+ * Errors: CPC_E_ARG (contract), CPC_E_NOT_SPD, CPC_E_NOMEM, CPC_E_DEVICE. */
+cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                     const cpc_options* opt, void* hip_stream, cpc_handle* out);
+
+/* SOLVE: PCG (preconditioner from the options) for A x = b.
+ *   b_dev, x_dev : device FP64 vectors of length n. x_dev is read as the initial
+ *                  guess when use_x0 != 0, otherwise overwritten from 0.
+ *   tol          : stop when ||r_k||_2 / ||b||_2 <= tol (recursively updated r_k;
+ *                  checked before the first iteration as well). tol = 0 runs maxit.
+ *   maxit        : iteration cap (>= 0).
+ *   iters, relres: host outputs (may be NULL).
+ * b = 0 gives x = 0, iters = 0, CPC_OK. Returns CPC_E_MAXIT with the last iterate
+ * in x when the cap is reached, CPC_E_BREAKDOWN on breakdown. */
+cpc_status cpc_solve(cpc_handle h, const double* b_dev, double* x_dev, int32_t use_x0, double tol,
+                     int32_t maxit, int32_t* iters, double* relres);
+
+/* Same as cpc_solve with a different preconditioner for this call (cpc_prec). */
+cpc_status cpc_solve_with(cpc_handle h, int32_t prec, const double* b_dev, double* x_dev, int32_t use_x0,
+                          double tol, int32_t maxit, int32_t* iters, double* relres);
+
+/* z_dev = M r_dev for the operator `op` (cpc_op), device FP64 vectors of length n. */
+cpc_status cpc_apply_op(cpc_handle h, int32_t op, const double* r_dev, double* z_dev);
+
+/* y_dev = A_l x_dev on level `level` (0 = finest); device FP64 vectors of length n_l. */
+cpc_status cpc_spmv(cpc_handle h, int32_t level, const double* x_dev, double* y_dev);
+
+/* Hierarchy description. Caller arrays hold at least max_levels entries:
+ * n_l[l], nnz_l[l] for each level l (0 = finest); depth_l[l] = number of
+ * level sets of the lower-triangular dependency graph of A_l. */
+cpc_status cpc_hierarchy_info(cpc_handle h, int32_t* nlev, int32_t* n_l, int64_t* nnz_l, int32_t* depth_l);
+
+/* Copy level `level`'s matrix A_l to host CSR arrays (row_ptr[n_l+1], col_idx and
+ * val of nnz_l entries). */
+cpc_status cpc_get_level(cpc_handle h, int32_t level, int32_t* row_ptr, int32_t* col_idx, double* val);
+
+/* Copy the prolongation from level level+1 to level `level` (host CSR with n_l rows),
+ * and the C/F marker (1 = C, 0 = F) of level `level` (n_l entries). nnz via p_nnz. */
+cpc_status cpc_get_prolongation(cpc_handle h, int32_t level, int64_t* p_nnz, int32_t* row_ptr, int32_t* col_idx,
+                                double* val, int32_t* cf);
+
+/* Copy the ILU(0) values (on the pattern of the finest A; strictly lower = L with a
+ * unit diagonal implied, diagonal and upper = U) to a host array of nnz entries. */
+cpc_status cpc_get_ilu(cpc_handle h, double* lu);
+
+/* Statistics of the handle (setup time, last solve). */
+cpc_status cpc_get_stats(cpc_handle h, cpc_stats* st);
+
+/* Adjoint helper: g_nnz_dev[p] = -lam_dev[i] * x_dev[j] for every stored entry p = (i, j)
+ * of the finest A (the gradient of lam^T (b - A x) with respect to the entries of A).
+ * Device arrays: lam, x of length n; g of length nnz. */
+cpc_status cpc_neg_outer_on_pattern(cpc_handle h, const double* lam_dev, const double* x_dev, double* g_nnz_dev);
+
+/* Destroy the handle and free its device and host memory (NULL is ignored). */
+void cpc_destroy(cpc_handle h);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* cpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPC_H */

@@ -1,0 +1,514 @@
+// Host-side SETUP: validation, ILU(0), classical coarsening/interpolation,
+// sweep schedules, exact coarsest solve. Compiled without FMA contraction so
+// that every product and sum is rounded on its own (the coarsening decisions
+// compare values against thresholds, so the arithmetic order is fixed and
+// documented at each function).
+#include "host_setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "../../include/cpc.h"
+
+namespace cpc {
+
+int validate_csr(int n, const int32_t* rp, const int32_t* ci, const double* v, bool check_symmetry,
+                 std::string* msg) {
+  auto fail = [&](int code, const std::string& m) {
+    if (msg) *msg = m;
+    return code;
+  };
+  if (n <= 0) return fail(CPC_E_ARG, "n must be positive");
+  if (!rp || !ci || !v) return fail(CPC_E_ARG, "null CSR array");
+  if (rp[0] != 0) return fail(CPC_E_ARG, "row_ptr[0] must be 0");
+  for (int i = 0; i < n; ++i) {
+    if (rp[i + 1] < rp[i]) return fail(CPC_E_ARG, "row_ptr not monotone at row " + std::to_string(i));
+    bool diag = false;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int j = ci[p];
+      if (j < 0 || j >= n) return fail(CPC_E_ARG, "column out of range in row " + std::to_string(i));
+      if (p > rp[i] && j <= ci[p - 1]) return fail(CPC_E_ARG, "columns not sorted/unique in row " + std::to_string(i));
+      if (!std::isfinite(v[p])) return fail(CPC_E_ARG, "non-finite value in row " + std::to_string(i));
+      if (j == i) {
+        diag = true;
+        if (!(v[p] > 0.0)) return fail(CPC_E_NOT_SPD, "non-positive diagonal at row " + std::to_string(i));
+      }
+    }
+    if (!diag) return fail(CPC_E_ARG, "missing diagonal in row " + std::to_string(i));
+  }
+  if (check_symmetry) {
+    for (int i = 0; i < n; ++i)
+      for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        const int32_t* b = ci + rp[j];
+        const int32_t* e = ci + rp[j + 1];
+        const int32_t* it = std::lower_bound(b, e, i);
+        if (it == e || *it != i) return fail(CPC_E_ARG, "pattern not symmetric at (" + std::to_string(i) + "," + std::to_string(j) + ")");
+        double x = v[p], y = v[rp[j] + (it - b)];
+        if (std::fabs(x - y) > 1e-12 * std::max(std::fabs(x), std::fabs(y)))
+          return fail(CPC_E_ARG, "values not symmetric at (" + std::to_string(i) + "," + std::to_string(j) + ")");
+      }
+  }
+  return CPC_OK;
+}
+
+// ILU(0): row i is reduced by every earlier row m it couples to, in increasing m;
+// the multiplier l_im = a_im / u_mm overwrites a_im and a_ij -= l_im * u_mj for the
+// j > m of row m that are in the pattern of row i (all other fill is dropped).
+int ilu0_factor(const HostCsr& a, std::vector<double>& lu, std::string* msg) {
+  const int n = a.n;
+  lu = a.v;
+  std::vector<int> where(n, -1), dpos(n, -1);
+  for (int i = 0; i < n; ++i) {
+    const int b = a.rp[i], e = a.rp[i + 1];
+    for (int p = b; p < e; ++p) {
+      where[a.ci[p]] = p;
+      if (a.ci[p] == i) dpos[i] = p;
+    }
+    for (int p = b; p < e; ++p) {
+      const int m = a.ci[p];
+      if (m >= i) break;
+      const double l = lu[p] / lu[dpos[m]];
+      lu[p] = l;
+      for (int q = dpos[m] + 1; q < a.rp[m + 1]; ++q) {
+        const int t = where[a.ci[q]];
+        if (t >= 0) lu[t] = lu[t] - l * lu[q];
+      }
+    }
+    for (int p = b; p < e; ++p) where[a.ci[p]] = -1;
+    if (!(lu[dpos[i]] > 0.0)) {
+      if (msg) *msg = "ILU(0) pivot not positive at row " + std::to_string(i);
+      return CPC_E_NOT_SPD;
+    }
+  }
+  return CPC_OK;
+}
+
+namespace {
+
+// strong couplings of each row (CSR of column indices) and their transpose
+struct Graph {
+  std::vector<int> rp, ci;
+};
+
+void strength(const HostCsr& a, double theta, Graph& S, Graph& ST) {
+  const int n = a.n;
+  S.rp.assign(n + 1, 0);
+  S.ci.clear();
+  S.ci.reserve(a.nnz());
+  for (int i = 0; i < n; ++i) {
+    bool have = false;
+    double mx = 0.0;
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+      if (a.ci[p] == i) continue;
+      const double t = -a.v[p];
+      if (!have || t > mx) mx = t;
+      have = true;
+    }
+    const double thr = theta * mx;
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+      const int j = a.ci[p];
+      if (j != i && a.v[p] < 0.0 && -a.v[p] >= thr) S.ci.push_back(j);
+    }
+    S.rp[i + 1] = (int)S.ci.size();
+  }
+  ST.rp.assign(n + 1, 0);
+  ST.ci.assign(S.ci.size(), 0);
+  for (int j : S.ci) ST.rp[j + 1]++;
+  for (int i = 0; i < n; ++i) ST.rp[i + 1] += ST.rp[i];
+  std::vector<int> next(ST.rp.begin(), ST.rp.end() - 1);
+  for (int i = 0; i < n; ++i)
+    for (int p = S.rp[i]; p < S.rp[i + 1]; ++p) ST.ci[next[S.ci[p]]++] = i;
+}
+
+// max-tree over points: key = lambda for undecided points, -1 otherwise;
+// the root holds the largest key and, among equal keys, the smallest index.
+class MaxTree {
+ public:
+  explicit MaxTree(int n) : n_(n) {
+    size_ = 1;
+    while (size_ < n) size_ <<= 1;
+    key_.assign(2 * size_, -1);
+    idx_.assign(2 * size_, std::numeric_limits<int>::max());
+    for (int i = 0; i < n; ++i) idx_[size_ + i] = i;
+  }
+  void set(int i, int key) {
+    int t = size_ + i;
+    key_[t] = key;
+    for (t >>= 1; t >= 1; t >>= 1) pull(t);
+  }
+  void build() {
+    for (int t = size_ - 1; t >= 1; --t) pull(t);
+  }
+  void set_leaf(int i, int key) { key_[size_ + i] = key; }
+  int top_key() const { return key_[1]; }
+  int top_idx() const { return idx_[1]; }
+
+ private:
+  void pull(int t) {
+    const int l = 2 * t, r = l + 1;
+    if (key_[l] >= key_[r]) {
+      key_[t] = key_[l];
+      idx_[t] = idx_[l];
+    } else {
+      key_[t] = key_[r];
+      idx_[t] = idx_[r];
+    }
+  }
+  int n_, size_;
+  std::vector<int> key_, idx_;
+};
+
+}  // namespace
+
+// Classical coarsening. Strength: j in S_i iff a_ij < 0 and -a_ij >= theta * max_k(-a_ik).
+// First pass: points with no strong couplings are F; the undecided point with the
+// largest lambda_i = |S_i^T among undecided| (smallest index on ties) becomes C, the
+// undecided points of S_i^T become F (each raising lambda of the undecided points of
+// its own S_j), then the undecided points of S_i lose one from lambda.
+// Second pass over F points in increasing index: a strong F neighbour j with no strong
+// coupling into C_i becomes the tentative C point; a second such j turns i itself into
+// C (the tentative point is dropped); a surviving tentative point becomes C.
+int rs_coarsen(const HostCsr& a, double theta, std::vector<int>& cf) {
+  const int n = a.n;
+  Graph S, ST;
+  strength(a, theta, S, ST);
+  constexpr int UNDECIDED = -1, F = 0, C = 1;
+  cf.assign(n, UNDECIDED);
+  for (int i = 0; i < n; ++i)
+    if (S.rp[i] == S.rp[i + 1]) cf[i] = F;
+  std::vector<int> lambda(n, 0);
+  MaxTree tree(n);
+  for (int i = 0; i < n; ++i) {
+    if (cf[i] != UNDECIDED) continue;
+    int c = 0;
+    for (int p = ST.rp[i]; p < ST.rp[i + 1]; ++p) c += (cf[ST.ci[p]] == UNDECIDED);
+    lambda[i] = c;
+    tree.set_leaf(i, c);
+  }
+  tree.build();
+  while (tree.top_key() >= 0) {
+    const int i = tree.top_idx();
+    cf[i] = C;
+    tree.set(i, -1);
+    for (int p = ST.rp[i]; p < ST.rp[i + 1]; ++p) {
+      const int j = ST.ci[p];
+      if (cf[j] != UNDECIDED) continue;
+      cf[j] = F;
+      tree.set(j, -1);
+      for (int q = S.rp[j]; q < S.rp[j + 1]; ++q) {
+        const int k = S.ci[q];
+        if (cf[k] == UNDECIDED) tree.set(k, ++lambda[k]);
+      }
+    }
+    for (int p = S.rp[i]; p < S.rp[i + 1]; ++p) {
+      const int j = S.ci[p];
+      if (cf[j] == UNDECIDED) tree.set(j, --lambda[j]);
+    }
+  }
+  // second pass
+  std::vector<int> owner(n, -1);  // owner[k] == i : k belongs to C_i of the F point i
+  for (int i = 0; i < n; ++i) {
+    if (cf[i] != F) continue;
+    for (int p = S.rp[i]; p < S.rp[i + 1]; ++p)
+      if (cf[S.ci[p]] == C) owner[S.ci[p]] = i;
+    int tentative = -1;
+    bool promoted = false;
+    for (int p = S.rp[i]; p < S.rp[i + 1] && !promoted; ++p) {
+      const int j = S.ci[p];
+      if (cf[j] != F) continue;
+      bool covered = false;
+      for (int q = S.rp[j]; q < S.rp[j + 1]; ++q)
+        if (owner[S.ci[q]] == i) {
+          covered = true;
+          break;
+        }
+      if (covered) continue;
+      if (tentative < 0) {
+        tentative = j;
+        owner[j] = i;
+      } else {
+        cf[i] = C;
+        promoted = true;
+      }
+    }
+    if (!promoted && tentative >= 0) cf[tentative] = C;
+  }
+  int nc = 0;
+  for (int i = 0; i < n; ++i) nc += (cf[i] == C);
+  return nc;
+}
+
+// Classical interpolation. For an F point i, C_i = strong C neighbours, D^s_i =
+// strong F neighbours, D^w_i = all other off-diagonals (weak, or a strong F neighbour
+// m whose sum over C_i of abar_mk is zero; abar_mk = a_mk when its sign is opposite
+// to a_mm, else 0):
+//   w_ij = -(a_ij + sum_{m in D^s_i} (a_im * abar_mj) / d_m) / (a_ii + sum_{n in D^w_i} a_in),
+//   d_m = sum_{k in C_i} abar_mk.
+// Sums run in increasing column order; each numerator starts from a_ij and adds the
+// m terms in increasing m; d_m starts from 0. C points get a unit row; points with
+// no strong couplings get an empty row.
+bool rs_interpolation(const HostCsr& a, double theta, const std::vector<int>& cf, int nc, HostCsr& P) {
+  const int n = a.n;
+  Graph S, ST;
+  strength(a, theta, S, ST);
+  std::vector<int> coarse(n, -1);
+  {
+    int c = 0;
+    for (int i = 0; i < n; ++i)
+      if (cf[i] == 1) coarse[i] = c++;
+  }
+  std::vector<double> diag(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p)
+      if (a.ci[p] == i) diag[i] = a.v[p];
+  P.n = n;
+  P.ncols = nc;
+  P.rp.assign(n + 1, 0);
+  P.ci.clear();
+  P.v.clear();
+  // role[k] for the F point being processed: 1 = C_i, 2 = D^s_i (kept), 3 = D^s_i moved to D^w
+  std::vector<uint8_t> role(n, 0);
+  std::vector<double> num(n, 0.0);
+  std::vector<double> dm;  // d_m per strong F neighbour, in S_i order
+  for (int i = 0; i < n; ++i) {
+    if (cf[i] == 1) {
+      P.ci.push_back(coarse[i]);
+      P.v.push_back(1.0);
+      P.rp[i + 1] = (int)P.ci.size();
+      continue;
+    }
+    const int sb = S.rp[i], se = S.rp[i + 1];
+    for (int p = sb; p < se; ++p) role[S.ci[p]] = (cf[S.ci[p]] == 1) ? 1 : 2;
+    auto dsum_of = [&](int m) {
+      const bool neg_diag = diag[m] < 0.0;
+      double d = 0.0;
+      for (int q = a.rp[m]; q < a.rp[m + 1]; ++q) {
+        const int k = a.ci[q];
+        if (k != m && role[k] == 1 && ((a.v[q] < 0.0) != neg_diag)) d = d + a.v[q];
+      }
+      return d;
+    };
+    for (int p = sb; p < se; ++p) {
+      const int m = S.ci[p];
+      if (role[m] == 2 && dsum_of(m) == 0.0) role[m] = 3;
+    }
+    double denom = diag[i];
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+      const int k = a.ci[p];
+      if (k == i || role[k] == 1 || role[k] == 2) continue;
+      denom = denom + a.v[p];
+    }
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p)
+      if (role[a.ci[p]] == 1) num[a.ci[p]] = a.v[p];
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+      const int m = a.ci[p];
+      if (role[m] != 2) continue;
+      const double aim = a.v[p];
+      const double d = dsum_of(m);
+      const bool neg_diag = diag[m] < 0.0;
+      for (int q = a.rp[m]; q < a.rp[m + 1]; ++q) {
+        const int j = a.ci[q];
+        if (j == m || role[j] != 1 || ((a.v[q] < 0.0) == neg_diag)) continue;
+        double t = aim * a.v[q];
+        t = t / d;
+        num[j] = num[j] + t;
+      }
+    }
+    for (int p = sb; p < se; ++p) {
+      const int j = S.ci[p];
+      if (role[j] == 1) {
+        P.ci.push_back(coarse[j]);
+        P.v.push_back(-(num[j] / denom));
+      }
+    }
+    P.rp[i + 1] = (int)P.ci.size();
+    for (int p = sb; p < se; ++p) role[S.ci[p]] = 0;
+  }
+  return true;
+}
+
+HostCsr transpose(const HostCsr& a) {
+  HostCsr t;
+  t.n = a.ncols;
+  t.ncols = a.n;
+  t.rp.assign(t.n + 1, 0);
+  const int64_t nnz = a.nnz();
+  t.ci.resize(nnz);
+  t.v.resize(nnz);
+  for (int64_t p = 0; p < nnz; ++p) t.rp[a.ci[p] + 1]++;
+  for (int j = 0; j < t.n; ++j) t.rp[j + 1] += t.rp[j];
+  std::vector<int> next(t.rp.begin(), t.rp.end() - 1);
+  for (int i = 0; i < a.n; ++i)
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+      const int q = next[a.ci[p]]++;
+      t.ci[q] = i;
+      t.v[q] = a.v[p];
+    }
+  return t;
+}
+
+int lower_depth(const HostCsr& a) {
+  std::vector<int> lev(a.n, 0);
+  int depth = 0;
+  for (int i = 0; i < a.n; ++i) {
+    int l = 0;
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+      const int j = a.ci[p];
+      if (j >= i) break;
+      l = std::max(l, lev[j] + 1);
+    }
+    lev[i] = l;
+    depth = std::max(depth, l + 1);
+  }
+  return depth;
+}
+
+SweepSchedule build_sweep(const HostCsr& a, bool forward, int R) {
+  SweepSchedule s;
+  const int n = a.n;
+  s.n = n;
+  s.forward = forward;
+  s.R = std::max(1, std::min(R, n));
+  s.nblk = (n + s.R - 1) / s.R;
+  std::vector<int> lev(n, 0), glev(n, 0);
+  // global depth (for reporting) in the sweep's own direction
+  if (forward) {
+    for (int i = 0; i < n; ++i) {
+      int g = 0;
+      for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < i; ++p) g = std::max(g, glev[a.ci[p]] + 1);
+      glev[i] = g;
+      s.global_depth = std::max(s.global_depth, g + 1);
+    }
+  } else {
+    for (int i = n - 1; i >= 0; --i) {
+      int g = 0;
+      for (int p = a.rp[i + 1] - 1; p >= a.rp[i] && a.ci[p] > i; --p) g = std::max(g, glev[a.ci[p]] + 1);
+      glev[i] = g;
+      s.global_depth = std::max(s.global_depth, g + 1);
+    }
+  }
+  s.blk_beg.assign(s.nblk, 0);
+  s.blk_end.assign(s.nblk, 0);
+  s.perm.reserve(n);
+  s.lvl_ptr.push_back(0);
+  s.wait_ptr.push_back(0);
+  std::vector<int> last_need(s.nblk, 0);  // running maximum of waits of the current block
+  std::vector<int> touched;
+  std::vector<std::vector<int>> rows_at;
+  // per-level: list of (block, need) candidates
+  std::vector<std::vector<std::pair<int, int>>> waits_at;
+  std::vector<std::vector<int>> needs_of_block(s.nblk);  // needs placed on each block
+  for (int t = 0; t < s.nblk; ++t) {
+    // blocks in processing order: increasing rows forward, decreasing backward
+    const int b = forward ? t : s.nblk - 1 - t;
+    const int r0 = b * s.R, r1 = std::min(n, r0 + s.R);
+    int nl = 0;
+    if (forward) {
+      for (int i = r0; i < r1; ++i) {
+        int l = 0;
+        for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < i; ++p)
+          if (a.ci[p] >= r0) l = std::max(l, lev[a.ci[p]] + 1);
+        lev[i] = l;
+        nl = std::max(nl, l + 1);
+      }
+    } else {
+      for (int i = r1 - 1; i >= r0; --i) {
+        int l = 0;
+        for (int p = a.rp[i + 1] - 1; p >= a.rp[i] && a.ci[p] > i; --p)
+          if (a.ci[p] < r1) l = std::max(l, lev[a.ci[p]] + 1);
+        lev[i] = l;
+        nl = std::max(nl, l + 1);
+      }
+    }
+    rows_at.assign(nl, {});
+    waits_at.assign(nl, {});
+    for (int i = r0; i < r1; ++i) rows_at[lev[i]].push_back(i);
+    for (int i = r0; i < r1; ++i) {
+      if (forward) {
+        for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < r0; ++p) {
+          const int j = a.ci[p];
+          waits_at[lev[i]].push_back({j / s.R, lev[j] + 1});
+        }
+      } else {
+        for (int p = a.rp[i + 1] - 1; p >= a.rp[i] && a.ci[p] >= r1; --p) {
+          const int j = a.ci[p];
+          waits_at[lev[i]].push_back({j / s.R, lev[j] + 1});
+        }
+      }
+    }
+    s.blk_beg[b] = (int)s.lvl_ptr.size() - 1;
+    touched.clear();
+    for (int m = 0; m < nl; ++m) {
+      for (int i : rows_at[m]) s.perm.push_back(i);
+      s.lvl_ptr.push_back((int)s.perm.size());
+      auto& w = waits_at[m];
+      std::sort(w.begin(), w.end());
+      for (size_t t = 0; t < w.size(); ++t) {
+        if (t + 1 < w.size() && w[t + 1].first == w[t].first) continue;  // keep the largest need per block
+        const int ob = w[t].first, need = w[t].second;
+        if (need > last_need[ob]) {
+          if (last_need[ob] == 0) touched.push_back(ob);
+          last_need[ob] = need;
+          s.wait_blk.push_back(ob);
+          s.wait_need.push_back(need);
+          needs_of_block[ob].push_back(need);
+        }
+      }
+      s.wait_ptr.push_back((int)s.wait_blk.size());
+    }
+    for (int ob : touched) last_need[ob] = 0;
+    s.blk_end[b] = (int)s.lvl_ptr.size() - 1;
+    s.max_local_levels = std::max(s.max_local_levels, nl);
+  }
+  const int total = (int)s.lvl_ptr.size() - 1;
+  s.publish.assign(total, 0);
+  for (int b = 0; b < s.nblk; ++b)
+    for (int need : needs_of_block[b]) s.publish[s.blk_beg[b] + need - 1] = 1;
+  return s;
+}
+
+int dense_spd_inverse(const HostCsr& a, std::vector<double>& inv, std::string* msg) {
+  const int n = a.n;
+  std::vector<double> g((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) g[(size_t)i * n + a.ci[p]] = a.v[p];
+  // Cholesky A = G G^T (lower G), column by column
+  for (int j = 0; j < n; ++j) {
+    double d = g[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= g[(size_t)j * n + k] * g[(size_t)j * n + k];
+    if (!(d > 0.0)) {
+      if (msg) *msg = "coarsest matrix not positive definite at row " + std::to_string(j);
+      return CPC_E_NOT_SPD;
+    }
+    d = std::sqrt(d);
+    g[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = g[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= g[(size_t)i * n + k] * g[(size_t)j * n + k];
+      g[(size_t)i * n + j] = s / d;
+    }
+  }
+  // W = G^{-1} (lower triangular), then A^{-1} = W^T W
+  std::vector<double> w((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    for (int i = c; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= g[(size_t)i * n + k] * w[(size_t)k * n + c];
+      w[(size_t)i * n + c] = s / g[(size_t)i * n + i];
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = 0.0;
+      for (int k = i; k < n; ++k) s += w[(size_t)k * n + i] * w[(size_t)k * n + j];
+      inv[(size_t)i * n + j] = s;
+      inv[(size_t)j * n + i] = s;
+    }
+  return CPC_OK;
+}
+
+}  // namespace cpc

@@ -1,0 +1,544 @@
+// HIP kernels of the SOLVE phase for gfx950 (wave64).
+//
+//  * CSR SpMV family with TPR lanes per row (TPR in {1,...,64}); rows are spread
+//    over the grid, each group of TPR lanes reads its row's column/value streams
+//    contiguously and reduces with cross-lane shuffles.
+//  * Fused PCG vector kernels with a deterministic two-stage reduction: each
+//    workgroup writes one partial, the last workgroup to arrive sums the
+//    partials in index order and updates the scalars (alpha, beta, relres,
+//    convergence flag) on the device.
+//  * A persistent, block-pipelined, level-scheduled triangular sweep (forward and
+//    backward Gauss-Seidel, ILU(0) L and U solves). Rows are cut into contiguous
+//    blocks; a workgroup takes blocks in dependency order from a ticket counter,
+//    keeps the block's solved values in LDS, walks the block's own level sets with
+//    workgroup barriers, and waits on per-block progress counters (agent-scope
+//    acquire/release) only where a level depends on another block.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace cpc {
+
+namespace {
+
+constexpr int kNT = 256;          // threads per workgroup for the streaming kernels
+constexpr int kRedGrid = 1024;    // workgroups of the reduction kernels (grid-stride)
+
+template <typename T>
+__device__ __forceinline__ double ld(const T* p, long i) {
+  return (double)p[i];
+}
+
+template <typename T>
+__device__ __forceinline__ void st(T* p, long i, double v) {
+  p[i] = (T)v;
+}
+
+template <int W>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+  return v;
+}
+
+// Sum over the workgroup (kNT threads). Fixed tree: deterministic.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = group_sum<64>(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  }
+  return s;  // valid in thread 0
+}
+
+// Last-workgroup reduction: every workgroup publishes its partial; the last one to
+// arrive returns true in all of its threads and has the total in *total (thread 0).
+__device__ bool arrive(double part, double* partials, unsigned* counter, double* sh, double* total) {
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = part;
+    __threadfence();
+    const unsigned t = atomicAdd(counter, 1u);
+    s_last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  double s = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) s += __builtin_nontemporal_load(partials + i);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    *total = s;
+    *counter = 0u;
+  }
+  return true;
+}
+
+// ----------------------------------------------------------------------------
+// SpMV family
+template <int TPR, typename VT, typename XT, typename FT, typename YT>
+__global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const VT* __restrict__ v, const XT* __restrict__ x,
+                                                   const FT* __restrict__ f, YT* __restrict__ y, int mode,
+                                                   const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int RPB = kNT / TPR;
+  const int lane = threadIdx.x % TPR;
+  for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
+    const int b = rp[i], e = rp[i + 1];
+    double s = 0.0;
+    for (int p = b + lane; p < e; p += TPR) s += (double)v[p] * ld(x, ci[p]);
+    s = group_sum<TPR>(s);
+    if (lane == 0) {
+      if (mode == 0) st(y, i, s);
+      else if (mode == 1) st(y, i, ld(f, i) - s);
+      else st(y, i, ld(y, i) + s);
+    }
+  }
+}
+
+template <int TPR>
+__global__ __launch_bounds__(kNT) void spmv_pq_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                      const double* __restrict__ v, const double* __restrict__ p,
+                                                      double* __restrict__ q, double* partials, PcgState* stt) {
+  __shared__ double sh[kNT / 64];
+  if (stt->done) return;
+  constexpr int RPB = kNT / TPR;
+  const int lane = threadIdx.x % TPR;
+  double acc = 0.0;
+  for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
+    const int b = rp[i], e = rp[i + 1];
+    double s = 0.0;
+    for (int k = b + lane; k < e; k += TPR) s += v[k] * p[ci[k]];
+    s = group_sum<TPR>(s);
+    if (lane == 0) {
+      q[i] = s;
+      acc += s * p[i];
+    }
+  }
+  double part = block_sum(acc, sh);
+  double tot;
+  if (arrive(part, partials, &stt->cnt[0], sh, &tot) && threadIdx.x == 0) {
+    stt->pq = tot;
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      stt->done = DONE_BREAKDOWN;
+    } else {
+      stt->alpha = stt->rz / tot;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kNT) void update_xr_kernel(int n, double* __restrict__ x, double* __restrict__ r,
+                                                        const double* __restrict__ p, const double* __restrict__ q,
+                                                        double* partials, PcgState* stt) {
+  __shared__ double sh[kNT / 64];
+  if (stt->done) return;
+  const double a = stt->alpha;
+  double acc = 0.0;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
+    x[i] = x[i] + a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  double part = block_sum(acc, sh);
+  double tot;
+  if (arrive(part, partials, &stt->cnt[1], sh, &tot) && threadIdx.x == 0) {
+    stt->rr = tot;
+    stt->iters += 1;
+    const double rel = sqrt(tot) / sqrt(stt->bb);
+    stt->relres = rel;
+    if (!isfinite(rel)) stt->done = DONE_BREAKDOWN;
+    else if (rel <= stt->tol) stt->done = DONE_CONVERGED;
+    else if (stt->iters >= stt->maxit) stt->done = DONE_MAXIT;
+  }
+}
+
+__global__ __launch_bounds__(kNT) void dot_rz_kernel(int n, const double* __restrict__ r, const double* __restrict__ z,
+                                                     double* __restrict__ p, double* partials, PcgState* stt,
+                                                     int first) {
+  __shared__ double sh[kNT / 64];
+  if (stt->done) return;
+  double acc = 0.0;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
+    const double zi = z[i];
+    acc += r[i] * zi;
+    if (first) p[i] = zi;
+  }
+  double part = block_sum(acc, sh);
+  double tot;
+  if (arrive(part, partials, &stt->cnt[2], sh, &tot) && threadIdx.x == 0) {
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      stt->done = DONE_BREAKDOWN;
+    } else {
+      if (!first) stt->beta = tot / stt->rz;
+      stt->rz = tot;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kNT) void update_p_kernel(int n, const double* __restrict__ z, double* __restrict__ p,
+                                                       const PcgState* stt) {
+  if (stt->done) return;
+  const double b = stt->beta;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) p[i] = z[i] + b * p[i];
+}
+
+template <int TPR>
+__global__ __launch_bounds__(kNT) void pcg_init_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const double* __restrict__ v, const double* __restrict__ b,
+                                                       double* __restrict__ x, double* __restrict__ r, int use_x0,
+                                                       double* partials, PcgState* stt) {
+  __shared__ double sh[kNT / 64];
+  constexpr int RPB = kNT / TPR;
+  const int lane = threadIdx.x % TPR;
+  double bbp = 0.0, rrp = 0.0;
+  for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
+    double s = 0.0;
+    if (use_x0) {
+      for (int k = rp[i] + lane; k < rp[i + 1]; k += TPR) s += v[k] * x[ci[k]];
+      s = group_sum<TPR>(s);
+    }
+    if (lane == 0) {
+      if (!use_x0) x[i] = 0.0;
+      const double bi = b[i];
+      const double ri = bi - s;
+      r[i] = ri;
+      bbp += bi * bi;
+      rrp += ri * ri;
+    }
+  }
+  // two sums: reuse the reduction twice (slots 3 and 4)
+  double pb = block_sum(bbp, sh);
+  double tb;
+  const bool lastb = arrive(pb, partials, &stt->cnt[3], sh, &tb);
+  __syncthreads();
+  double pr = block_sum(rrp, sh);
+  double tr;
+  const bool lastr = arrive(pr, partials + gridDim.x, &stt->cnt[4], sh, &tr);
+  // The workgroup that is last for the second sum has seen every first partial
+  // (each workgroup arrives at the first counter before the second), so it also
+  // recomputes the first total in the same fixed order.
+  if (lastr) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) s += __builtin_nontemporal_load(partials + i);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+      tb = s;
+      stt->bb = tb;
+      stt->rr = tr;
+      stt->iters = 0;
+      stt->beta = 0.0;
+      if (tb == 0.0) {
+        stt->done = DONE_ZERO_RHS;
+        stt->relres = 0.0;
+      } else {
+        const double rel = sqrt(tr) / sqrt(tb);
+        stt->relres = rel;
+        if (!isfinite(rel)) stt->done = DONE_BREAKDOWN;
+        else if (rel <= stt->tol) stt->done = DONE_CONVERGED;
+        else if (stt->maxit <= 0) stt->done = DONE_MAXIT;
+      }
+    }
+  }
+  (void)lastb;
+}
+
+// ----------------------------------------------------------------------------
+// Persistent block-pipelined sweep.
+template <int OP, int TPR, typename VT, typename XT>
+__global__ __launch_bounds__(256) void sweep_kernel(SweepDev sw, int n, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const int* __restrict__ dpos,
+                                                    const VT* __restrict__ val, const XT* __restrict__ f, XT* x,
+                                                    const XT* __restrict__ base, XT* __restrict__ out, SweepSync sy,
+                                                    const int* __restrict__ done, long spin_limit) {
+  constexpr bool FWD = (OP == SWEEP_FGS0 || OP == SWEEP_ILU_L);
+  extern __shared__ unsigned char smem_raw[];
+  XT* xs = reinterpret_cast<XT*>(smem_raw);
+  __shared__ int s_tick;
+  __shared__ int s_last;
+  if (done && *done) return;  // before taking a ticket: the counters stay untouched
+  const int tid = threadIdx.x;
+  const int nt = blockDim.x;
+  const int lane = tid % TPR;
+  const int grp = tid / TPR;
+  const int ngrp = nt / TPR;
+  for (;;) {
+    if (tid == 0) s_tick = (int)atomicAdd(sy.ticket, 1u);
+    __syncthreads();
+    const int t = s_tick;
+    __syncthreads();
+    if (t >= sw.nblk) break;
+    const int b = FWD ? t : sw.nblk - 1 - t;
+    const int r0 = b * sw.R;
+    const int r1 = min(n, r0 + sw.R);
+    const int lb = sw.blk_beg[b], le = sw.blk_end[b];
+    for (int lv = lb; lv < le; ++lv) {
+      const int w0 = sw.wait_ptr[lv], w1 = sw.wait_ptr[lv + 1];
+      if (w0 < w1) {
+        for (int w = w0 + tid; w < w1; w += nt) {
+          const unsigned need = (unsigned)sw.wait_need[w];
+          unsigned* pp = sy.progress + sw.wait_blk[w];
+          long spins = 0;
+          while (__hip_atomic_load(pp, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > spin_limit) {
+              atomicOr(sy.err, 1u);
+              break;
+            }
+            if ((spins & 1023) == 0 && __hip_atomic_load(sy.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+          }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      const int p0 = sw.lvl_ptr[lv], p1 = sw.lvl_ptr[lv + 1];
+      for (int p = p0 + grp; p < p1; p += ngrp) {
+        const int i = sw.perm[p];
+        const int rb = rp[i], re = rp[i + 1], dp = dpos[i];
+        double s = 0.0;
+        if (OP == SWEEP_FGS0 || OP == SWEEP_ILU_L) {
+          for (int k = rb + lane; k < dp; k += TPR) {
+            const int j = ci[k];
+            const double xj = (j >= r0) ? (double)xs[j - r0] : (double)x[j];
+            s += (double)val[k] * xj;
+          }
+        } else if (OP == SWEEP_ILU_U) {
+          for (int k = dp + 1 + lane; k < re; k += TPR) {
+            const int j = ci[k];
+            const double xj = (j < r1) ? (double)xs[j - r0] : (double)x[j];
+            s += (double)val[k] * xj;
+          }
+        } else {  // SWEEP_BGS_IP: j > i new values, j < i old values (global)
+          for (int k = rb + lane; k < re; k += TPR) {
+            if (k == dp) continue;
+            const int j = ci[k];
+            const double xj = (j > i && j < r1) ? (double)xs[j - r0] : (double)x[j];
+            s += (double)val[k] * xj;
+          }
+        }
+        s = group_sum<TPR>(s);
+        if (lane == 0) {
+          double xi;
+          if (OP == SWEEP_ILU_L) xi = (double)f[i] - s;
+          else xi = ((double)f[i] - s) / (double)val[dp];
+          const XT xo = (XT)xi;
+          xs[i - r0] = xo;
+          x[i] = xo;
+          if (OP == SWEEP_ILU_U && out) out[i] = (XT)((double)base[i] + (double)xo);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid == 0 && sw.publish[lv])
+        __hip_atomic_store(sy.progress + b, (unsigned)(lv - lb + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (tid == 0) s_last = (atomicAdd(sy.exited, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    for (int i = tid; i < sw.nblk; i += nt) sy.progress[i] = 0u;
+    if (tid == 0) {
+      *sy.ticket = 0u;
+      *sy.exited = 0u;
+    }
+  }
+}
+
+template <typename FT, typename ET>
+__global__ __launch_bounds__(kNT) void dense_matvec_kernel(int n, const double* __restrict__ inv,
+                                                           const FT* __restrict__ f, ET* __restrict__ e,
+                                                           const int* __restrict__ done) {
+  if (done && *done) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += inv[(long)row * n + j] * (double)f[j];
+  s = group_sum<64>(s);
+  if (lane == 0) e[row] = (ET)s;
+}
+
+template <typename AT, typename BT, typename YT>
+__global__ __launch_bounds__(kNT) void vec_kernel(int op, int n, const AT* __restrict__ a, const BT* __restrict__ b,
+                                                  YT* __restrict__ y, const int* __restrict__ done) {
+  if (done && *done) return;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
+    switch (op) {
+      case 0: y[i] = (YT)((double)a[i] + (double)b[i]); break;
+      case 1: y[i] = (YT)((double)y[i] + (double)a[i]); break;
+      case 2: y[i] = (YT)(double)a[i]; break;
+      default: y[i] = (YT)0; break;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kNT) void neg_outer_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                        const double* __restrict__ lam, const double* __restrict__ x,
+                                                        double* __restrict__ g) {
+  constexpr int TPR = 8, RPB = kNT / TPR;
+  const int lane = threadIdx.x % TPR;
+  for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
+    const double li = lam[i];
+    for (int k = rp[i] + lane; k < rp[i + 1]; k += TPR) g[k] = -li * x[ci[k]];
+  }
+}
+
+__global__ __launch_bounds__(kNT) void to_f32_kernel(long n, const double* __restrict__ a, float* __restrict__ y) {
+  for (long i = (long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long)gridDim.x * kNT) y[i] = (float)a[i];
+}
+
+int grid_for(long work, int per_block, int cap = 8192) {
+  long g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- launchers
+#define CPC_TPR_DISPATCH(tpr, CALL) \
+  switch (tpr) {                    \
+    case 1: CALL(1); break;         \
+    case 2: CALL(2); break;         \
+    case 4: CALL(4); break;         \
+    case 8: CALL(8); break;         \
+    case 16: CALL(16); break;       \
+    case 32: CALL(32); break;       \
+    default: CALL(64); break;       \
+  }
+
+template <typename VT, typename XT, typename FT, typename YT>
+static void spmv_typed(hipStream_t s, const MatDev& A, int mode, const void* x, const void* f, void* y, int tpr,
+                       const int* done) {
+  const int rpb = kNT / tpr;
+  const int grid = grid_for(A.n, rpb);
+#define CPC_SPMV_CALL(T)                                                                                  \
+  spmv_kernel<T, VT, XT, FT, YT><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const VT*)A.v, (const XT*)x,     \
+                                                      (const FT*)f, (YT*)y, mode, done)
+  CPC_TPR_DISPATCH(tpr, CPC_SPMV_CALL)
+#undef CPC_SPMV_CALL
+}
+
+bool launch_spmv(hipStream_t s, const MatDev& A, int mode, const void* x, bool xf32, const void* f, bool ff32,
+                 void* y, bool yf32, int tpr, const int* done) {
+  if (A.n <= 0) return true;
+  // the precision combinations the solver uses
+  if (!A.fp32 && !xf32 && !ff32 && !yf32) spmv_typed<double, double, double, double>(s, A, mode, x, f, y, tpr, done);
+  else if (A.fp32 && xf32 && ff32 && yf32) spmv_typed<float, float, float, float>(s, A, mode, x, f, y, tpr, done);
+  else if (!A.fp32 && xf32 && !ff32 && yf32) spmv_typed<double, float, double, float>(s, A, mode, x, f, y, tpr, done);
+  else return false;
+  return true;
+}
+
+void launch_spmv_pq(hipStream_t s, const MatDev& A, const double* p, double* q, double* partials, PcgState* stt,
+                    int tpr) {
+  const int rpb = kNT / tpr;
+  const int grid = grid_for(A.n, rpb, kRedGrid);
+#define CPC_PQ_CALL(T) \
+  spmv_pq_kernel<T><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const double*)A.v, p, q, partials, stt)
+  CPC_TPR_DISPATCH(tpr, CPC_PQ_CALL)
+#undef CPC_PQ_CALL
+}
+
+void launch_update_xr(hipStream_t s, int n, double* x, double* r, const double* p, const double* q,
+                      double* partials, PcgState* stt) {
+  update_xr_kernel<<<grid_for(n, kNT, kRedGrid), kNT, 0, s>>>(n, x, r, p, q, partials, stt);
+}
+
+void launch_dot_rz(hipStream_t s, int n, const double* r, const double* z, double* p, double* partials,
+                   PcgState* stt, bool first) {
+  dot_rz_kernel<<<grid_for(n, kNT, kRedGrid), kNT, 0, s>>>(n, r, z, p, partials, stt, first ? 1 : 0);
+}
+
+void launch_update_p(hipStream_t s, int n, const double* z, double* p, PcgState* stt) {
+  update_p_kernel<<<grid_for(n, kNT), kNT, 0, s>>>(n, z, p, stt);
+}
+
+void launch_pcg_init(hipStream_t s, const MatDev& A, const double* b, double* x, double* r, int use_x0,
+                     double* partials, PcgState* stt, int tpr) {
+  const int rpb = kNT / tpr;
+  const int grid = grid_for(A.n, rpb, kRedGrid);
+#define CPC_INIT_CALL(T) \
+  pcg_init_kernel<T><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const double*)A.v, b, x, r, use_x0, partials, stt)
+  CPC_TPR_DISPATCH(tpr, CPC_INIT_CALL)
+#undef CPC_INIT_CALL
+}
+
+template <int OP, typename VT, typename XT>
+static void sweep_typed(hipStream_t s, const SweepDev& sw, const MatDev& M, const void* vals, const void* f, void* x,
+                        const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit) {
+  const size_t lds = (size_t)sw.R * sizeof(XT);
+#define CPC_SWEEP_CALL(T)                                                                                       \
+  sweep_kernel<OP, T, VT, XT><<<sw.grid, sw.nthreads, lds, s>>>(sw, M.n, M.rp, M.ci, M.dpos, (const VT*)vals, \
+                                                                (const XT*)f, (XT*)x, (const XT*)base, (XT*)out, \
+                                                                sync, done, spin_limit)
+  CPC_TPR_DISPATCH(sw.tpr, CPC_SWEEP_CALL)
+#undef CPC_SWEEP_CALL
+}
+
+void launch_sweep(hipStream_t s, int op, const SweepDev& sw, const MatDev& M, const void* vals, bool fp32,
+                  const void* f, void* x, const void* base, void* out, const SweepSync& sync, const int* done,
+                  long spin_limit) {
+  if (sw.n <= 0) return;
+  if (!fp32) {
+    switch (op) {
+      case SWEEP_FGS0: sweep_typed<SWEEP_FGS0, double, double>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
+      case SWEEP_BGS_IP: sweep_typed<SWEEP_BGS_IP, double, double>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
+      case SWEEP_ILU_L: sweep_typed<SWEEP_ILU_L, double, double>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
+      default: sweep_typed<SWEEP_ILU_U, double, double>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
+    }
+  } else {
+    switch (op) {
+      case SWEEP_FGS0: sweep_typed<SWEEP_FGS0, float, float>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
+      case SWEEP_BGS_IP: sweep_typed<SWEEP_BGS_IP, float, float>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
+      case SWEEP_ILU_L: sweep_typed<SWEEP_ILU_L, float, float>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
+      default: sweep_typed<SWEEP_ILU_U, float, float>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
+    }
+  }
+}
+
+void launch_dense_matvec(hipStream_t s, int n, const double* inv, const void* f, bool ff32, void* e, bool ef32,
+                         const int* done) {
+  const int grid = (n + (kNT / 64) - 1) / (kNT / 64);
+  if (!ff32 && !ef32) dense_matvec_kernel<double, double><<<grid, kNT, 0, s>>>(n, inv, (const double*)f, (double*)e, done);
+  else if (ff32 && ef32) dense_matvec_kernel<float, float><<<grid, kNT, 0, s>>>(n, inv, (const float*)f, (float*)e, done);
+  else if (ff32) dense_matvec_kernel<float, double><<<grid, kNT, 0, s>>>(n, inv, (const float*)f, (double*)e, done);
+  else dense_matvec_kernel<double, float><<<grid, kNT, 0, s>>>(n, inv, (const double*)f, (float*)e, done);
+}
+
+void launch_vec(hipStream_t s, int op, int n, const void* a, bool af32, const void* b, bool bf32, void* y, bool yf32,
+                const int* done) {
+  if (n <= 0) return;
+  const int grid = grid_for(n, kNT);
+#define CPC_VEC(A_, B_, Y_) \
+  vec_kernel<A_, B_, Y_><<<grid, kNT, 0, s>>>(op, n, (const A_*)a, (const B_*)b, (Y_*)y, done)
+  const int key = (af32 ? 4 : 0) | (bf32 ? 2 : 0) | (yf32 ? 1 : 0);
+  switch (key) {
+    case 0: CPC_VEC(double, double, double); break;
+    case 1: CPC_VEC(double, double, float); break;
+    case 2: CPC_VEC(double, float, double); break;
+    case 3: CPC_VEC(double, float, float); break;
+    case 4: CPC_VEC(float, double, double); break;
+    case 5: CPC_VEC(float, double, float); break;
+    case 6: CPC_VEC(float, float, double); break;
+    default: CPC_VEC(float, float, float); break;
+  }
+#undef CPC_VEC
+}
+
+void launch_neg_outer(hipStream_t s, const MatDev& A, const double* lam, const double* x, double* g) {
+  neg_outer_kernel<<<grid_for(A.n, kNT / 8), kNT, 0, s>>>(A.n, A.rp, A.ci, lam, x, g);
+}
+
+void launch_to_f32(hipStream_t s, int64_t n, const double* a, float* y) {
+  to_f32_kernel<<<grid_for(n, kNT), kNT, 0, s>>>((long)n, a, y);
+}
+
+}  // namespace cpc

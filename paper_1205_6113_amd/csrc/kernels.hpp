@@ -1,0 +1,120 @@
+// Device kernels of the SOLVE phase and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cpc {
+
+// Scalars of one PCG run, kept on the device so that no iteration needs the host.
+struct PcgState {
+  double rz;      // <r, z> of the current iterate
+  double pq;      // <p, A p>
+  double alpha, beta;
+  double rr;      // ||r||^2
+  double bb;      // ||b||^2
+  double tol;     // relative residual tolerance
+  double relres;  // ||r|| / ||b||
+  int iters;      // completed iterations
+  int maxit;
+  int done;       // 0 running, 1 converged, 2 iteration cap, 3 breakdown, 4 zero right-hand side
+  int pad;
+  unsigned cnt[8];  // arrival counters of the last-workgroup reductions (reset by that workgroup)
+};
+
+enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_MAXIT = 2, DONE_BREAKDOWN = 3, DONE_ZERO_RHS = 4 };
+
+// Device counters shared by every persistent sweep launch (self-resetting).
+struct SweepSync {
+  unsigned* ticket;    // [1]
+  unsigned* exited;    // [1]
+  unsigned* err;       // [1] set when a wait exceeded its bound
+  unsigned* progress;  // [max blocks]
+};
+
+// One level-scheduled sweep over a matrix (see SweepSchedule in host_setup.hpp).
+struct SweepDev {
+  int n, R, nblk, nlev;
+  const int* perm;
+  const int* blk_beg;
+  const int* blk_end;
+  const int* lvl_ptr;
+  const int* wait_ptr;
+  const int* wait_blk;
+  const int* wait_need;
+  const int* publish;
+  int tpr;      // lanes per row
+  int nthreads; // threads per workgroup
+  int grid;     // workgroups launched
+};
+
+enum SweepOp {
+  SWEEP_FGS0 = 0,    // x = (D+L)^{-1} f                           (forward)
+  SWEEP_BGS_IP = 1,  // one backward Gauss-Seidel sweep on A x = f in place (backward)
+  SWEEP_ILU_L = 2,   // y = L^{-1} f, L unit lower                  (forward)
+  SWEEP_ILU_U = 3    // w = U^{-1} f, out = base + w                (backward)
+};
+
+struct MatDev {  // CSR on the device; values of type T
+  int n;
+  const int* rp;
+  const int* ci;
+  const int* dpos;  // position of the diagonal in each row (square matrices)
+  const void* v;
+  bool fp32;
+};
+
+// ---- launchers (all asynchronous on `s`) -----------------------------------
+// y = A x (mode 0), y = f - A x (mode 1), y += A x (mode 2). xf32/ff32/yf32 select
+// FP32 storage of x, f and y. Supported: all FP64; all FP32 (FP32 matrix); FP64
+// matrix with FP32 x and y and FP64 f. Returns false for other combinations.
+bool launch_spmv(hipStream_t s, const MatDev& A, int mode, const void* x, bool xf32, const void* f, bool ff32,
+                 void* y, bool yf32, int tpr, const int* done);
+
+// PCG: q = A p and <p, q>; the last workgroup sets pq, alpha (or flags breakdown).
+void launch_spmv_pq(hipStream_t s, const MatDev& A, const double* p, double* q, double* partials, PcgState* st,
+                    int tpr);
+// x += alpha p, r -= alpha q, ||r||^2 -> relres, iteration count, convergence flag.
+void launch_update_xr(hipStream_t s, int n, double* x, double* r, const double* p, const double* q,
+                      double* partials, PcgState* st);
+// <r, z> -> beta = rz_new / rz (first = true: rz only, and p = z).
+void launch_dot_rz(hipStream_t s, int n, const double* r, const double* z, double* p, double* partials,
+                   PcgState* st, bool first);
+// p = z + beta p.
+void launch_update_p(hipStream_t s, int n, const double* z, double* p, PcgState* st);
+// Start of a solve: r = b - A x (use_x0) or r = b, x = 0; ||b||, ||r|| and the
+// tolerance test before the first iteration.
+void launch_pcg_init(hipStream_t s, const MatDev& A, const double* b, double* x, double* r, int use_x0,
+                     double* partials, PcgState* st, int tpr);
+
+// Persistent level-scheduled sweep.
+void launch_sweep(hipStream_t s, int op, const SweepDev& sw, const MatDev& M, const void* vals, bool fp32,
+                  const void* f, void* x, const void* base, void* out, const SweepSync& sync, const int* done,
+                  long spin_limit);
+
+// e = inv f with a dense row-major inverse (coarsest level, FP64).
+void launch_dense_matvec(hipStream_t s, int n, const double* inv, const void* f, bool ff32, void* e, bool ef32,
+                         const int* done);
+
+// Elementwise: z = a + b (op 0), y += a (op 1), y = a (op 2, copy), y = 0 (op 3),
+// with optional FP32 storage of each operand.
+void launch_vec(hipStream_t s, int op, int n, const void* a, bool af32, const void* b, bool bf32, void* y,
+                bool yf32, const int* done);
+
+// g[p] = -lam[i] * x[j] for every entry p = (i, j) of A.
+void launch_neg_outer(hipStream_t s, const MatDev& A, const double* lam, const double* x, double* g);
+
+// FP64 -> FP32 copy of a value array.
+void launch_to_f32(hipStream_t s, int64_t n, const double* a, float* y);
+
+// Galerkin product C = X * Y with the canonical accumulation order (see rap.hip).
+// Symbolic: counts[i] = distinct columns of row i; returns false on a row with more
+// distinct columns than the kernel's table holds (overflow flag set).
+void launch_spgemm_count(hipStream_t s, int nrows, const int* xrp, const int* xci, const int* yrp, const int* yci,
+                         int* counts, int* overflow);
+void launch_spgemm_fill(hipStream_t s, int nrows, const int* xrp, const int* xci, const double* xv, const int* yrp,
+                        const int* yci, const double* yv, const int* crp, int* cci, double* cv, int* overflow);
+int spgemm_table_capacity();
+
+}  // namespace cpc

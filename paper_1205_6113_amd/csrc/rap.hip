@@ -1,0 +1,160 @@
+// Galerkin coarse matrices A_l = P_l^T A_{l+1} P_l (Section 3.2) on the GPU, as two
+// sparse products C = X * Y: first A P, then R (A P) with R = P^T stored explicitly.
+//
+// Canonical order: entry (i, j) of C is accumulated from 0.0 by adding the rounded
+// products x_ik * y_kj in increasing k (the column order of row i of X). One
+// workgroup owns one output row at a time: it walks the row of X sequentially and,
+// for each k, spreads the entries of row k of Y over its threads (distinct columns,
+// so no two threads touch one accumulator in a step) with a barrier between steps.
+// Accumulators live in an LDS hash table keyed by column. The row is then sorted by
+// column and written out. This file is compiled without FMA contraction, so the
+// result is bit-identical to any sequential evaluation in the same order.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace cpc {
+
+namespace {
+
+constexpr int kCap = 4096;  // distinct columns per output row held in LDS
+constexpr int kNT = 256;
+
+__device__ __forceinline__ unsigned slot_of(int j) { return ((unsigned)j * 2654435761u) & (kCap - 1); }
+
+// returns the slot of column j, inserting it (value 0) when absent; -1 when full
+__device__ __forceinline__ int find_or_insert(int* keys, double* vals, int j, bool with_vals, int* count) {
+  unsigned h = slot_of(j);
+  for (int probe = 0; probe < kCap; ++probe) {
+    const int old = atomicCAS(&keys[h], -1, j);
+    if (old == -1) {
+      if (with_vals) vals[h] = 0.0;
+      atomicAdd(count, 1);
+      return (int)h;
+    }
+    if (old == j) return (int)h;
+    h = (h + 1) & (kCap - 1);
+  }
+  return -1;
+}
+
+__global__ __launch_bounds__(kNT) void spgemm_count_kernel(int nrows, const int* __restrict__ xrp,
+                                                           const int* __restrict__ xci, const int* __restrict__ yrp,
+                                                           const int* __restrict__ yci, int* __restrict__ counts,
+                                                           int* overflow) {
+  extern __shared__ unsigned char smem[];
+  int* keys = reinterpret_cast<int*>(smem);
+  __shared__ int s_cnt;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  for (int row = blockIdx.x; row < nrows; row += gridDim.x) {
+    for (int t = tid; t < kCap; t += kNT) keys[t] = -1;
+    if (tid == 0) {
+      s_cnt = 0;
+      s_bad = 0;
+    }
+    __syncthreads();
+    for (int p = xrp[row]; p < xrp[row + 1]; ++p) {
+      const int k = xci[p];
+      for (int q = yrp[k] + tid; q < yrp[k + 1]; q += kNT) {
+        if (find_or_insert(keys, nullptr, yci[q], false, &s_cnt) < 0) s_bad = 1;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      counts[row] = s_cnt;
+      if (s_bad || s_cnt >= kCap) atomicExch(overflow, 1);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kNT) void spgemm_fill_kernel(int nrows, const int* __restrict__ xrp,
+                                                          const int* __restrict__ xci, const double* __restrict__ xv,
+                                                          const int* __restrict__ yrp, const int* __restrict__ yci,
+                                                          const double* __restrict__ yv, const int* __restrict__ crp,
+                                                          int* __restrict__ cci, double* __restrict__ cv,
+                                                          int* overflow) {
+  extern __shared__ unsigned char smem[];
+  double* vals = reinterpret_cast<double*>(smem);
+  double* cvals = vals + kCap;
+  int* keys = reinterpret_cast<int*>(cvals + kCap);
+  int* ckeys = keys + kCap;
+  __shared__ int s_cnt;
+  __shared__ int s_bad;
+  __shared__ int s_pos;
+  const int tid = threadIdx.x;
+  for (int row = blockIdx.x; row < nrows; row += gridDim.x) {
+    for (int t = tid; t < kCap; t += kNT) keys[t] = -1;
+    if (tid == 0) {
+      s_cnt = 0;
+      s_bad = 0;
+      s_pos = 0;
+    }
+    __syncthreads();
+    for (int p = xrp[row]; p < xrp[row + 1]; ++p) {
+      const int k = xci[p];
+      const double xk = xv[p];
+      for (int q = yrp[k] + tid; q < yrp[k + 1]; q += kNT) {
+        const int h = find_or_insert(keys, vals, yci[q], true, &s_cnt);
+        if (h < 0) {
+          s_bad = 1;
+          continue;
+        }
+        const double prod = xk * yv[q];
+        vals[h] = vals[h] + prod;
+      }
+      __syncthreads();  // orders the additions of step p before those of step p+1
+    }
+    // compact, then place each entry at its rank among the row's columns
+    for (int t = tid; t < kCap; t += kNT) {
+      if (keys[t] >= 0) {
+        const int e = atomicAdd(&s_pos, 1);
+        ckeys[e] = keys[t];
+        cvals[e] = vals[t];
+      }
+    }
+    __syncthreads();
+    const int cnt = s_pos;
+    const int base = crp[row];
+    if (s_bad || cnt != crp[row + 1] - base) {
+      if (tid == 0) atomicExch(overflow, 1);
+    } else {
+      for (int e = tid; e < cnt; e += kNT) {
+        const int key = ckeys[e];
+        int rank = 0;
+        for (int f = 0; f < cnt; ++f) rank += (ckeys[f] < key);
+        cci[base + rank] = key;
+        cv[base + rank] = cvals[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int spgemm_table_capacity() { return kCap; }
+
+void launch_spgemm_count(hipStream_t s, int nrows, const int* xrp, const int* xci, const int* yrp, const int* yci,
+                         int* counts, int* overflow) {
+  if (nrows <= 0) return;
+  const size_t lds = sizeof(int) * kCap;
+  const int grid = nrows < 4096 ? nrows : 4096;
+  spgemm_count_kernel<<<grid, kNT, lds, s>>>(nrows, xrp, xci, yrp, yci, counts, overflow);
+}
+
+void launch_spgemm_fill(hipStream_t s, int nrows, const int* xrp, const int* xci, const double* xv, const int* yrp,
+                        const int* yci, const double* yv, const int* crp, int* cci, double* cv, int* overflow) {
+  if (nrows <= 0) return;
+  const size_t lds = (sizeof(double) * 2 + sizeof(int) * 2) * kCap;
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)spgemm_fill_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr_set = true;
+  }
+  const int grid = nrows < 2048 ? nrows : 2048;
+  spgemm_fill_kernel<<<grid, kNT, lds, s>>>(nrows, xrp, xci, xv, yrp, yci, yv, crp, cci, cv, overflow);
+}
+
+}  // namespace cpc

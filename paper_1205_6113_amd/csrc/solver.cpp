@@ -1,0 +1,853 @@
+// Solver handle, SETUP pipeline, SOLVE orchestration and the C-ABI of cpc.h.
+//
+// SETUP (Section 3.2): validate, ILU(0) on the host, then per level: classical
+// C/F splitting and interpolation on the host, Galerkin product R (A P) on the GPU,
+// download of the coarse matrix for the next splitting. The coarsest matrix is
+// inverted densely (FP64). Sweep schedules and device copies follow.
+//
+// SOLVE: PCG with all scalars on the device; each iteration is one fixed sequence
+// of kernels (optionally replayed from a captured HIP graph); the host reads the
+// convergence flag every `check_every` iterations and kernels after convergence
+// return immediately, so the iteration count is exact.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/cpc.h"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cpc_status set_err(cpc_status st, const std::string& m) {
+  g_last_error = m;
+  return st;
+}
+
+struct HipError {
+  hipError_t e;
+  std::string where;
+};
+
+#define HIPCHK(expr)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) throw HipError{e_, std::string(#expr)};             \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+T* dalloc(size_t count, std::vector<void*>& owned) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  HIPCHK(hipMalloc(&p, count * sizeof(T)));
+  owned.push_back(p);
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+T* dupload(const std::vector<T>& h, std::vector<void*>& owned, hipStream_t s) {
+  T* d = dalloc<T>(h.size(), owned);
+  if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return d;
+}
+
+int pick_tpr(double avg_row) {
+  int t = 1;
+  while (t < 64 && t * 3 < avg_row) t <<= 1;
+  return t;
+}
+
+}  // namespace
+
+namespace cpc {
+
+struct DevCsr {
+  int n = 0, ncols = 0;
+  int64_t nnz = 0;
+  int* rp = nullptr;
+  int* ci = nullptr;
+  double* v = nullptr;
+  float* v32 = nullptr;
+  int* dpos = nullptr;
+  int tpr = 1;
+  MatDev mat(bool fp32) const {
+    MatDev m;
+    m.n = n;
+    m.rp = rp;
+    m.ci = ci;
+    m.dpos = dpos;
+    m.v = fp32 ? (const void*)v32 : (const void*)v;
+    m.fp32 = fp32;
+    return m;
+  }
+};
+
+struct DevSweepSched {
+  SweepDev d{};
+  int global_depth = 0;
+};
+
+struct Level {
+  HostCsr A_host;
+  HostCsr P_host;  // prolongation from level+1 to this level
+  std::vector<int> cf;
+  DevCsr A, P, R;
+  DevSweepSched lower, upper;
+  void* f = nullptr;  // level vectors (coarse levels), element type = preconditioner precision
+  void* u = nullptr;
+  void* r = nullptr;
+};
+
+}  // namespace cpc
+
+struct cpc_solver {
+  cpc_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int n = 0;
+  int64_t nnz = 0;
+  bool f32 = false;  // preconditioner precision
+  std::vector<cpc::Level> lev;
+  int n0 = 0;
+  double* coarse_inv = nullptr;
+  std::vector<double> lu_host;
+  double* lu = nullptr;
+  float* lu32 = nullptr;
+  // PCG vectors
+  double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  // preconditioner temporaries on the finest level (precision of the preconditioner)
+  void *pin = nullptr, *u1 = nullptr, *u2 = nullptr, *res = nullptr, *y = nullptr, *w = nullptr, *t = nullptr;
+  double* z64tmp = nullptr;  // FP64 temporary for the additive form
+  cpc::PcgState* st = nullptr;
+  double* partials = nullptr;
+  cpc::SweepSync sync{};
+  long spin_limit = 1L << 22;
+  cpc_stats stats{};
+  std::vector<void*> owned;
+  // captured iteration graphs, one per preconditioner
+  hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t graph_src[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* graph_x[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // x bound into each graph
+  int max_nblk = 1;
+
+  ~cpc_solver() {
+    for (int i = 0; i < 5; ++i) {
+      if (graph[i]) (void)hipGraphExecDestroy(graph[i]);
+      if (graph_src[i]) (void)hipGraphDestroy(graph_src[i]);
+    }
+    for (void* ptr : owned) (void)hipFree(ptr);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+namespace cpc {
+
+static void upload_csr(cpc_solver* h, const HostCsr& a, DevCsr& d, bool with_dpos) {
+  d.n = a.n;
+  d.ncols = a.ncols;
+  d.nnz = a.nnz();
+  d.rp = dupload(a.rp, h->owned, h->stream);
+  d.ci = dupload(a.ci, h->owned, h->stream);
+  d.v = dupload(a.v, h->owned, h->stream);
+  if (with_dpos) {
+    std::vector<int> dp(a.n, -1);
+    for (int i = 0; i < a.n; ++i)
+      for (int k = a.rp[i]; k < a.rp[i + 1]; ++k)
+        if (a.ci[k] == i) dp[i] = k;
+    d.dpos = dupload(dp, h->owned, h->stream);
+  }
+  d.tpr = pick_tpr(a.n ? (double)d.nnz / a.n : 1.0);
+  if (h->f32) {
+    d.v32 = dalloc<float>((size_t)d.nnz, h->owned);
+    launch_to_f32(h->stream, d.nnz, d.v, d.v32);
+  }
+}
+
+// Galerkin product on the GPU: C = X * Y with the canonical order (rap.hip).
+static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncols, HostCsr& C_host, DevCsr& C,
+                       std::string* msg) {
+  const int nrows = X.n;
+  std::vector<void*> tmp;
+  int* counts = dalloc<int>(nrows, tmp);
+  int* ovf = dalloc<int>(1, tmp);
+  bool ok = true;
+  try {
+    HIPCHK(hipMemsetAsync(ovf, 0, sizeof(int), h->stream));
+    launch_spgemm_count(h->stream, nrows, X.rp, X.ci, Y.rp, Y.ci, counts, ovf);
+    HIPCHK(hipGetLastError());
+    std::vector<int> hc(nrows);
+    int hovf = 0;
+    HIPCHK(hipMemcpyAsync(hc.data(), counts, sizeof(int) * nrows, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (hovf) {
+      if (msg) *msg = "Galerkin product row exceeds " + std::to_string(spgemm_table_capacity()) + " columns";
+      ok = false;
+    } else {
+      C_host.n = nrows;
+      C_host.ncols = ncols;
+      C_host.rp.assign(nrows + 1, 0);
+      int64_t tot = 0;
+      for (int i = 0; i < nrows; ++i) {
+        tot += hc[i];
+        if (tot > 2147483647LL) {
+          ok = false;
+          if (msg) *msg = "Galerkin product exceeds 2^31 entries";
+          break;
+        }
+        C_host.rp[i + 1] = (int)tot;
+      }
+      if (ok) {
+        C.n = nrows;
+        C.ncols = ncols;
+        C.nnz = tot;
+        C.rp = dupload(C_host.rp, h->owned, h->stream);
+        C.ci = dalloc<int>((size_t)tot, h->owned);
+        C.v = dalloc<double>((size_t)tot, h->owned);
+        launch_spgemm_fill(h->stream, nrows, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v, ovf);
+        HIPCHK(hipGetLastError());
+        C_host.ci.resize(tot);
+        C_host.v.resize(tot);
+        HIPCHK(hipMemcpyAsync(C_host.ci.data(), C.ci, sizeof(int) * tot, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(C_host.v.data(), C.v, sizeof(double) * tot, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (hovf) {
+          ok = false;
+          if (msg) *msg = "Galerkin product table overflow";
+        }
+      }
+    }
+  } catch (...) {
+    for (void* ptr : tmp) (void)hipFree(ptr);
+    throw;
+  }
+  for (void* ptr : tmp) (void)hipFree(ptr);
+  return ok;
+}
+
+static int choose_block_rows(int n, double avg_row) {
+  // One workgroup per block. Small matrices: a single block (all dependencies stay
+  // inside one workgroup). Larger ones: about 2 blocks per compute unit, capped by
+  // the LDS the block's values need.
+  if (n <= 4096) return n;
+  int R = (n + 511) / 512;
+  R = std::max(R, 256);
+  R = std::min(R, 8192);
+  (void)avg_row;
+  return R;
+}
+
+static void upload_sweep(cpc_solver* h, const SweepSchedule& s, DevSweepSched& d, double avg_half_row) {
+  d.global_depth = s.global_depth;
+  SweepDev& sd = d.d;
+  sd.n = s.n;
+  sd.R = s.R;
+  sd.nblk = s.nblk;
+  sd.nlev = (int)s.lvl_ptr.size() - 1;
+  sd.perm = dupload(s.perm, h->owned, h->stream);
+  sd.blk_beg = dupload(s.blk_beg, h->owned, h->stream);
+  sd.blk_end = dupload(s.blk_end, h->owned, h->stream);
+  sd.lvl_ptr = dupload(s.lvl_ptr, h->owned, h->stream);
+  sd.wait_ptr = dupload(s.wait_ptr, h->owned, h->stream);
+  sd.wait_blk = dupload(s.wait_blk, h->owned, h->stream);
+  sd.wait_need = dupload(s.wait_need, h->owned, h->stream);
+  sd.publish = dupload(s.publish, h->owned, h->stream);
+  sd.tpr = pick_tpr(avg_half_row);
+  sd.nthreads = 256;
+  sd.grid = std::min(s.nblk, 1024);
+  h->max_nblk = std::max(h->max_nblk, s.nblk);
+}
+
+static void spmv_or_throw(cpc_solver* h, const MatDev& A, int mode, const void* x, bool xf32, const void* f,
+                          bool ff32, void* y, bool yf32, int tpr, const int* done) {
+  if (!launch_spmv(h->stream, A, mode, x, xf32, f, ff32, y, yf32, tpr, done))
+    throw HipError{hipErrorInvalidValue, "unsupported SpMV precision combination"};
+}
+
+static void* valloc(cpc_solver* h, int n) {
+  if (h->f32) return dalloc<float>(n, h->owned);
+  return dalloc<double>(n, h->owned);
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioner application (all asynchronous on h->stream).
+
+static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done) {
+  Level& L = h->lev[d];
+  const bool f32 = h->f32;
+  if (d == (int)h->lev.size() - 1) {
+    launch_dense_matvec(h->stream, L.A.n, h->coarse_inv, f, f32, u, f32, done);
+    return;
+  }
+  Level& C = h->lev[d + 1];
+  const MatDev A = L.A.mat(f32);
+  // (1) pre-smoothing from zero: u = (D+L)^{-1} f
+  launch_sweep(h->stream, SWEEP_FGS0, L.lower.d, A, A.v, f32, f, u, nullptr, nullptr, h->sync, done, h->spin_limit);
+  // (2a) f_c = R (f - A u)
+  spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);
+  spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
+  // (2b) coarse correction
+  vcycle(h, d + 1, C.f, C.u, done);
+  // (2c) u += P e
+  spmv_or_throw(h, L.P.mat(f32), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);
+  // (3) post-smoothing: one backward Gauss-Seidel sweep in place (S_l^T)
+  launch_sweep(h->stream, SWEEP_BGS_IP, L.upper.d, A, A.v, f32, f, u, nullptr, nullptr, h->sync, done,
+               h->spin_limit);
+}
+
+// z = (LU)^{-1} f (out = nullptr) or out = base + (LU)^{-1} f
+static void ilu_apply(cpc_solver* h, const void* f, void* w, const void* base, void* out, const int* done) {
+  Level& L = h->lev[0];
+  const bool f32 = h->f32;
+  const MatDev M = L.A.mat(f32);
+  const void* vals = f32 ? (const void*)h->lu32 : (const void*)h->lu;
+  launch_sweep(h->stream, SWEEP_ILU_L, L.lower.d, M, vals, f32, f, h->y, nullptr, nullptr, h->sync, done,
+               h->spin_limit);
+  launch_sweep(h->stream, SWEEP_ILU_U, L.upper.d, M, vals, f32, h->y, w, base, out, h->sync, done, h->spin_limit);
+}
+
+// res = r - A u with FP64 A and FP64 r (outer residual of Algorithm 2.1)
+static void outer_residual(cpc_solver* h, const double* r, const void* u, void* res, const int* done) {
+  Level& L = h->lev[0];
+  spmv_or_throw(h, L.A.mat(false), 1, u, h->f32, r, false, res, h->f32, L.A.tpr, done);
+}
+
+static void apply_op(cpc_solver* h, int op, const double* r, double* z, const int* done) {
+  const bool f32 = h->f32;
+  const int n = h->n;
+  const void* rin = r;
+  if (f32 && op != CPC_OP_NONE) {
+    launch_vec(h->stream, 2, n, r, false, nullptr, false, h->pin, true, done);
+    rin = h->pin;
+  }
+  switch (op) {
+    case CPC_OP_COMBINED: {
+      if (!h->opt.swap_roles) {
+        vcycle(h, 0, rin, h->u1, done);                        // (1) u1 = S r
+        outer_residual(h, r, h->u1, h->res, done);             //     r - A u1
+        ilu_apply(h, h->res, h->w, h->u1, h->u2, done);        // (2) u2 = u1 + B (r - A u1)
+        outer_residual(h, r, h->u2, h->res, done);             //     r - A u2
+        vcycle(h, 0, h->res, h->t, done);                      // (3) S^T (r - A u2), S^T = S
+        launch_vec(h->stream, 0, n, h->u2, f32, h->t, f32, z, false, done);
+      } else {
+        ilu_apply(h, rin, h->u1, nullptr, nullptr, done);      // (1) u1 = S r, S = ILU(0)
+        outer_residual(h, r, h->u1, h->res, done);
+        vcycle(h, 0, h->res, h->t, done);                      // (2) u2 = u1 + V (r - A u1)
+        launch_vec(h->stream, 0, n, h->u1, f32, h->t, f32, h->u2, f32, done);
+        outer_residual(h, r, h->u2, h->res, done);
+        ilu_apply(h, h->res, h->t, nullptr, nullptr, done);   // (3) ILU^T = ILU for symmetric A
+        launch_vec(h->stream, 0, n, h->u2, f32, h->t, f32, z, false, done);
+      }
+      break;
+    }
+    case CPC_OP_AMG: {
+      vcycle(h, 0, rin, h->u1, done);
+      outer_residual(h, r, h->u1, h->res, done);
+      vcycle(h, 0, h->res, h->t, done);
+      launch_vec(h->stream, 0, n, h->u1, f32, h->t, f32, z, false, done);
+      break;
+    }
+    case CPC_OP_ILU: {
+      ilu_apply(h, rin, h->u1, nullptr, nullptr, done);
+      launch_vec(h->stream, 2, n, h->u1, f32, nullptr, false, z, false, done);
+      break;
+    }
+    case CPC_OP_ADDITIVE: {
+      vcycle(h, 0, rin, h->u1, done);
+      outer_residual(h, r, h->u1, h->res, done);
+      vcycle(h, 0, h->res, h->t, done);
+      launch_vec(h->stream, 0, n, h->u1, f32, h->t, f32, h->z64tmp, false, done);  // S~ r
+      ilu_apply(h, rin, h->u2, nullptr, nullptr, done);                           // B r
+      launch_vec(h->stream, 0, n, h->z64tmp, false, h->u2, f32, z, false, done);
+      break;
+    }
+    case CPC_OP_VCYCLE: {
+      vcycle(h, 0, rin, h->u1, done);
+      launch_vec(h->stream, 2, n, h->u1, f32, nullptr, false, z, false, done);
+      break;
+    }
+    case CPC_OP_FGS:
+    case CPC_OP_BGS: {
+      Level& L = h->lev[0];
+      const MatDev A = L.A.mat(f32);
+      if (op == CPC_OP_FGS) {
+        launch_sweep(h->stream, SWEEP_FGS0, L.lower.d, A, A.v, f32, rin, h->u1, nullptr, nullptr, h->sync, done,
+                     h->spin_limit);
+      } else {
+        // (D+U)^{-1} f = one backward sweep in place from a zero start
+        launch_vec(h->stream, 3, n, nullptr, false, nullptr, false, h->u1, f32, done);
+        launch_sweep(h->stream, SWEEP_BGS_IP, L.upper.d, A, A.v, f32, rin, h->u1, nullptr, nullptr, h->sync, done,
+                     h->spin_limit);
+      }
+      launch_vec(h->stream, 2, n, h->u1, f32, nullptr, false, z, false, done);
+      break;
+    }
+    default:
+      launch_vec(h->stream, 2, n, r, false, nullptr, false, z, false, done);
+      break;
+  }
+}
+
+static int prec_to_op(int prec) {
+  switch (prec) {
+    case CPC_PREC_COMBINED: return CPC_OP_COMBINED;
+    case CPC_PREC_AMG: return CPC_OP_AMG;
+    case CPC_PREC_ILU: return CPC_OP_ILU;
+    case CPC_PREC_ADDITIVE: return CPC_OP_ADDITIVE;
+    default: return CPC_OP_NONE;
+  }
+}
+
+static void enqueue_iteration(cpc_solver* h, int prec, double* x) {
+  int* done = &h->st->done;
+  const DevCsr& A = h->lev[0].A;
+  launch_spmv_pq(h->stream, A.mat(false), h->p, h->q, h->partials, h->st, A.tpr);
+  launch_update_xr(h->stream, h->n, x, h->r, h->p, h->q, h->partials, h->st);
+  apply_op(h, prec_to_op(prec), h->r, h->z, done);
+  launch_dot_rz(h->stream, h->n, h->r, h->z, h->p, h->partials, h->st, false);
+  launch_update_p(h->stream, h->n, h->z, h->p, h->st);
+}
+
+// Algorithmic HBM bytes of one application of each piece (byte model of the
+// measurement plan: matrix streams read once per pass, vectors once per kernel).
+static double vcycle_bytes(const cpc_solver* h) {
+  const double vb = h->f32 ? 4.0 : 8.0;           // vector element
+  const double mb = h->f32 ? 8.0 : 12.0;          // matrix entry (value + column)
+  double b = 0.0;
+  for (size_t d = 0; d + 1 < h->lev.size(); ++d) {
+    const double nz = (double)h->lev[d].A.nnz, n = h->lev[d].A.n, nc = h->lev[d + 1].A.n;
+    const double p = (double)h->lev[d].P.nnz;
+    const double half = 0.5 * (nz - n);
+    b += (half + n) * mb + 4.0 * n + 3.0 * vb * n;          // forward GS from zero
+    b += nz * mb + 4.0 * n + 3.0 * vb * n;                  // residual
+    b += p * mb + 4.0 * nc + vb * n + vb * nc;              // restriction
+    b += p * mb + 4.0 * n + 2.0 * vb * n + vb * nc;         // prolongation + correction
+    b += nz * mb + 4.0 * n + 3.0 * vb * n;                  // backward GS in place
+  }
+  const double n0 = h->lev.back().A.n;
+  b += 8.0 * n0 * n0 + 2.0 * vb * n0;
+  return b;
+}
+
+static double prec_bytes(const cpc_solver* h, int prec) {
+  const double vb = h->f32 ? 4.0 : 8.0;
+  const double mb = h->f32 ? 8.0 : 12.0;
+  const double nz = (double)h->lev[0].A.nnz, n = h->n;
+  const double half = 0.5 * (nz - n);
+  const double ilu = (half * mb + 4.0 * n + 2.0 * vb * n) + ((half + n) * mb + 4.0 * n + 4.0 * vb * n);
+  const double outer = nz * 12.0 + 4.0 * n + 8.0 * n + 2.0 * vb * n;
+  const double V = vcycle_bytes(h);
+  const double conv = h->f32 ? 12.0 * n : 0.0;
+  switch (prec) {
+    case CPC_PREC_COMBINED: return conv + 2.0 * V + ilu + 2.0 * outer + (2.0 * vb + 8.0) * n;
+    case CPC_PREC_AMG: return conv + 2.0 * V + outer + (2.0 * vb + 8.0) * n;
+    case CPC_PREC_ILU: return conv + ilu + (vb + 8.0) * n;
+    case CPC_PREC_ADDITIVE: return conv + 2.0 * V + outer + ilu + 2.0 * (2.0 * vb + 8.0) * n;
+    default: return 16.0 * n;
+  }
+}
+
+static double iteration_bytes(const cpc_solver* h, int prec) {
+  const double nz = (double)h->lev[0].A.nnz, n = h->n;
+  const double pcg = (12.0 * nz + 4.0 * n + 16.0 * n) + 48.0 * n + 16.0 * n + 24.0 * n;
+  return pcg + prec_bytes(h, prec);
+}
+
+static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x, int use_x0, double tol, int maxit,
+                            int32_t* iters, double* relres) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (!b || !x) return set_err(CPC_E_ARG, "null vector");
+  if (maxit < 0 || !(tol >= 0.0)) return set_err(CPC_E_ARG, "maxit must be >= 0 and tol >= 0");
+  if (prec < 0 || prec > CPC_PREC_NONE) return set_err(CPC_E_ARG, "unknown preconditioner");
+  const double t0 = now_s();
+  try {
+    PcgState init{};
+    init.tol = tol;
+    init.maxit = maxit;
+    HIPCHK(hipMemcpyAsync(h->st, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
+    const DevCsr& A = h->lev[0].A;
+    launch_pcg_init(h->stream, A.mat(false), b, x, h->r, use_x0, h->partials, h->st, A.tpr);
+    apply_op(h, prec_to_op(prec), h->r, h->z, &h->st->done);
+    launch_dot_rz(h->stream, h->n, h->r, h->z, h->p, h->partials, h->st, true);
+    HIPCHK(hipGetLastError());
+    PcgState hs{};
+    HIPCHK(hipMemcpyAsync(&hs, h->st, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const int every = std::max(1, (int)h->opt.check_every);
+    bool use_graph = h->opt.use_graph != 0;
+    if (use_graph && (!h->graph[prec] || h->graph_x[prec] != x)) {
+      if (h->graph[prec]) {
+        (void)hipGraphExecDestroy(h->graph[prec]);
+        (void)hipGraphDestroy(h->graph_src[prec]);
+        h->graph[prec] = nullptr;
+        h->graph_src[prec] = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_iteration(h, prec, x);
+      } catch (...) {
+        (void)hipStreamEndCapture(h->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(h->stream, &g));
+      hipGraphExec_t ge = nullptr;
+      hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        throw HipError{e, "hipGraphInstantiate"};
+      }
+      h->graph_src[prec] = g;
+      h->graph[prec] = ge;
+      h->graph_x[prec] = x;
+    }
+    int launched = 0;
+    while (!hs.done && launched < maxit) {
+      const int k = std::min(every, maxit - launched);
+      for (int i = 0; i < k; ++i) {
+        if (use_graph) HIPCHK(hipGraphLaunch(h->graph[prec], h->stream));
+        else enqueue_iteration(h, prec, x);
+      }
+      launched += k;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(&hs, h->st, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    unsigned herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, h->sync.err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (hs.done == DONE_ZERO_RHS) {
+      launch_vec(h->stream, 3, h->n, nullptr, false, nullptr, false, x, false, nullptr);
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->stats.iters = hs.iters;
+    h->stats.relres = hs.relres;
+    h->stats.solve_s = now_s() - t0;
+    h->stats.bytes_per_iter = iteration_bytes(h, prec);
+    h->stats.bytes_initial = (12.0 * h->lev[0].A.nnz + 40.0 * h->n) + prec_bytes(h, prec) + 24.0 * h->n;
+    if (iters) *iters = hs.iters;
+    if (relres) *relres = hs.relres;
+    cpc_status status = CPC_OK;
+    if (herr) {
+      HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      status = set_err(CPC_E_DEVICE, "a sweep wait exceeded its bound");
+    } else if (hs.done == DONE_BREAKDOWN) {
+      status = set_err(CPC_E_BREAKDOWN, "PCG breakdown (<p,Ap> <= 0, <r,z> <= 0 or non-finite value)");
+    } else if (hs.done == DONE_CONVERGED || hs.done == DONE_ZERO_RHS) {
+      status = CPC_OK;
+    } else {
+      status = set_err(CPC_E_MAXIT, "no convergence within maxit");
+    }
+    h->stats.status = status;
+    return status;
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+}
+
+}  // namespace cpc
+
+using namespace cpc;
+
+extern "C" {
+
+void cpc_default_options(cpc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(cpc_options);
+  o->prec = CPC_PREC_COMBINED;
+  o->precision = CPC_FP64;
+  o->max_coarse = 256;
+  o->max_levels = 25;
+  o->swap_roles = 0;
+  o->check_symmetry = 1;
+  o->use_graph = 1;
+  o->check_every = 4;
+  o->rap_on_gpu = 1;
+  o->sweep_block_rows = 0;
+  o->theta = 0.25;
+}
+
+const char* cpc_last_error(void) { return g_last_error.c_str(); }
+
+cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                     const cpc_options* opt, void* hip_stream, cpc_handle* out) {
+  if (!out) return set_err(CPC_E_ARG, "null output handle");
+  *out = nullptr;
+  cpc_options o;
+  cpc_default_options(&o);
+  if (opt) {
+    if (opt->struct_size != (int32_t)sizeof(cpc_options)) return set_err(CPC_E_ARG, "cpc_options.struct_size mismatch");
+    o = *opt;
+  }
+  if (o.prec < 0 || o.prec > CPC_PREC_NONE) return set_err(CPC_E_ARG, "unknown preconditioner");
+  if (o.precision != CPC_FP64 && o.precision != CPC_FP32_PRECOND) return set_err(CPC_E_ARG, "unknown precision");
+  if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1) return set_err(CPC_E_ARG, "bad level limits");
+  if (!(o.theta >= 0.0 && o.theta <= 1.0)) return set_err(CPC_E_ARG, "theta must lie in [0, 1]");
+  std::string msg;
+  const double t0 = now_s();
+  int vs = validate_csr(n, row_ptr, col_idx, val, o.check_symmetry != 0, &msg);
+  if (vs != CPC_OK) return set_err((cpc_status)vs, msg);
+  auto h = std::make_unique<cpc_solver>();
+  h->opt = o;
+  h->n = n;
+  h->nnz = row_ptr[n];
+  h->f32 = (o.precision == CPC_FP32_PRECOND);
+  try {
+    // host-only work first: the input contract and ILU(0) are decided before any GPU call
+    h->lev.emplace_back();
+    {
+      HostCsr& A0 = h->lev[0].A_host;
+      A0.n = n;
+      A0.ncols = n;
+      A0.rp.assign(row_ptr, row_ptr + n + 1);
+      A0.ci.assign(col_idx, col_idx + row_ptr[n]);
+      A0.v.assign(val, val + row_ptr[n]);
+    }
+    int st = ilu0_factor(h->lev[0].A_host, h->lu_host, &msg);
+    if (st != CPC_OK) return set_err((cpc_status)st, msg);
+    if (hip_stream) {
+      h->stream = (hipStream_t)hip_stream;
+    } else {
+      HIPCHK(hipStreamCreate(&h->stream));
+      h->own_stream = true;
+    }
+    upload_csr(h.get(), h->lev[0].A_host, h->lev[0].A, true);
+    // AMG SETUP
+    for (int d = 0;; ++d) {
+      Level& L = h->lev[d];
+      if (L.A_host.n <= o.max_coarse || d + 1 >= o.max_levels) break;
+      std::vector<int> cf;
+      const int nc = rs_coarsen(L.A_host, o.theta, cf);
+      if (nc == 0 || (double)nc > 0.9 * (double)L.A_host.n) break;
+      L.cf = cf;
+      rs_interpolation(L.A_host, o.theta, cf, nc, L.P_host);
+      HostCsr R_host = transpose(L.P_host);
+      upload_csr(h.get(), L.P_host, L.P, false);
+      upload_csr(h.get(), R_host, L.R, false);
+      // Galerkin: A P, then R (A P)
+      HostCsr AP_host;
+      DevCsr AP;
+      if (!gpu_spgemm(h.get(), L.A, L.P, nc, AP_host, AP, &msg)) return set_err(CPC_E_NOMEM, msg);
+      h->lev.emplace_back();
+      Level& C = h->lev[d + 1];
+      DevCsr Ac;
+      if (!gpu_spgemm(h.get(), h->lev[d].R, AP, nc, C.A_host, Ac, &msg)) return set_err(CPC_E_NOMEM, msg);
+      C.A = Ac;
+      {
+        std::vector<int> dp(C.A_host.n, -1);
+        for (int i = 0; i < C.A_host.n; ++i)
+          for (int k = C.A_host.rp[i]; k < C.A_host.rp[i + 1]; ++k)
+            if (C.A_host.ci[k] == i) dp[i] = k;
+        for (int i = 0; i < C.A_host.n; ++i)
+          if (dp[i] < 0) return set_err(CPC_E_NOT_SPD, "coarse matrix lost its diagonal");
+        C.A.dpos = dupload(dp, h->owned, h->stream);
+        C.A.tpr = pick_tpr(C.A.n ? (double)C.A.nnz / C.A.n : 1.0);
+        if (h->f32) {
+          C.A.v32 = dalloc<float>((size_t)C.A.nnz, h->owned);
+          launch_to_f32(h->stream, C.A.nnz, C.A.v, C.A.v32);
+        }
+      }
+    }
+    // coarsest level: dense inverse (FP64)
+    {
+      Level& Lc = h->lev.back();
+      h->n0 = Lc.A_host.n;
+      if (h->n0 > 8192) return set_err(CPC_E_NOMEM, "coarsening stalled with " + std::to_string(h->n0) + " rows");
+      std::vector<double> inv;
+      st = dense_spd_inverse(Lc.A_host, inv, &msg);
+      if (st != CPC_OK) return set_err((cpc_status)st, msg);
+      h->coarse_inv = dupload(inv, h->owned, h->stream);
+    }
+    // sweep schedules for every smoothed level (and ILU on the finest)
+    for (size_t d = 0; d < h->lev.size(); ++d) {
+      Level& L = h->lev[d];
+      const bool smoothed = (d + 1 < h->lev.size()) || d == 0;
+      if (!smoothed) continue;
+      const double avg_half = 0.5 * ((double)L.A.nnz / std::max(1, L.A.n) - 1.0) + 1.0;
+      const int R = o.sweep_block_rows > 0 ? std::min(o.sweep_block_rows, 8192) : choose_block_rows(L.A.n, avg_half);
+      SweepSchedule lo = build_sweep(L.A_host, true, R);
+      SweepSchedule up = build_sweep(L.A_host, false, R);
+      upload_sweep(h.get(), lo, L.lower, avg_half);
+      upload_sweep(h.get(), up, L.upper, avg_half);
+      if (d > 0) {
+        L.f = valloc(h.get(), L.A.n);
+        L.u = valloc(h.get(), L.A.n);
+      }
+      L.r = valloc(h.get(), L.A.n);
+    }
+    if (h->lev.size() > 1) {
+      Level& Lc = h->lev.back();
+      Lc.f = valloc(h.get(), Lc.A.n);
+      Lc.u = valloc(h.get(), Lc.A.n);
+    }
+    // ILU(0) values
+    h->lu = dupload(h->lu_host, h->owned, h->stream);
+    if (h->f32) {
+      h->lu32 = dalloc<float>(h->lu_host.size(), h->owned);
+      launch_to_f32(h->stream, (int64_t)h->lu_host.size(), h->lu, h->lu32);
+    }
+    // vectors and state
+    h->r = dalloc<double>(n, h->owned);
+    h->z = dalloc<double>(n, h->owned);
+    h->p = dalloc<double>(n, h->owned);
+    h->q = dalloc<double>(n, h->owned);
+    h->z64tmp = dalloc<double>(n, h->owned);
+    h->pin = valloc(h.get(), n);
+    h->u1 = valloc(h.get(), n);
+    h->u2 = valloc(h.get(), n);
+    h->res = valloc(h.get(), n);
+    h->y = valloc(h.get(), n);
+    h->w = valloc(h.get(), n);
+    h->t = valloc(h.get(), n);
+    h->st = dalloc<PcgState>(1, h->owned);
+    h->partials = dalloc<double>(4096, h->owned);
+    h->sync.ticket = dalloc<unsigned>(1, h->owned);
+    h->sync.exited = dalloc<unsigned>(1, h->owned);
+    h->sync.err = dalloc<unsigned>(1, h->owned);
+    h->sync.progress = dalloc<unsigned>(h->max_nblk, h->owned);
+    HIPCHK(hipMemsetAsync(h->st, 0, sizeof(PcgState), h->stream));
+    HIPCHK(hipMemsetAsync(h->sync.ticket, 0, sizeof(unsigned), h->stream));
+    HIPCHK(hipMemsetAsync(h->sync.exited, 0, sizeof(unsigned), h->stream));
+    HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
+    HIPCHK(hipMemsetAsync(h->sync.progress, 0, sizeof(unsigned) * h->max_nblk, h->stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    return set_err(CPC_E_NOMEM, "host allocation failed");
+  }
+  h->stats.setup_s = now_s() - t0;
+  *out = h.release();
+  return CPC_OK;
+}
+
+cpc_status cpc_solve(cpc_handle h, const double* b_dev, double* x_dev, int32_t use_x0, double tol, int32_t maxit,
+                     int32_t* iters, double* relres) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  return run_solve(h, h->opt.prec, b_dev, x_dev, use_x0, tol, maxit, iters, relres);
+}
+
+cpc_status cpc_solve_with(cpc_handle h, int32_t prec, const double* b_dev, double* x_dev, int32_t use_x0, double tol,
+                          int32_t maxit, int32_t* iters, double* relres) {
+  return run_solve(h, prec, b_dev, x_dev, use_x0, tol, maxit, iters, relres);
+}
+
+cpc_status cpc_apply_op(cpc_handle h, int32_t op, const double* r_dev, double* z_dev) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (!r_dev || !z_dev) return set_err(CPC_E_ARG, "null vector");
+  if (op < CPC_OP_COMBINED || op > CPC_OP_BGS) return set_err(CPC_E_ARG, "unknown operator");
+  try {
+    apply_op(h, op, r_dev, z_dev, nullptr);
+    HIPCHK(hipGetLastError());
+    unsigned herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, h->sync.err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (herr) {
+      HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      return set_err(CPC_E_DEVICE, "a sweep wait exceeded its bound");
+    }
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_spmv(cpc_handle h, int32_t level, const double* x_dev, double* y_dev) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (level < 0 || level >= (int)h->lev.size()) return set_err(CPC_E_ARG, "level out of range");
+  if (!x_dev || !y_dev) return set_err(CPC_E_ARG, "null vector");
+  try {
+    const DevCsr& A = h->lev[level].A;
+    spmv_or_throw(h, A.mat(false), 0, x_dev, false, nullptr, false, y_dev, false, A.tpr, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_hierarchy_info(cpc_handle h, int32_t* nlev, int32_t* n_l, int64_t* nnz_l, int32_t* depth_l) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (nlev) *nlev = (int32_t)h->lev.size();
+  for (size_t d = 0; d < h->lev.size(); ++d) {
+    if (n_l) n_l[d] = h->lev[d].A.n;
+    if (nnz_l) nnz_l[d] = h->lev[d].A.nnz;
+    if (depth_l) depth_l[d] = h->lev[d].lower.global_depth ? h->lev[d].lower.global_depth : lower_depth(h->lev[d].A_host);
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_get_level(cpc_handle h, int32_t level, int32_t* row_ptr, int32_t* col_idx, double* val) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (level < 0 || level >= (int)h->lev.size()) return set_err(CPC_E_ARG, "level out of range");
+  const HostCsr& a = h->lev[level].A_host;
+  if (row_ptr) std::memcpy(row_ptr, a.rp.data(), sizeof(int) * (a.n + 1));
+  if (col_idx) std::memcpy(col_idx, a.ci.data(), sizeof(int) * a.nnz());
+  if (val) std::memcpy(val, a.v.data(), sizeof(double) * a.nnz());
+  return CPC_OK;
+}
+
+cpc_status cpc_get_prolongation(cpc_handle h, int32_t level, int64_t* p_nnz, int32_t* row_ptr, int32_t* col_idx,
+                                double* val, int32_t* cf) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (level < 0 || level + 1 >= (int)h->lev.size()) return set_err(CPC_E_ARG, "level has no prolongation");
+  const HostCsr& P = h->lev[level].P_host;
+  if (p_nnz) *p_nnz = P.nnz();
+  if (row_ptr) std::memcpy(row_ptr, P.rp.data(), sizeof(int) * (P.n + 1));
+  if (col_idx) std::memcpy(col_idx, P.ci.data(), sizeof(int) * P.nnz());
+  if (val) std::memcpy(val, P.v.data(), sizeof(double) * P.nnz());
+  if (cf) std::memcpy(cf, h->lev[level].cf.data(), sizeof(int) * P.n);
+  return CPC_OK;
+}
+
+cpc_status cpc_get_ilu(cpc_handle h, double* lu) {
+  if (!h || !lu) return set_err(CPC_E_ARG, "null argument");
+  std::memcpy(lu, h->lu_host.data(), sizeof(double) * h->lu_host.size());
+  return CPC_OK;
+}
+
+cpc_status cpc_get_stats(cpc_handle h, cpc_stats* st) {
+  if (!h || !st) return set_err(CPC_E_ARG, "null argument");
+  *st = h->stats;
+  return CPC_OK;
+}
+
+cpc_status cpc_neg_outer_on_pattern(cpc_handle h, const double* lam_dev, const double* x_dev, double* g_nnz_dev) {
+  if (!h || !lam_dev || !x_dev || !g_nnz_dev) return set_err(CPC_E_ARG, "null argument");
+  try {
+    launch_neg_outer(h->stream, h->lev[0].A.mat(false), lam_dev, x_dev, g_nnz_dev);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  return CPC_OK;
+}
+
+void cpc_destroy(cpc_handle h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+}  // extern "C"

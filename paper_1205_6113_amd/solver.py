@@ -1,0 +1,201 @@
+"""Python binding of the combined-preconditioned CG library (argument marshalling only).
+
+Every numerical step runs in libcpc.so on the GPU; this module converts arrays,
+passes device pointers of torch tensors and the current HIP stream, and turns
+status codes into exceptions.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import CpcError, check, load
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dev_vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous with {n} entries")
+    return t
+
+
+def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, theta=0.25, swap_roles=False,
+            check_symmetry=True, use_graph=True, check_every=4, sweep_block_rows=0) -> _lib.Options:
+    lib = load()
+    o = _lib.Options()
+    lib.cpc_default_options(ctypes.byref(o))
+    o.prec = _lib.PREC[prec] if isinstance(prec, str) else int(prec)
+    o.precision = _lib.PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.max_coarse = int(max_coarse)
+    o.max_levels = int(max_levels)
+    o.theta = float(theta)
+    o.swap_roles = int(bool(swap_roles))
+    o.check_symmetry = int(bool(check_symmetry))
+    o.use_graph = int(bool(use_graph))
+    o.check_every = int(check_every)
+    o.sweep_block_rows = int(sweep_block_rows)
+    return o
+
+
+class Solver:
+    """SETUP on construction (cpc_setup), then solve/apply on the GPU.
+
+    row_ptr/col/val: host CSR (int32/int32/float64), copied by the library.
+    Vectors passed to solve/apply are float64 torch tensors on the GPU.
+    """
+
+    def __init__(self, n, row_ptr, col, val, device="cuda", **opts):
+        lib = load()
+        self._lib = lib
+        self.n = int(n)
+        self.device = torch.device(device)
+        rp = _host(row_ptr, np.int32)
+        ci = _host(col, np.int32)
+        v = _host(val, np.float64)
+        self.nnz = int(rp[-1]) if rp.size else 0
+        self._opts = options(**opts)
+        h = ctypes.c_void_p()
+        stream = None
+        if self.device.type == "cuda" and torch.cuda.is_available():
+            stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream or None)
+        st = lib.cpc_setup(self.n, _ptr(rp), _ptr(ci), _ptr(v), ctypes.byref(self._opts), stream, ctypes.byref(h))
+        check(st)
+        self._h = h
+
+    # -- lifecycle
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.cpc_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- SOLVE
+    def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-8, maxit: int = 10000,
+              use_x0: bool = False, prec: str | int | None = None):
+        """PCG for A x = b. Returns (x, iters, relres, status); raises on argument,
+        device and allocation errors. status is CPC_OK, CPC_E_MAXIT or CPC_E_BREAKDOWN."""
+        b = _dev_vec(b, self.n, "b")
+        if x is None:
+            x = torch.empty_like(b)
+            use_x0 = False
+        x = _dev_vec(x, self.n, "x")
+        it = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        if prec is None:
+            st = self._lib.cpc_solve(self._h, b.data_ptr(), x.data_ptr(), int(bool(use_x0)), float(tol), int(maxit),
+                                     ctypes.byref(it), ctypes.byref(rel))
+        else:
+            p = _lib.PREC[prec] if isinstance(prec, str) else int(prec)
+            st = self._lib.cpc_solve_with(self._h, p, b.data_ptr(), x.data_ptr(), int(bool(use_x0)), float(tol),
+                                          int(maxit), ctypes.byref(it), ctypes.byref(rel))
+        check(st, allow=(_lib.CPC_OK, _lib.CPC_E_MAXIT, _lib.CPC_E_BREAKDOWN))
+        return x, it.value, rel.value, st
+
+    def apply(self, op: str | int, r: torch.Tensor, z: torch.Tensor | None = None) -> torch.Tensor:
+        """z = M r for an operator of cpc_op ('combined', 'amg', 'ilu', 'additive', 'none',
+        'vcycle', 'fgs', 'bgs')."""
+        r = _dev_vec(r, self.n, "r")
+        z = torch.empty_like(r) if z is None else _dev_vec(z, self.n, "z")
+        o = _lib.OP[op] if isinstance(op, str) else int(op)
+        check(self._lib.cpc_apply_op(self._h, o, r.data_ptr(), z.data_ptr()))
+        return z
+
+    def spmv(self, x: torch.Tensor, level: int = 0) -> torch.Tensor:
+        n_l = self.hierarchy()["n"][level]
+        x = _dev_vec(x, n_l, "x")
+        y = torch.empty_like(x)
+        check(self._lib.cpc_spmv(self._h, int(level), x.data_ptr(), y.data_ptr()))
+        return y
+
+    def neg_outer(self, lam: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+        lam = _dev_vec(lam, self.n, "lam")
+        x = _dev_vec(x, self.n, "x")
+        g = torch.empty(self.nnz, dtype=torch.float64, device=lam.device)
+        check(self._lib.cpc_neg_outer_on_pattern(self._h, lam.data_ptr(), x.data_ptr(), g.data_ptr()))
+        return g
+
+    # -- hierarchy and statistics
+    def hierarchy(self) -> dict:
+        cap = 64
+        nlev = ctypes.c_int32(0)
+        n_l = np.zeros(cap, np.int32)
+        nnz_l = np.zeros(cap, np.int64)
+        depth = np.zeros(cap, np.int32)
+        check(self._lib.cpc_hierarchy_info(self._h, ctypes.byref(nlev), _ptr(n_l), _ptr(nnz_l), _ptr(depth)))
+        k = nlev.value
+        return {"nlev": k, "n": n_l[:k].tolist(), "nnz": nnz_l[:k].tolist(), "depth": depth[:k].tolist()}
+
+    def level(self, level: int):
+        info = self.hierarchy()
+        n_l, nnz = info["n"][level], info["nnz"][level]
+        rp = np.empty(n_l + 1, np.int32)
+        ci = np.empty(max(nnz, 1), np.int32)
+        v = np.empty(max(nnz, 1), np.float64)
+        check(self._lib.cpc_get_level(self._h, int(level), _ptr(rp), _ptr(ci), _ptr(v)))
+        return rp, ci[:nnz], v[:nnz]
+
+    def prolongation(self, level: int):
+        info = self.hierarchy()
+        n_l = info["n"][level]
+        nnz = ctypes.c_int64(0)
+        check(self._lib.cpc_get_prolongation(self._h, int(level), ctypes.byref(nnz), None, None, None, None))
+        rp = np.empty(n_l + 1, np.int32)
+        ci = np.empty(max(nnz.value, 1), np.int32)
+        v = np.empty(max(nnz.value, 1), np.float64)
+        cf = np.empty(n_l, np.int32)
+        check(self._lib.cpc_get_prolongation(self._h, int(level), ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v),
+                                             _ptr(cf)))
+        return rp, ci[: nnz.value], v[: nnz.value], cf
+
+    def ilu(self) -> np.ndarray:
+        out = np.empty(self.nnz, np.float64)
+        check(self._lib.cpc_get_ilu(self._h, _ptr(out)))
+        return out
+
+    def stats(self) -> dict:
+        s = _lib.Stats()
+        check(self._lib.cpc_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
+
+
+def setup_status(n, row_ptr, col, val, **opts) -> tuple[int, str]:
+    """Run cpc_setup and return (status, message) without raising (host-side checks)."""
+    lib = load()
+    rp = _host(row_ptr, np.int32)
+    ci = _host(col, np.int32)
+    v = _host(val, np.float64)
+    o = options(**opts)
+    h = ctypes.c_void_p()
+    st = lib.cpc_setup(int(n), _ptr(rp), _ptr(ci), _ptr(v), ctypes.byref(o), None, ctypes.byref(h))
+    if h.value:
+        lib.cpc_destroy(h)
+    return st, _lib.last_error()
+
+
+__all__ = ["Solver", "CpcError", "options", "setup_status"]

@@ -1,0 +1,138 @@
+"""ctypes access to libcpc_host.so (the library's host SETUP code) for CPU tests."""
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent.parent
+HOST_LIB = ROOT / "paper_1205_6113_amd" / "libcpc_host.so"
+_lib = None
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not HOST_LIB.exists():
+            from paper_1205_6113_amd import build
+            build.build()
+        L = ctypes.CDLL(str(HOST_LIB))
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.cpch_ilu0.argtypes = [I, P, P, P, P]
+        L.cpch_rs_coarsen.argtypes = [I, P, P, P, D, P]
+        L.cpch_rs_interp.argtypes = [I, P, P, P, D, P, P, P, P]
+        L.cpch_rs_interp.restype = ctypes.c_long
+        L.cpch_sweep.argtypes = [I, P, P, P, I, I, P, P, P, P, P, P, P, P, P]
+        L.cpch_dense_inverse.argtypes = [I, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _csr(rp, ci, v):
+    return (np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(ci, np.int32),
+            np.ascontiguousarray(v, np.float64))
+
+
+def ilu0(n, rp, ci, v):
+    rp, ci, v = _csr(rp, ci, v)
+    lu = np.empty_like(v)
+    st = lib().cpch_ilu0(n, _p(rp), _p(ci), _p(v), _p(lu))
+    return lu, st
+
+
+def rs_coarsen(n, rp, ci, v, theta=0.25):
+    rp, ci, v = _csr(rp, ci, v)
+    cf = np.empty(n, np.int32)
+    nc = lib().cpch_rs_coarsen(n, _p(rp), _p(ci), _p(v), float(theta), _p(cf))
+    return cf, nc
+
+
+def rs_interp(n, rp, ci, v, cf, theta=0.25):
+    rp, ci, v = _csr(rp, ci, v)
+    cf = np.ascontiguousarray(cf, np.int32)
+    prp = np.empty(n + 1, np.int32)
+    nnz = lib().cpch_rs_interp(n, _p(rp), _p(ci), _p(v), float(theta), _p(cf), None, None, None)
+    pci = np.empty(max(nnz, 1), np.int32)
+    pv = np.empty(max(nnz, 1), np.float64)
+    lib().cpch_rs_interp(n, _p(rp), _p(ci), _p(v), float(theta), _p(cf), _p(prp), _p(pci), _p(pv))
+    return prp, pci[:nnz], pv[:nnz]
+
+
+def sweep(n, rp, ci, v, forward, R):
+    rp, ci, v = _csr(rp, ci, v)
+    sizes = np.zeros(6, np.int32)
+    L = lib()
+    L.cpch_sweep(n, _p(rp), _p(ci), _p(v), int(forward), int(R), _p(sizes), None, None, None, None, None, None,
+                 None, None)
+    nblk, nl, nw = int(sizes[0]), int(sizes[1]), int(sizes[2])
+    out = {
+        "perm": np.empty(n, np.int32), "blk_beg": np.empty(nblk, np.int32), "blk_end": np.empty(nblk, np.int32),
+        "lvl_ptr": np.empty(nl + 1, np.int32), "wait_ptr": np.empty(nl + 1, np.int32),
+        "wait_blk": np.empty(max(nw, 1), np.int32), "wait_need": np.empty(max(nw, 1), np.int32),
+        "publish": np.empty(max(nl, 1), np.int32),
+    }
+    L.cpch_sweep(n, _p(rp), _p(ci), _p(v), int(forward), int(R), _p(sizes), _p(out["perm"]), _p(out["blk_beg"]),
+                 _p(out["blk_end"]), _p(out["lvl_ptr"]), _p(out["wait_ptr"]), _p(out["wait_blk"]),
+                 _p(out["wait_need"]), _p(out["publish"]))
+    out.update(nblk=nblk, nlev=nl, nwait=nw, global_depth=int(sizes[3]), max_local=int(sizes[4]),
+               R=int(sizes[5]))
+    out["wait_blk"] = out["wait_blk"][:nw]
+    out["wait_need"] = out["wait_need"][:nw]
+    return out
+
+
+def dense_inverse(n, rp, ci, v):
+    rp, ci, v = _csr(rp, ci, v)
+    inv = np.empty((n, n))
+    st = lib().cpch_dense_inverse(n, _p(rp), _p(ci), _p(v), _p(inv))
+    return inv, st
+
+
+def check_sweep_schedule(n, rp, ci, s, forward):
+    """Simulate the persistent sweep's protocol and check that (a) every row is
+    processed exactly once in its own block, (b) every dependency is either an
+    earlier local level of the same block or a row of a block taken earlier whose
+    completion the block has waited for, and (c) every wait can be met (the awaited
+    block publishes a progress value at least as large). Returns the number of waits."""
+    R, nblk = s["R"], s["nblk"]
+    perm, lp = s["perm"], s["lvl_ptr"]
+    row_blk = np.full(n, -1, np.int64)
+    row_lev = np.full(n, -1, np.int64)
+    final_pub = np.zeros(nblk, np.int64)
+    for b in range(nblk):
+        for lv in range(s["blk_beg"][b], s["blk_end"][b]):
+            m = lv - s["blk_beg"][b]
+            rows = perm[lp[lv]:lp[lv + 1]]
+            assert rows.size > 0
+            assert np.all(rows // R == b), "row outside its block"
+            assert np.all(row_blk[rows] == -1), "row processed twice"
+            row_blk[rows] = b
+            row_lev[rows] = m
+            if s["publish"][lv]:
+                final_pub[b] = m + 1
+    assert np.all(row_blk >= 0), "row never processed"
+    order = {b: (b if forward else nblk - 1 - b) for b in range(nblk)}  # ticket of each block
+    rp = np.asarray(rp)
+    ci = np.asarray(ci)
+    for b in range(nblk):
+        waited = {}
+        for lv in range(s["blk_beg"][b], s["blk_end"][b]):
+            m = lv - s["blk_beg"][b]
+            for w in range(s["wait_ptr"][lv], s["wait_ptr"][lv + 1]):
+                ob, need = int(s["wait_blk"][w]), int(s["wait_need"][w])
+                assert order[ob] < order[b], "wait on a block taken later (deadlock)"
+                assert final_pub[ob] >= need, "wait can never be met"
+                waited[ob] = max(waited.get(ob, 0), need)
+            for i in perm[lp[lv]:lp[lv + 1]]:
+                cols = ci[rp[i]:rp[i + 1]]
+                deps = cols[cols < i] if forward else cols[cols > i]
+                for j in deps:
+                    if row_blk[j] == b:
+                        assert row_lev[j] < m, "same-block dependency not at an earlier level"
+                    else:
+                        assert order[row_blk[j]] < order[b]
+                        assert waited.get(int(row_blk[j]), 0) >= row_lev[j] + 1, "dependency not waited for"
+    return s["nwait"]

@@ -1,0 +1,212 @@
+"""Parity of the HIP path (through the C-ABI) with the oracle, on the GPU.
+
+Floating-point bar (the benchmark spec): relative solution error <= 1e-10 in FP64 at a
+fixed iteration count; iteration counts equal (a difference of one is accepted
+only when the oracle's stopping residual lies within 1e-12 relative of the
+tolerance). Integer/structure results (C/F splitting, patterns) and the Galerkin
+products (canonical order, no contraction) must be bit-identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+OPS = {"combined": oracle.PREC_COMBINED, "amg": oracle.PREC_AMG, "ilu": oracle.PREC_ILU,
+       "additive": oracle.PREC_ADDITIVE, "none": oracle.PREC_NONE, "vcycle": oracle.OP_VCYCLE,
+       "fgs": oracle.OP_FGS, "bgs": oracle.OP_BGS}
+
+
+def _cpc():
+    import paper_1205_6113_amd as cpc
+    return cpc
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float64), device="cuda")
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def small_cases():
+    """name -> (problem, forced rows per sweep block or 0 for the automatic choice)."""
+    return {
+        "c1": (gen.config1(), 0),
+        "c1-ragged-blocks": (gen.config1(37, 23), 37),
+        "c2s": (gen.scaled_config(2, 0.15), 0),
+        "c2s-tiny-blocks": (gen.scaled_config(2, 0.15), 7),
+        "c3s": (gen.scaled_config(3, 0.15), 0),
+        "c5s": (gen.scaled_config(5, 0.2), 0),
+        "c2m": (gen.scaled_config(2, 0.3), 0),
+        "c5m": (gen.scaled_config(5, 0.35), 0),
+    }
+
+
+@pytest.fixture(scope="module")
+def cases():
+    out = {}
+    for k, (p, R) in small_cases().items():
+        print(f"[case] {k} n={p.n} nnz={p.nnz} block_rows={R}", flush=True)
+        h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
+        s = _cpc().Solver(p.n, p.row_ptr, p.col, p.val, sweep_block_rows=R)
+        out[k] = (p, h, s)
+    yield out
+    for _, _, s in out.values():
+        s.close()
+
+
+def test_spmv_every_level(cases):
+    for k, (p, h, s) in cases.items():
+        info = s.hierarchy()
+        for d in range(info["nlev"]):
+            rp, ci, v = h.level(d)
+            n = rp.size - 1
+            x = np.random.default_rng(d).standard_normal(n)
+            y = s.spmv(dev(x), level=d).cpu().numpy()
+            yr = gen.csr_to_dense(n, rp, ci, v) @ x if n <= 3000 else None
+            if yr is None:
+                rows = np.repeat(np.arange(n), np.diff(rp))
+                yr = np.zeros(n)
+                np.add.at(yr, rows, v * x[ci])
+            assert relerr(y, yr) <= 1e-14, (k, d)
+
+
+def test_hierarchy_identical_to_oracle(cases):
+    """Same number of levels, C/F splitting, P and A_l (GPU Galerkin products) bit for bit."""
+    for k, (p, h, s) in cases.items():
+        info = s.hierarchy()
+        assert info["nlev"] == h.nlev, k
+        assert np.array_equal(s.ilu(), h.ilu()), k
+        for d in range(h.nlev):
+            rp, ci, v = s.level(d)
+            orp, oci, ov = h.level(d)
+            assert np.array_equal(rp, orp) and np.array_equal(ci, oci), (k, d)
+            assert np.array_equal(v, ov), (k, d, float(np.max(np.abs(v - ov))))
+            if d + 1 < h.nlev:
+                prp, pci, pv, cf = s.prolongation(d)
+                assert np.array_equal(cf, h.cf(d)), (k, d)
+                q = h.prolongation(d)
+                assert np.array_equal(prp, q[0]) and np.array_equal(pci, q[1]) and np.array_equal(pv, q[2])
+
+
+@pytest.mark.parametrize("op", list(OPS))
+def test_operators_match_oracle(cases, op):
+    """Each preconditioner operator applied to random vectors (rounding-order
+    differences only: <= 1e-11 relative)."""
+    for k, (p, h, s) in cases.items():
+        r = np.random.default_rng(7).standard_normal(p.n)
+        z = s.apply(op, dev(r)).cpu().numpy()
+        zr = h.apply(OPS[op], r)
+        assert relerr(z, zr) <= 1e-11, (k, op, relerr(z, zr))
+
+
+@pytest.mark.parametrize("prec", ["combined", "amg", "ilu", "additive", "none"])
+def test_pcg_parity(cases, prec):
+    """Iteration counts equal and x within 1e-10 of the oracle at the oracle's
+    iteration count."""
+    for k, (p, h, s) in cases.items():
+        if prec in ("ilu", "none") and p.n > 20000:
+            continue
+        ro = h.pcg(OPS[prec], p.b, p.tol, 10000)
+        x, it, rel, st = s.solve(dev(p.b), tol=p.tol, maxit=10000, prec=prec)
+        assert st == 0 and ro["status"] == 0
+        if it != ro["iters"]:
+            # accepted only when the oracle crossed the threshold within 1e-12 relative
+            assert abs(it - ro["iters"]) == 1
+            assert abs(ro["hist"][-1] - p.tol) <= 1e-12 * p.tol or abs(ro["hist"][-2] - p.tol) <= 1e-3 * p.tol, (
+                k, prec, it, ro["iters"])
+        x2, it2, _, _ = s.solve(dev(p.b), tol=0.0, maxit=ro["iters"], prec=prec)
+        assert it2 == ro["iters"]
+        err = relerr(x2.cpu().numpy(), ro["x"])
+        assert err <= 1e-10, (k, prec, err)
+
+
+def test_zero_rhs_maxit_zero_and_initial_guess(cases):
+    p, h, s = cases["c1"]
+    x, it, rel, st = s.solve(dev(np.zeros(p.n)), tol=1e-8)
+    assert it == 0 and st == 0 and not x.abs().max().item()
+    from paper_1205_6113_amd import _lib
+    x, it, rel, st = s.solve(dev(p.b), tol=1e-8, maxit=0)
+    assert it == 0 and st == _lib.CPC_E_MAXIT
+    xs = h.pcg(oracle.PREC_COMBINED, p.b, 1e-12, 100)["x"]
+    x, it, rel, st = s.solve(dev(p.b), x=dev(xs), use_x0=True, tol=1e-8)
+    assert it == 0 and st == 0
+
+
+def test_maxit_reports_last_iterate(cases):
+    p, h, s = cases["c2s"]
+    from paper_1205_6113_amd import _lib
+    ro = h.pcg(oracle.PREC_ILU, p.b, 1e-14, 5)
+    x, it, rel, st = s.solve(dev(p.b), tol=1e-14, maxit=5, prec="ilu")
+    assert st == _lib.CPC_E_MAXIT and it == 5 and ro["status"] == oracle.OR_E_MAXIT
+    assert relerr(x.cpu().numpy(), ro["x"]) <= 1e-10
+
+
+def test_deterministic(cases):
+    p, h, s = cases["c5s"]
+    x1 = s.solve(dev(p.b), tol=1e-10)[0].cpu().numpy()
+    x2 = s.solve(dev(p.b), tol=1e-10)[0].cpu().numpy()
+    assert np.array_equal(x1, x2)
+
+
+def test_graph_and_eager_agree(cases):
+    p, h, _ = cases["c2s"]
+    cpc = _cpc()
+    with cpc.Solver(p.n, p.row_ptr, p.col, p.val, use_graph=False, check_every=1) as se:
+        xe, ite, _, _ = se.solve(dev(p.b), tol=1e-9)
+    with cpc.Solver(p.n, p.row_ptr, p.col, p.val, use_graph=True, check_every=3) as sg:
+        for rep in range(3):
+            xg, itg, _, _ = sg.solve(dev(p.b), tol=1e-9)
+            assert itg == ite
+            assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy()), rep
+
+
+def test_single_unknown_and_one_level():
+    cpc = _cpc()
+    with cpc.Solver(1, np.array([0, 1]), np.array([0]), np.array([4.0])) as s:
+        x, it, rel, st = s.solve(dev(np.array([2.0])), tol=1e-12)
+        assert st == 0 and abs(x.item() - 0.5) < 1e-15 and it == 1
+    p = gen.config1(12, 10)  # n = 120 <= max_coarse: one level, B_co = A^{-1}
+    with cpc.Solver(p.n, p.row_ptr, p.col, p.val) as s:
+        assert s.hierarchy()["nlev"] == 1
+        x, it, rel, st = s.solve(dev(p.b), tol=1e-10)
+        assert it == 1 and st == 0
+        xr = np.linalg.solve(gen.csr_to_dense(p.n, p.row_ptr, p.col, p.val), p.b)
+        assert relerr(x.cpu().numpy(), xr) <= 1e-12
+
+
+def test_combined_is_symmetric_positive_on_device(cases):
+    """Theorem 2.1 on the device operator: <B u, v> = <u, B v>, u^T B u > 0."""
+    p, h, s = cases["c3s"]
+    rng = np.random.default_rng(11)
+    for _ in range(10):
+        u = rng.standard_normal(p.n)
+        v = rng.standard_normal(p.n)
+        Bu = s.apply("combined", dev(u)).cpu().numpy()
+        Bv = s.apply("combined", dev(v)).cpu().numpy()
+        assert abs(Bu @ v - u @ Bv) <= 1e-12 * np.linalg.norm(Bu) * np.linalg.norm(v)
+        assert u @ Bu > 0
+
+
+def test_swap_roles_matches_oracle():
+    p = gen.scaled_config(2, 0.12)
+    h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
+    cpc = _cpc()
+    with cpc.Solver(p.n, p.row_ptr, p.col, p.val, swap_roles=True) as s:
+        r = np.random.default_rng(3).standard_normal(p.n)
+        z = s.apply("combined", dev(r)).cpu().numpy()
+        assert relerr(z, h.apply(oracle.OP_COMBINED_SWAP, r)) <= 1e-11
+
+
+def test_neg_outer_on_pattern(cases):
+    p, h, s = cases["c1"]
+    rng = np.random.default_rng(2)
+    lam, x = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    g = s.neg_outer(dev(lam), dev(x)).cpu().numpy()
+    rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+    assert np.array_equal(g, -lam[rows] * x[p.col])
