@@ -160,6 +160,32 @@ cpc_status cpc_get_stats(cpc_handle h, cpc_stats* st);
  * Device arrays: lam, x of length n; g of length nnz. */
 cpc_status cpc_neg_outer_on_pattern(cpc_handle h, const double* lam_dev, const double* x_dev, double* g_nnz_dev);
 
+/* Kernel families timed by cpc_time_kernel. */
+typedef enum {
+  CPC_K_SPMV_PQ = 0,   /* PCG q = A p with <p, q> (finest level)                           */
+  CPC_K_FGS = 1,       /* forward Gauss-Seidel sweep from zero (V-cycle pre-smoothing)      */
+  CPC_K_BGS = 2,       /* backward Gauss-Seidel sweep in place (V-cycle post-smoothing)     */
+  CPC_K_ILU_L = 3,     /* ILU(0) unit-lower solve                                           */
+  CPC_K_ILU_U = 4,     /* ILU(0) upper solve with the u2 = u1 + w epilogue                  */
+  CPC_K_RESIDUAL = 5,  /* level residual r = f - A u                                        */
+  CPC_K_RESTRICT = 6,  /* f_c = R r                                                         */
+  CPC_K_PROLONG = 7,   /* u += P e                                                          */
+  CPC_K_VCYCLE = 8,    /* one whole V-cycle                                                 */
+  CPC_K_PRECOND = 9,   /* one application of the handle's preconditioner                    */
+  CPC_K_ITERATION = 10 /* one whole PCG iteration                                           */
+} cpc_kernel;
+
+/* Measurement helper (not needed to solve): runs `reps` repetitions of the kernel
+ * family `kernel` (cpc_kernel) on the handle's current work vectors and reports the
+ * mean duration of one launch (HIP events recorded on the handle's stream around all
+ * repetitions, ms), the algorithmic HBM bytes of one launch (the byte model: matrix
+ * streams read once, vectors read or written once per launch) and the number of
+ * launches timed. level >= 0 selects one level; level = -1 takes every level the
+ * family runs on in one V-cycle, one launch per level per repetition (the averages
+ * are then over that mix). Work vectors are overwritten. */
+cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t reps, double* avg_ms,
+                           double* bytes_per_launch, int32_t* launches);
+
 /* Destroy the handle and free its device and host memory (NULL is ignored). */
 void cpc_destroy(cpc_handle h);
 

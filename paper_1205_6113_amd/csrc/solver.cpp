@@ -278,6 +278,8 @@ static void spmv_or_throw(cpc_solver* h, const MatDev& A, int mode, const void* 
     throw HipError{hipErrorInvalidValue, "unsupported SpMV precision combination"};
 }
 
+static size_t esz_of(const cpc_solver* h) { return h->f32 ? sizeof(float) : sizeof(double); }
+
 static void* valloc(cpc_solver* h, int n) {
   if (h->f32) return dalloc<float>(n, h->owned);
   return dalloc<double>(n, h->owned);
@@ -441,6 +443,28 @@ static double vcycle_bytes(const cpc_solver* h) {
   const double n0 = h->lev.back().A.n;
   b += 8.0 * n0 * n0 + 2.0 * vb * n0;
   return b;
+}
+
+// Bytes of one launch of a kernel family on level d (same model as vcycle_bytes).
+static double kernel_bytes(const cpc_solver* h, int kernel, int d) {
+  const double vb = h->f32 ? 4.0 : 8.0;
+  const double mb = h->f32 ? 8.0 : 12.0;
+  const Level& L = h->lev[d];
+  const double nz = (double)L.A.nnz, n = L.A.n;
+  const double half = 0.5 * (nz - n);
+  const double nc = (d + 1 < (int)h->lev.size()) ? (double)h->lev[d + 1].A.n : 0.0;
+  const double p = (double)L.P.nnz;
+  switch (kernel) {
+    case CPC_K_SPMV_PQ: return 12.0 * nz + 4.0 * n + 16.0 * n;
+    case CPC_K_FGS: return (half + n) * mb + 4.0 * n + 3.0 * vb * n;
+    case CPC_K_BGS: return nz * mb + 4.0 * n + 3.0 * vb * n;
+    case CPC_K_ILU_L: return half * mb + 4.0 * n + 2.0 * vb * n;
+    case CPC_K_ILU_U: return (half + n) * mb + 4.0 * n + 4.0 * vb * n;
+    case CPC_K_RESIDUAL: return nz * mb + 4.0 * n + 3.0 * vb * n;
+    case CPC_K_RESTRICT: return p * mb + 4.0 * nc + vb * n + vb * nc;
+    case CPC_K_PROLONG: return p * mb + 4.0 * n + 2.0 * vb * n + vb * nc;
+    default: return 0.0;
+  }
 }
 
 static double prec_bytes(const cpc_solver* h, int prec) {
@@ -722,6 +746,13 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
     h->sync.exited = dalloc<unsigned>(1, h->owned);
     h->sync.err = dalloc<unsigned>(1, h->owned);
     h->sync.progress = dalloc<unsigned>(h->max_nblk, h->owned);
+    for (void* v : {h->pin, h->u1, h->u2, h->res, h->y, h->w, h->t})
+      HIPCHK(hipMemsetAsync(v, 0, esz_of(h.get()) * (size_t)n, h->stream));
+    for (void* v : {(void*)h->r, (void*)h->z, (void*)h->p, (void*)h->q, (void*)h->z64tmp})
+      HIPCHK(hipMemsetAsync(v, 0, sizeof(double) * (size_t)n, h->stream));
+    for (auto& L : h->lev)
+      for (void* v : {L.f, L.u, L.r})
+        if (v) HIPCHK(hipMemsetAsync(v, 0, esz_of(h.get()) * (size_t)L.A.n, h->stream));
     HIPCHK(hipMemsetAsync(h->st, 0, sizeof(PcgState), h->stream));
     HIPCHK(hipMemsetAsync(h->sync.ticket, 0, sizeof(unsigned), h->stream));
     HIPCHK(hipMemsetAsync(h->sync.exited, 0, sizeof(unsigned), h->stream));
@@ -838,6 +869,123 @@ cpc_status cpc_neg_outer_on_pattern(cpc_handle h, const double* lam_dev, const d
     launch_neg_outer(h->stream, h->lev[0].A.mat(false), lam_dev, x_dev, g_nnz_dev);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t reps, double* avg_ms,
+                           double* bytes_per_launch, int32_t* launches) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (reps < 1 || kernel < CPC_K_SPMV_PQ || kernel > CPC_K_ITERATION) return set_err(CPC_E_ARG, "bad kernel or reps");
+  const int nlev = (int)h->lev.size();
+  const bool per_level = kernel >= CPC_K_FGS && kernel <= CPC_K_PROLONG && kernel != CPC_K_ILU_L &&
+                         kernel != CPC_K_ILU_U;
+  // levels the family runs on: smoothed levels (all but the coarsest), finest only for ILU/PCG
+  std::vector<int> levels;
+  if (per_level) {
+    if (level >= 0) {
+      if (level >= nlev - 1 && !(nlev == 1 && level == 0 && kernel == CPC_K_RESIDUAL))
+        return set_err(CPC_E_ARG, "level has no such kernel");
+      levels.push_back(level);
+    } else {
+      for (int d = 0; d + 1 < nlev; ++d) levels.push_back(d);
+    }
+    if (levels.empty()) return set_err(CPC_E_ARG, "hierarchy has one level");
+  } else {
+    levels.push_back(0);
+  }
+  const bool f32 = h->f32;
+  auto launch_once = [&](int d) {
+    Level& L = h->lev[d];
+    const MatDev A = L.A.mat(f32);
+    void* f = d == 0 ? h->pin : L.f;
+    void* u = d == 0 ? h->u1 : L.u;
+    switch (kernel) {
+      case CPC_K_SPMV_PQ:
+        launch_spmv_pq(h->stream, L.A.mat(false), h->p, h->q, h->partials, h->st, L.A.tpr);
+        break;
+      case CPC_K_FGS:
+        launch_sweep(h->stream, SWEEP_FGS0, L.lower.d, A, A.v, f32, f, u, nullptr, nullptr, h->sync, nullptr,
+                     h->spin_limit);
+        break;
+      case CPC_K_BGS:
+        launch_sweep(h->stream, SWEEP_BGS_IP, L.upper.d, A, A.v, f32, f, u, nullptr, nullptr, h->sync, nullptr,
+                     h->spin_limit);
+        break;
+      case CPC_K_ILU_L:
+        launch_sweep(h->stream, SWEEP_ILU_L, L.lower.d, A, f32 ? (const void*)h->lu32 : (const void*)h->lu, f32,
+                     h->res, h->y, nullptr, nullptr, h->sync, nullptr, h->spin_limit);
+        break;
+      case CPC_K_ILU_U:
+        launch_sweep(h->stream, SWEEP_ILU_U, L.upper.d, A, f32 ? (const void*)h->lu32 : (const void*)h->lu, f32,
+                     h->y, h->w, h->u1, h->u2, h->sync, nullptr, h->spin_limit);
+        break;
+      case CPC_K_RESIDUAL:
+        spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, nullptr);
+        break;
+      case CPC_K_RESTRICT:
+        spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, h->lev[d + 1].f, f32, L.R.tpr, nullptr);
+        break;
+      case CPC_K_PROLONG:
+        spmv_or_throw(h, L.P.mat(f32), 2, h->lev[d + 1].u, f32, nullptr, f32, u, f32, L.P.tpr, nullptr);
+        break;
+      case CPC_K_VCYCLE:
+        vcycle(h, 0, h->pin, h->u1, nullptr);
+        break;
+      case CPC_K_PRECOND:
+        apply_op(h, prec_to_op(h->opt.prec), h->r, h->z, nullptr);
+        break;
+      default:
+        enqueue_iteration(h, h->opt.prec, h->z64tmp);
+        break;
+    }
+  };
+  try {
+    if (kernel == CPC_K_SPMV_PQ || kernel == CPC_K_ITERATION) {
+      // a running state with positive scalars so that nothing returns early
+      PcgState s{};
+      s.rz = 1.0;
+      s.bb = 1.0;
+      s.tol = 0.0;
+      s.maxit = 1 << 30;
+      HIPCHK(hipMemcpyAsync(h->st, &s, sizeof(s), hipMemcpyHostToDevice, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    for (int d : levels) launch_once(d);  // warm-up
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int r = 0; r < reps; ++r)
+      for (int d : levels) launch_once(d);
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    double b = 0.0;
+    for (int d : levels) {
+      if (kernel <= CPC_K_PROLONG) b += kernel_bytes(h, kernel, d);
+      else if (kernel == CPC_K_VCYCLE) b += vcycle_bytes(h);
+      else if (kernel == CPC_K_PRECOND) b += prec_bytes(h, h->opt.prec);
+      else b += iteration_bytes(h, h->opt.prec);
+    }
+    const int nl = reps * (int)levels.size();
+    if (avg_ms) *avg_ms = ms / nl;
+    if (bytes_per_launch) *bytes_per_launch = b / levels.size();
+    if (launches) *launches = nl;
+    unsigned herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, h->sync.err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (herr) {
+      HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      return set_err(CPC_E_DEVICE, "a sweep wait exceeded its bound");
+    }
   } catch (const HipError& e) {
     return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
   }

@@ -178,6 +178,16 @@ class Solver:
         check(self._lib.cpc_get_ilu(self._h, _ptr(out)))
         return out
 
+    def time_kernel(self, kernel: str | int, level: int = -1, reps: int = 10) -> dict:
+        """HIP-event timing of one kernel family (see cpc_time_kernel)."""
+        k = _lib.KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
+        ms = ctypes.c_double(0.0)
+        b = ctypes.c_double(0.0)
+        nl = ctypes.c_int32(0)
+        check(self._lib.cpc_time_kernel(self._h, k, int(level), int(reps), ctypes.byref(ms), ctypes.byref(b),
+                                        ctypes.byref(nl)))
+        return {"avg_ms": ms.value, "bytes": b.value, "launches": nl.value}
+
     def stats(self) -> dict:
         s = _lib.Stats()
         check(self._lib.cpc_get_stats(self._h, ctypes.byref(s)))
