@@ -160,6 +160,37 @@ cpc_status cpc_get_stats(cpc_handle h, cpc_stats* st);
  * Device arrays: lam, x of length n; g of length nnz. */
 cpc_status cpc_neg_outer_on_pattern(cpc_handle h, const double* lam_dev, const double* x_dev, double* g_nnz_dev);
 
+/* ---- Differentiable form (gradient of a misfit through the solve) ---------------
+ * The two-point-flux matrix of the model problem of Section 4 (c = 0) on an
+ * nx x ny x nz grid of unit cells (cell index i + nx*(j + ny*k)): a_ij = -T_ij,
+ * T = 2 s k_a k_b / (k_a + k_b), k = exp(log k), s = 1 on x/y faces and kz_ratio on
+ * z faces; a_ii = sum of the cell's T, plus T_b = 2 k_i per Dirichlet (p = 0) face
+ * on x = 0 and x = nx when dirichlet_x != 0. Rows list z-, y-, x-, diagonal, x+, y+,
+ * z+ (the neighbours that exist). */
+
+/* Host pattern: row_ptr[n+1] and col_idx[nnz] (host arrays; call with col_idx = NULL
+ * first to get nnz = row_ptr[n]). */
+cpc_status cpc_tpfa_pattern(int32_t nx, int32_t ny, int32_t nz, int32_t* row_ptr, int32_t* col_idx);
+
+/* Device values of the matrix for log-permeability logk_dev[n] on the pattern whose
+ * device row pointers are row_ptr_dev; writes val_dev[nnz]. Asynchronous on hip_stream. */
+cpc_status cpc_tpfa_values(int32_t nx, int32_t ny, int32_t nz, double kz_ratio, int32_t dirichlet_x,
+                           const double* logk_dev, const int32_t* row_ptr_dev, double* val_dev, void* hip_stream);
+
+/* grad_dev[c] = dL/dlog k_c given the adjoint lam = A^{-1} dL/dx and the state x
+ * (all device FP64 arrays of length n), through the face transmissibilities.
+ * Asynchronous on hip_stream. */
+cpc_status cpc_tpfa_logk_grad(int32_t nx, int32_t ny, int32_t nz, double kz_ratio, int32_t dirichlet_x,
+                              const double* logk_dev, const double* lam_dev, const double* x_dev, double* grad_dev,
+                              void* hip_stream);
+
+/* Replace the values of the matrix that PCG multiplies by (same pattern as the setup
+ * matrix; device FP64 array of nnz entries, read at each solve, caller-owned, must
+ * stay alive) while keeping the preconditioner built at setup. NULL restores the
+ * setup matrix. A preconditioner built for a nearby matrix is still SPD, so PCG
+ * converges to the new system's solution (used for finite-difference checks). */
+cpc_status cpc_set_operator_values(cpc_handle h, const double* val_dev);
+
 /* Kernel families timed by cpc_time_kernel. */
 typedef enum {
   CPC_K_SPMV_PQ = 0,   /* PCG q = A p with <p, q> (finest level)                           */

@@ -21,7 +21,8 @@ PRECISION = {"fp64": 0, "fp32": 1}
 # every entry point declared in include/cpc.h
 EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "cpc_apply_op", "cpc_spmv",
            "cpc_hierarchy_info", "cpc_get_level", "cpc_get_prolongation", "cpc_get_ilu", "cpc_get_stats",
-           "cpc_neg_outer_on_pattern", "cpc_time_kernel", "cpc_destroy", "cpc_last_error")
+           "cpc_neg_outer_on_pattern", "cpc_time_kernel", "cpc_destroy", "cpc_last_error", "cpc_tpfa_pattern",
+           "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values")
 KERNEL = {"spmv_pq": 0, "fgs": 1, "bgs": 2, "ilu_l": 3, "ilu_u": 4, "residual": 5, "restrict": 6, "prolong": 7,
           "vcycle": 8, "precond": 9, "iteration": 10}
 
@@ -85,6 +86,14 @@ def load():
     lib.cpc_neg_outer_on_pattern.restype = I32
     lib.cpc_time_kernel.argtypes = [P, I32, I32, I32, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32)]
     lib.cpc_time_kernel.restype = I32
+    lib.cpc_tpfa_pattern.argtypes = [I32, I32, I32, P, P]
+    lib.cpc_tpfa_pattern.restype = I32
+    lib.cpc_tpfa_values.argtypes = [I32, I32, I32, D, I32, P, P, P, P]
+    lib.cpc_tpfa_values.restype = I32
+    lib.cpc_tpfa_logk_grad.argtypes = [I32, I32, I32, D, I32, P, P, P, P, P]
+    lib.cpc_tpfa_logk_grad.restype = I32
+    lib.cpc_set_operator_values.argtypes = [P, P]
+    lib.cpc_set_operator_values.restype = I32
     lib.cpc_destroy.argtypes = [P]
     lib.cpc_destroy.restype = None
     lib.cpc_last_error.argtypes = []

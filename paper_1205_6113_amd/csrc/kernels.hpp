@@ -117,4 +117,10 @@ void launch_spgemm_fill(hipStream_t s, int nrows, const int* xrp, const int* xci
                         const int* yci, const double* yv, const int* crp, int* cci, double* cv, int* overflow);
 int spgemm_table_capacity();
 
+// Two-point-flux matrix values and log-permeability gradient (tpfa.hip).
+void launch_tpfa_values(hipStream_t s, int nx, int ny, int nz, double kz, int dirichlet, const double* logk,
+                        const int* rp, double* val);
+void launch_tpfa_grad(hipStream_t s, int nx, int ny, int nz, double kz, int dirichlet, const double* logk,
+                      const double* lam, const double* x, double* g);
+
 }  // namespace cpc

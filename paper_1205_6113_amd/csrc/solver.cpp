@@ -142,6 +142,7 @@ struct cpc_solver {
   hipGraph_t graph_src[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   double* graph_x[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // x bound into each graph
   int max_nblk = 1;
+  const double* op_vals = nullptr;  // values PCG multiplies by (null: the setup matrix)
 
   ~cpc_solver() {
     for (int i = 0; i < 5; ++i) {
@@ -414,10 +415,16 @@ static int prec_to_op(int prec) {
   }
 }
 
+static MatDev pcg_operator(const cpc_solver* h) {
+  MatDev m = h->lev[0].A.mat(false);
+  if (h->op_vals) m.v = h->op_vals;
+  return m;
+}
+
 static void enqueue_iteration(cpc_solver* h, int prec, double* x) {
   int* done = &h->st->done;
   const DevCsr& A = h->lev[0].A;
-  launch_spmv_pq(h->stream, A.mat(false), h->p, h->q, h->partials, h->st, A.tpr);
+  launch_spmv_pq(h->stream, pcg_operator(h), h->p, h->q, h->partials, h->st, A.tpr);
   launch_update_xr(h->stream, h->n, x, h->r, h->p, h->q, h->partials, h->st);
   apply_op(h, prec_to_op(prec), h->r, h->z, done);
   launch_dot_rz(h->stream, h->n, h->r, h->z, h->p, h->partials, h->st, false);
@@ -504,7 +511,7 @@ static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x,
     init.maxit = maxit;
     HIPCHK(hipMemcpyAsync(h->st, &init, sizeof(init), hipMemcpyHostToDevice, h->stream));
     const DevCsr& A = h->lev[0].A;
-    launch_pcg_init(h->stream, A.mat(false), b, x, h->r, use_x0, h->partials, h->st, A.tpr);
+    launch_pcg_init(h->stream, pcg_operator(h), b, x, h->r, use_x0, h->partials, h->st, A.tpr);
     apply_op(h, prec_to_op(prec), h->r, h->z, &h->st->done);
     launch_dot_rz(h->stream, h->n, h->r, h->z, h->p, h->partials, h->st, true);
     HIPCHK(hipGetLastError());
@@ -986,6 +993,69 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
       HIPCHK(hipStreamSynchronize(h->stream));
       return set_err(CPC_E_DEVICE, "a sweep wait exceeded its bound");
     }
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_set_operator_values(cpc_handle h, const double* val_dev) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (h->op_vals != val_dev) {
+    h->op_vals = val_dev;
+    for (int i = 0; i < 5; ++i) {  // captured graphs bind the operator's values
+      if (h->graph[i]) (void)hipGraphExecDestroy(h->graph[i]);
+      if (h->graph_src[i]) (void)hipGraphDestroy(h->graph_src[i]);
+      h->graph[i] = nullptr;
+      h->graph_src[i] = nullptr;
+      h->graph_x[i] = nullptr;
+    }
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_tpfa_pattern(int32_t nx, int32_t ny, int32_t nz, int32_t* row_ptr, int32_t* col_idx) {
+  if (nx < 1 || ny < 1 || nz < 1 || !row_ptr) return set_err(CPC_E_ARG, "bad grid or null row_ptr");
+  const int64_t N = (int64_t)nx * ny * nz;
+  if (N * 7 > 2147483647LL) return set_err(CPC_E_ARG, "grid too large for int32 indices");
+  const int64_t nxy = (int64_t)nx * ny;
+  int64_t p = 0;
+  row_ptr[0] = 0;
+  for (int64_t c = 0; c < N; ++c) {
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / nxy);
+    const int64_t nb[7] = {k > 0 ? c - nxy : -1, j > 0 ? c - nx : -1, i > 0 ? c - 1 : -1, c,
+                           i < nx - 1 ? c + 1 : -1, j < ny - 1 ? c + nx : -1, k < nz - 1 ? c + nxy : -1};
+    for (int t = 0; t < 7; ++t)
+      if (nb[t] >= 0) {
+        if (col_idx) col_idx[p] = (int32_t)nb[t];
+        ++p;
+      }
+    row_ptr[c + 1] = (int32_t)p;
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_tpfa_values(int32_t nx, int32_t ny, int32_t nz, double kz_ratio, int32_t dirichlet_x,
+                           const double* logk_dev, const int32_t* row_ptr_dev, double* val_dev, void* hip_stream) {
+  if (nx < 1 || ny < 1 || nz < 1 || !logk_dev || !row_ptr_dev || !val_dev || !(kz_ratio > 0.0))
+    return set_err(CPC_E_ARG, "bad grid, null pointer or kz_ratio <= 0");
+  try {
+    launch_tpfa_values((hipStream_t)hip_stream, nx, ny, nz, kz_ratio, dirichlet_x, logk_dev, row_ptr_dev, val_dev);
+    HIPCHK(hipGetLastError());
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_tpfa_logk_grad(int32_t nx, int32_t ny, int32_t nz, double kz_ratio, int32_t dirichlet_x,
+                              const double* logk_dev, const double* lam_dev, const double* x_dev, double* grad_dev,
+                              void* hip_stream) {
+  if (nx < 1 || ny < 1 || nz < 1 || !logk_dev || !lam_dev || !x_dev || !grad_dev || !(kz_ratio > 0.0))
+    return set_err(CPC_E_ARG, "bad grid, null pointer or kz_ratio <= 0");
+  try {
+    launch_tpfa_grad((hipStream_t)hip_stream, nx, ny, nz, kz_ratio, dirichlet_x, logk_dev, lam_dev, x_dev, grad_dev);
+    HIPCHK(hipGetLastError());
   } catch (const HipError& e) {
     return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
   }
