@@ -280,11 +280,12 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepDev sw, int n, const in
     for (int lv = lb; lv < le; ++lv) {
       const int w0 = sw.wait_ptr[lv], w1 = sw.wait_ptr[lv + 1];
       if (w0 < w1) {
+        // poll with relaxed agent-scope loads; one acquire fence once the value is seen
         for (int w = w0 + tid; w < w1; w += nt) {
           const unsigned need = (unsigned)sw.wait_need[w];
           unsigned* pp = sy.progress + sw.wait_blk[w];
           long spins = 0;
-          while (__hip_atomic_load(pp, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          while (__hip_atomic_load(pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > spin_limit) {
               atomicOr(sy.err, 1u);
@@ -292,9 +293,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepDev sw, int n, const in
             }
             if ((spins & 1023) == 0 && __hip_atomic_load(sy.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
           }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       const int p0 = sw.lvl_ptr[lv], p1 = sw.lvl_ptr[lv + 1];
       for (int p = p0 + grp; p < p1; p += ngrp) {
@@ -332,8 +333,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepDev sw, int n, const in
           if (OP == SWEEP_ILU_U && out) out[i] = (XT)((double)base[i] + (double)xo);
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
+      // another block waits for this level: release the block's stores (they
+      // happen-before this point through the barrier) with the progress counter
       if (tid == 0 && sw.publish[lv])
         __hip_atomic_store(sy.progress + b, (unsigned)(lv - lb + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
