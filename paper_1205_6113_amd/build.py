@@ -29,6 +29,7 @@ DEVICE_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 SOURCES = [
     # (source, compiler, extra flags)
     ("kernels.hip", "hip", []),
+    ("sweep.hip", "hip", []),
     ("rap.hip", "hip", ["-ffp-contract=off"]),
     ("tpfa.hip", "hip", ["-ffp-contract=off"]),
     ("host_setup.cpp", "gxx", ["-ffp-contract=off"]),

@@ -88,7 +88,23 @@ void launch_update_p(hipStream_t s, int n, const double* z, double* p, PcgState*
 void launch_pcg_init(hipStream_t s, const MatDev& A, const double* b, double* x, double* r, int use_x0,
                      double* partials, PcgState* st, int tpr);
 
-// Persistent level-scheduled sweep.
+// Rows of one sweep packed in processing order (see sweep.hip).
+struct SweepPackDev {
+  const int* row;    // [n] row of the p-th processed row
+  const int* ptr;    // [n+1] entries of processed row p: [ptr[p], ptr[p+1])
+  const int* col;    // entry columns
+  const void* val;   // entry values (FP64 or FP32)
+  const void* diag;  // [n] diagonal of processed row p (unused by the ILU L solve)
+  int tpr;           // lanes per row for this sweep
+};
+
+// Persistent block-pipelined sweep over packed rows with prefetching (sweep.hip).
+void launch_sweep_packed(hipStream_t s, int op, const SweepDev& sw, const SweepPackDev& pk, int n, bool fp32,
+                         const void* f, void* x, const void* base, void* out, const SweepSync& sync,
+                         const int* done, long spin_limit);
+int sweep_max_rows_per_block();
+
+// Persistent level-scheduled sweep (CSR rows through perm).
 void launch_sweep(hipStream_t s, int op, const SweepDev& sw, const MatDev& M, const void* vals, bool fp32,
                   const void* f, void* x, const void* base, void* out, const SweepSync& sync, const int* done,
                   long spin_limit);

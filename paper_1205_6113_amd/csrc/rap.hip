@@ -150,8 +150,11 @@ void launch_spgemm_fill(hipStream_t s, int nrows, const int* xrp, const int* xci
   const size_t lds = (sizeof(double) * 2 + sizeof(int) * 2) * kCap;
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)spgemm_fill_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr_set = true;
+    if (hipFuncSetAttribute((const void*)spgemm_fill_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
+        hipSuccess)
+      attr_set = true;
+    else
+      (void)hipGetLastError();
   }
   const int grid = nrows < 2048 ? nrows : 2048;
   spgemm_fill_kernel<<<grid, kNT, lds, s>>>(nrows, xrp, xci, xv, yrp, yci, yv, crp, cci, cv, overflow);

@@ -106,6 +106,7 @@ struct Level {
   std::vector<int> cf;
   DevCsr A, P, R;
   DevSweepSched lower, upper;
+  SweepPackDev fgs{}, bgs{};  // forward GS (lower entries), backward GS (all off-diagonal entries)
   void* f = nullptr;  // level vectors (coarse levels), element type = preconditioner precision
   void* u = nullptr;
   void* r = nullptr;
@@ -126,6 +127,7 @@ struct cpc_solver {
   std::vector<double> lu_host;
   double* lu = nullptr;
   float* lu32 = nullptr;
+  cpc::SweepPackDev ilu_l{}, ilu_u{};  // ILU(0) L (lower entries of LU) and U (upper entries, diagonal)
   // PCG vectors
   double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   // preconditioner temporaries on the finest level (precision of the preconditioner)
@@ -279,6 +281,71 @@ static void spmv_or_throw(cpc_solver* h, const MatDev& A, int mode, const void* 
     throw HipError{hipErrorInvalidValue, "unsupported SpMV precision combination"};
 }
 
+// Pack the rows a sweep touches in its processing order. kind 0: entries left of the
+// diagonal; 1: right of the diagonal; 2: every off-diagonal entry. share: reuse the
+// row/ptr/col arrays of a pack with the same schedule and kind (values differ).
+static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vector<double>& vals,
+                               const SweepSchedule& s, int kind, const SweepPackDev* share) {
+  SweepPackDev pk{};
+  const int n = a.n;
+  std::vector<int> ptr(n + 1, 0);
+  std::vector<double> diag(n, 1.0);
+  for (int p = 0; p < n; ++p) {
+    const int i = s.perm[p];
+    int c = 0;
+    for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
+      const int j = a.ci[q];
+      if (j == i) diag[p] = vals[q];
+      else if ((kind == 0 && j < i) || (kind == 1 && j > i) || kind == 2) ++c;
+    }
+    ptr[p + 1] = ptr[p] + c;
+  }
+  std::vector<int> col((size_t)ptr[n]);
+  std::vector<double> v((size_t)ptr[n]);
+  for (int p = 0; p < n; ++p) {
+    const int i = s.perm[p];
+    int w = ptr[p];
+    for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
+      const int j = a.ci[q];
+      if (j == i) continue;
+      if ((kind == 0 && j < i) || (kind == 1 && j > i) || kind == 2) {
+        col[w] = j;
+        v[w] = vals[q];
+        ++w;
+      }
+    }
+  }
+  if (share) {
+    pk.row = share->row;
+    pk.ptr = share->ptr;
+    pk.col = share->col;
+  } else {
+    pk.row = dupload(s.perm, h->owned, h->stream);
+    pk.ptr = dupload(ptr, h->owned, h->stream);
+    pk.col = dupload(col, h->owned, h->stream);
+  }
+  if (h->f32) {
+    std::vector<float> v32(v.begin(), v.end()), d32(diag.begin(), diag.end());
+    pk.val = dupload(v32, h->owned, h->stream);
+    pk.diag = dupload(d32, h->owned, h->stream);
+  } else {
+    pk.val = dupload(v, h->owned, h->stream);
+    pk.diag = dupload(diag, h->owned, h->stream);
+  }
+  const double avg = n ? (double)ptr[n] / n : 0.0;
+  int t = 1;
+  while (t < 64 && t * 6 < avg) t <<= 1;
+  pk.tpr = t;
+  return pk;
+}
+
+static void run_sweep(cpc_solver* h, int op, const DevSweepSched& sch, const SweepPackDev& pk, const void* f,
+                      void* x, const void* base, void* out, const int* done) {
+  SweepDev sd = sch.d;
+  sd.tpr = pk.tpr;
+  launch_sweep_packed(h->stream, op, sd, pk, sd.n, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
+}
+
 static size_t esz_of(const cpc_solver* h) { return h->f32 ? sizeof(float) : sizeof(double); }
 
 static void* valloc(cpc_solver* h, int n) {
@@ -299,7 +366,7 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
   Level& C = h->lev[d + 1];
   const MatDev A = L.A.mat(f32);
   // (1) pre-smoothing from zero: u = (D+L)^{-1} f
-  launch_sweep(h->stream, SWEEP_FGS0, L.lower.d, A, A.v, f32, f, u, nullptr, nullptr, h->sync, done, h->spin_limit);
+  run_sweep(h, SWEEP_FGS0, L.lower, L.fgs, f, u, nullptr, nullptr, done);
   // (2a) f_c = R (f - A u)
   spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);
   spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
@@ -308,19 +375,14 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
   // (2c) u += P e
   spmv_or_throw(h, L.P.mat(f32), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);
   // (3) post-smoothing: one backward Gauss-Seidel sweep in place (S_l^T)
-  launch_sweep(h->stream, SWEEP_BGS_IP, L.upper.d, A, A.v, f32, f, u, nullptr, nullptr, h->sync, done,
-               h->spin_limit);
+  run_sweep(h, SWEEP_BGS_IP, L.upper, L.bgs, f, u, nullptr, nullptr, done);
 }
 
 // z = (LU)^{-1} f (out = nullptr) or out = base + (LU)^{-1} f
 static void ilu_apply(cpc_solver* h, const void* f, void* w, const void* base, void* out, const int* done) {
   Level& L = h->lev[0];
-  const bool f32 = h->f32;
-  const MatDev M = L.A.mat(f32);
-  const void* vals = f32 ? (const void*)h->lu32 : (const void*)h->lu;
-  launch_sweep(h->stream, SWEEP_ILU_L, L.lower.d, M, vals, f32, f, h->y, nullptr, nullptr, h->sync, done,
-               h->spin_limit);
-  launch_sweep(h->stream, SWEEP_ILU_U, L.upper.d, M, vals, f32, h->y, w, base, out, h->sync, done, h->spin_limit);
+  run_sweep(h, SWEEP_ILU_L, L.lower, h->ilu_l, f, h->y, nullptr, nullptr, done);
+  run_sweep(h, SWEEP_ILU_U, L.upper, h->ilu_u, h->y, w, base, out, done);
 }
 
 // res = r - A u with FP64 A and FP64 r (outer residual of Algorithm 2.1)
@@ -387,14 +449,13 @@ static void apply_op(cpc_solver* h, int op, const double* r, double* z, const in
     case CPC_OP_BGS: {
       Level& L = h->lev[0];
       const MatDev A = L.A.mat(f32);
+      (void)A;
       if (op == CPC_OP_FGS) {
-        launch_sweep(h->stream, SWEEP_FGS0, L.lower.d, A, A.v, f32, rin, h->u1, nullptr, nullptr, h->sync, done,
-                     h->spin_limit);
+        run_sweep(h, SWEEP_FGS0, L.lower, L.fgs, rin, h->u1, nullptr, nullptr, done);
       } else {
         // (D+U)^{-1} f = one backward sweep in place from a zero start
         launch_vec(h->stream, 3, n, nullptr, false, nullptr, false, h->u1, f32, done);
-        launch_sweep(h->stream, SWEEP_BGS_IP, L.upper.d, A, A.v, f32, rin, h->u1, nullptr, nullptr, h->sync, done,
-                     h->spin_limit);
+        run_sweep(h, SWEEP_BGS_IP, L.upper, L.bgs, rin, h->u1, nullptr, nullptr, done);
       }
       launch_vec(h->stream, 2, n, h->u1, f32, nullptr, false, z, false, done);
       break;
@@ -717,6 +778,12 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
       SweepSchedule up = build_sweep(L.A_host, false, R);
       upload_sweep(h.get(), lo, L.lower, avg_half);
       upload_sweep(h.get(), up, L.upper, avg_half);
+      L.fgs = build_pack(h.get(), L.A_host, L.A_host.v, lo, 0, nullptr);
+      L.bgs = build_pack(h.get(), L.A_host, L.A_host.v, up, 2, nullptr);
+      if (d == 0) {
+        h->ilu_l = build_pack(h.get(), L.A_host, h->lu_host, lo, 0, &L.fgs);
+        h->ilu_u = build_pack(h.get(), L.A_host, h->lu_host, up, 1, nullptr);
+      }
       if (d > 0) {
         L.f = valloc(h.get(), L.A.n);
         L.u = valloc(h.get(), L.A.n);
@@ -914,20 +981,16 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         launch_spmv_pq(h->stream, L.A.mat(false), h->p, h->q, h->partials, h->st, L.A.tpr);
         break;
       case CPC_K_FGS:
-        launch_sweep(h->stream, SWEEP_FGS0, L.lower.d, A, A.v, f32, f, u, nullptr, nullptr, h->sync, nullptr,
-                     h->spin_limit);
+        run_sweep(h, SWEEP_FGS0, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
         break;
       case CPC_K_BGS:
-        launch_sweep(h->stream, SWEEP_BGS_IP, L.upper.d, A, A.v, f32, f, u, nullptr, nullptr, h->sync, nullptr,
-                     h->spin_limit);
+        run_sweep(h, SWEEP_BGS_IP, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
         break;
       case CPC_K_ILU_L:
-        launch_sweep(h->stream, SWEEP_ILU_L, L.lower.d, A, f32 ? (const void*)h->lu32 : (const void*)h->lu, f32,
-                     h->res, h->y, nullptr, nullptr, h->sync, nullptr, h->spin_limit);
+        run_sweep(h, SWEEP_ILU_L, L.lower, h->ilu_l, h->res, h->y, nullptr, nullptr, nullptr);
         break;
       case CPC_K_ILU_U:
-        launch_sweep(h->stream, SWEEP_ILU_U, L.upper.d, A, f32 ? (const void*)h->lu32 : (const void*)h->lu, f32,
-                     h->y, h->w, h->u1, h->u2, h->sync, nullptr, h->spin_limit);
+        run_sweep(h, SWEEP_ILU_U, L.upper, h->ilu_u, h->y, h->w, h->u1, h->u2, nullptr);
         break;
       case CPC_K_RESIDUAL:
         spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, nullptr);
