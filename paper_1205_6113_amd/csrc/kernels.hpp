@@ -88,6 +88,40 @@ void launch_update_p(hipStream_t s, int n, const double* z, double* p, PcgState*
 void launch_pcg_init(hipStream_t s, const MatDev& A, const double* b, double* x, double* r, int use_x0,
                      double* partials, PcgState* st, int tpr);
 
+// Per-system PCG scalars of a batch of independent systems (batch.hip). Rows of the
+// concatenated vectors are cut into chunks that never straddle two systems.
+struct BatchDev {
+  int nsys, nchunks;
+  const int* chunk_sys;  // [nchunks] system of each chunk
+  const int* chunk_row;  // [nchunks+1] first row of each chunk
+  const int* sys_chunk;  // [nsys+1] chunk range of each system
+  double* partials;      // [4 * nchunks] one partial per chunk and reduction slot
+  unsigned* cnt;         // [4 * nsys] arrival counters (reset by the last chunk)
+  double *rz, *pq, *alpha, *beta, *rr, *bb, *relres;  // [nsys]
+  int* iters;            // [nsys]
+  int* done;             // [nsys] 0 running, else a DONE_* code
+  const double* tol_dev; // relative residual tolerance (device scalar)
+  const int* maxit_dev;  // iteration cap (device scalar)
+};
+
+// Dense solves e = inv f on segments of a level vector (coarsest systems of a depth).
+struct DenseListDev {
+  int nblk;               // workgroups (4 rows each)
+  const int* blk_entry;   // [nblk] entry of each workgroup
+  const int* blk_row0;    // [nblk] first row of each workgroup within its entry
+  const int* n;           // [entries] rows of each system's coarsest matrix
+  const int* off;         // [entries] offset of its segment in the level vector
+  const long* inv_off;    // [entries] offset of its row-major inverse in inv
+  const double* inv;      // concatenated inverses (FP64)
+};
+
+void launch_bspmv_pq(hipStream_t s, const BatchDev& bd, const MatDev& A, const double* p, double* q, int tpr);
+void launch_bupdate_xr(hipStream_t s, const BatchDev& bd, double* x, double* r, const double* p, const double* q);
+void launch_bdot_rz(hipStream_t s, const BatchDev& bd, const double* r, const double* z, double* p, bool first);
+void launch_bupdate_p(hipStream_t s, const BatchDev& bd, const double* z, double* p);
+void launch_binit(hipStream_t s, const BatchDev& bd, const double* b, double* x, double* r);
+void launch_bdense(hipStream_t s, const DenseListDev& dl, const void* f, void* e, bool fp32, const int* done);
+
 // Rows of one sweep packed in processing order (see sweep.hip).
 struct SweepPackDev {
   const int* row;    // [n] row of the p-th processed row

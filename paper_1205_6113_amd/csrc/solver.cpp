@@ -107,6 +107,10 @@ struct Level {
   DevCsr A, P, R;
   DevSweepSched lower, upper;
   SweepPackDev fgs{}, bgs{};  // forward GS (lower entries), backward GS (all off-diagonal entries)
+  int nS = 0;                 // leading rows that are smoothed (systems not at their coarsest level)
+  int64_t nnzS = 0;           // nonzeros of those rows
+  DenseListDev dense{};       // systems whose coarsest level is this one (exact solve)
+  std::vector<int> dense_n;   // their sizes (host)
   void* f = nullptr;  // level vectors (coarse levels), element type = preconditioner precision
   void* u = nullptr;
   void* r = nullptr;
@@ -122,8 +126,6 @@ struct cpc_solver {
   int64_t nnz = 0;
   bool f32 = false;  // preconditioner precision
   std::vector<cpc::Level> lev;
-  int n0 = 0;
-  double* coarse_inv = nullptr;
   std::vector<double> lu_host;
   double* lu = nullptr;
   float* lu32 = nullptr;
@@ -158,30 +160,67 @@ struct cpc_solver {
 
 namespace cpc {
 
-static void upload_csr(cpc_solver* h, const HostCsr& a, DevCsr& d, bool with_dpos) {
+static void upload_csr(cpc_solver* h, const HostCsr& a, DevCsr& d, bool with_dpos, std::vector<void*>* into = nullptr,
+                       bool with_f32 = true) {
+  std::vector<void*>& own = into ? *into : h->owned;
   d.n = a.n;
   d.ncols = a.ncols;
   d.nnz = a.nnz();
-  d.rp = dupload(a.rp, h->owned, h->stream);
-  d.ci = dupload(a.ci, h->owned, h->stream);
-  d.v = dupload(a.v, h->owned, h->stream);
+  d.rp = dupload(a.rp, own, h->stream);
+  d.ci = dupload(a.ci, own, h->stream);
+  d.v = dupload(a.v, own, h->stream);
   if (with_dpos) {
     std::vector<int> dp(a.n, -1);
     for (int i = 0; i < a.n; ++i)
       for (int k = a.rp[i]; k < a.rp[i + 1]; ++k)
         if (a.ci[k] == i) dp[i] = k;
-    d.dpos = dupload(dp, h->owned, h->stream);
+    d.dpos = dupload(dp, own, h->stream);
   }
   d.tpr = pick_tpr(a.n ? (double)d.nnz / a.n : 1.0);
-  if (h->f32) {
-    d.v32 = dalloc<float>((size_t)d.nnz, h->owned);
+  if (h->f32 && with_f32) {
+    d.v32 = dalloc<float>((size_t)d.nnz, own);
     launch_to_f32(h->stream, d.nnz, d.v, d.v32);
   }
 }
 
+static HostCsr leading_rows(const HostCsr& a, int nrows) {
+  HostCsr t;
+  t.n = nrows;
+  t.ncols = nrows;
+  t.rp.assign(a.rp.begin(), a.rp.begin() + nrows + 1);
+  t.ci.assign(a.ci.begin(), a.ci.begin() + t.rp[nrows]);
+  t.v.assign(a.v.begin(), a.v.begin() + t.rp[nrows]);
+  return t;
+}
+
+static DenseListDev upload_dense_list(cpc_solver* h, const std::vector<int>& off, const std::vector<int>& nn,
+                                      const std::vector<const std::vector<double>*>& invs) {
+  DenseListDev dl{};
+  if (off.empty()) return dl;
+  std::vector<int> blk_entry, blk_row0;
+  std::vector<long> inv_off;
+  std::vector<double> inv_all;
+  for (size_t e = 0; e < off.size(); ++e) {
+    inv_off.push_back((long)inv_all.size());
+    inv_all.insert(inv_all.end(), invs[e]->begin(), invs[e]->end());
+    for (int r = 0; r < nn[e]; r += 4) {
+      blk_entry.push_back((int)e);
+      blk_row0.push_back(r);
+    }
+  }
+  dl.nblk = (int)blk_entry.size();
+  dl.blk_entry = dupload(blk_entry, h->owned, h->stream);
+  dl.blk_row0 = dupload(blk_row0, h->owned, h->stream);
+  dl.n = dupload(nn, h->owned, h->stream);
+  dl.off = dupload(off, h->owned, h->stream);
+  dl.inv_off = dupload(inv_off, h->owned, h->stream);
+  dl.inv = dupload(inv_all, h->owned, h->stream);
+  return dl;
+}
+
 // Galerkin product on the GPU: C = X * Y with the canonical order (rap.hip).
 static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncols, HostCsr& C_host, DevCsr& C,
-                       std::string* msg) {
+                       std::string* msg, std::vector<void*>& keep) {
   const int nrows = X.n;
   std::vector<void*> tmp;
   int* counts = dalloc<int>(nrows, tmp);
@@ -217,9 +256,9 @@ static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncol
         C.n = nrows;
         C.ncols = ncols;
         C.nnz = tot;
-        C.rp = dupload(C_host.rp, h->owned, h->stream);
-        C.ci = dalloc<int>((size_t)tot, h->owned);
-        C.v = dalloc<double>((size_t)tot, h->owned);
+        C.rp = dupload(C_host.rp, keep, h->stream);
+        C.ci = dalloc<int>((size_t)tot, keep);
+        C.v = dalloc<double>((size_t)tot, keep);
         launch_spgemm_fill(h->stream, nrows, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v, ovf);
         HIPCHK(hipGetLastError());
         C_host.ci.resize(tot);
@@ -356,26 +395,209 @@ static void* valloc(cpc_solver* h, int n) {
 // ---------------------------------------------------------------------------
 // Preconditioner application (all asynchronous on h->stream).
 
+// One system's hierarchy, built on its own (host splitting and interpolation, GPU
+// Galerkin products in temporary device buffers).
+struct SysHier {
+  std::vector<HostCsr> A;             // A_l for depth 0 .. L-1
+  std::vector<HostCsr> P;             // P for depth d -> d+1
+  std::vector<std::vector<int>> cf;   // C/F splitting of each split depth
+  std::vector<double> lu;             // ILU(0) values on A[0]
+  std::vector<double> inv;            // dense inverse of A[L-1]
+};
+
+static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::string* msg) {
+  std::vector<void*> tmp;
+  int status = CPC_OK;
+  try {
+    DevCsr Ad;
+    upload_csr(h, S.A[0], Ad, false, &tmp, false);
+    for (int d = 0;; ++d) {
+      const HostCsr& A = S.A[d];
+      if (A.n <= o.max_coarse || d + 1 >= o.max_levels) break;
+      std::vector<int> cf;
+      const int nc = rs_coarsen(A, o.theta, cf);
+      if (nc == 0 || (double)nc > 0.9 * (double)A.n) break;
+      HostCsr P;
+      rs_interpolation(A, o.theta, cf, nc, P);
+      HostCsr R = transpose(P);
+      DevCsr Pd, Rd, APd, Acd;
+      upload_csr(h, P, Pd, false, &tmp, false);
+      upload_csr(h, R, Rd, false, &tmp, false);
+      HostCsr AP, Ac;
+      if (!gpu_spgemm(h, Ad, Pd, nc, AP, APd, msg, tmp) || !gpu_spgemm(h, Rd, APd, nc, Ac, Acd, msg, tmp)) {
+        status = CPC_E_NOMEM;
+        break;
+      }
+      for (int i = 0; i < Ac.n; ++i) {
+        bool diag = false;
+        for (int k = Ac.rp[i]; k < Ac.rp[i + 1]; ++k) diag |= (Ac.ci[k] == i);
+        if (!diag) {
+          if (msg) *msg = "coarse matrix lost its diagonal";
+          status = CPC_E_NOT_SPD;
+          break;
+        }
+      }
+      if (status != CPC_OK) break;
+      S.cf.push_back(std::move(cf));
+      S.P.push_back(std::move(P));
+      S.A.push_back(std::move(Ac));
+      Ad = Acd;
+    }
+    if (status == CPC_OK) {
+      const HostCsr& Lc = S.A.back();
+      if (Lc.n > 8192) {
+        if (msg) *msg = "coarsening stalled with " + std::to_string(Lc.n) + " rows";
+        status = CPC_E_NOMEM;
+      } else {
+        status = dense_spd_inverse(Lc, S.inv, msg);
+      }
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (...) {
+    for (void* p : tmp) (void)hipFree(p);
+    throw;
+  }
+  for (void* p : tmp) (void)hipFree(p);
+  return status;
+}
+
+// Concatenate the systems' hierarchies depth by depth and upload them. At depth d
+// the level vector holds, in this order, the systems that are smoothed at d (still
+// coarsened further) and then the systems whose coarsest level is d; matrices are
+// block diagonal, so the leading smoothed rows couple only among themselves.
+// Depth 0 keeps the callers' system order (every system of a batch has >= 2 levels).
+static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_options& o, std::string* msg) {
+  const int ns = (int)sys.size();
+  int D = 0;
+  for (auto& S : sys) D = std::max(D, (int)S.A.size());
+  if (ns > 1)
+    for (int s = 0; s < ns; ++s)
+      if (sys[s].A.size() < 2) {
+        if (msg) *msg = "system " + std::to_string(s) + " of the batch has one level (n <= max_coarse)";
+        return CPC_E_ARG;
+      }
+  std::vector<std::vector<int>> order(D), off(D, std::vector<int>(ns, -1));
+  std::vector<int> ntot(D, 0), nS(D, 0);
+  for (int d = 0; d < D; ++d) {
+    for (int s = 0; s < ns; ++s)
+      if (d + 1 < (int)sys[s].A.size()) order[d].push_back(s);
+    const int nsm = (int)order[d].size();
+    for (int s = 0; s < ns; ++s)
+      if (d + 1 == (int)sys[s].A.size()) order[d].push_back(s);
+    int o_ = 0;
+    for (int k = 0; k < (int)order[d].size(); ++k) {
+      const int s = order[d][k];
+      off[d][s] = o_;
+      o_ += sys[s].A[d].n;
+      if (k < nsm) nS[d] = o_;
+    }
+    ntot[d] = o_;
+  }
+  h->lev.assign(D, Level());
+  h->lu_host.clear();
+  for (int s = 0; s < ns; ++s) h->lu_host.insert(h->lu_host.end(), sys[s].lu.begin(), sys[s].lu.end());
+  for (int d = 0; d < D; ++d) {
+    Level& L = h->lev[d];
+    // block-diagonal matrix of depth d
+    HostCsr& A = L.A_host;
+    A.n = A.ncols = ntot[d];
+    A.rp.assign(1, 0);
+    for (int s : order[d]) {
+      const HostCsr& a = sys[s].A[d];
+      const int o_ = off[d][s];
+      const int base = A.rp.back();
+      for (int i = 0; i < a.n; ++i) A.rp.push_back(base + a.rp[i + 1]);
+      for (int c : a.ci) A.ci.push_back(c + o_);
+      A.v.insert(A.v.end(), a.v.begin(), a.v.end());
+    }
+    L.nS = nS[d];
+    upload_csr(h, A, L.A, true);
+    L.nnzS = A.rp[L.nS];
+    // prolongation from depth d+1 (rows: smoothed systems at d; columns: depth d+1 layout)
+    if (d + 1 < D && L.nS > 0) {
+      HostCsr& P = L.P_host;
+      P.n = L.nS;
+      P.ncols = ntot[d + 1];
+      P.rp.assign(1, 0);
+      L.cf.clear();
+      for (int s : order[d]) {
+        if (d + 1 >= (int)sys[s].A.size()) continue;
+        const HostCsr& p = sys[s].P[d];
+        const int base = P.rp.back();
+        for (int i = 0; i < p.n; ++i) P.rp.push_back(base + p.rp[i + 1]);
+        for (int c : p.ci) P.ci.push_back(c + off[d + 1][s]);
+        P.v.insert(P.v.end(), p.v.begin(), p.v.end());
+        L.cf.insert(L.cf.end(), sys[s].cf[d].begin(), sys[s].cf[d].end());
+      }
+      HostCsr R = transpose(P);
+      upload_csr(h, P, L.P, false);
+      upload_csr(h, R, L.R, false);
+    }
+    // exact solves of the systems that bottom out here
+    {
+      std::vector<int> doff, dn;
+      std::vector<const std::vector<double>*> invs;
+      for (int s : order[d])
+        if (d + 1 == (int)sys[s].A.size()) {
+          doff.push_back(off[d][s]);
+          dn.push_back(sys[s].A[d].n);
+          invs.push_back(&sys[s].inv);
+        }
+      L.dense = upload_dense_list(h, doff, dn, invs);
+      L.dense_n = dn;
+    }
+    // sweep schedules and packed rows: the smoothed rows (all rows at depth 0, for ILU(0))
+    const int rows = (d == 0) ? ntot[0] : L.nS;
+    if (rows > 0) {
+      HostCsr sub = (rows == ntot[d]) ? A : leading_rows(A, rows);
+      const double avg_half = 0.5 * ((double)sub.nnz() / std::max(1, rows) - 1.0) + 1.0;
+      const int Rb = o.sweep_block_rows > 0 ? std::min(o.sweep_block_rows, 8192) : choose_block_rows(rows, avg_half);
+      SweepSchedule lo = build_sweep(sub, true, Rb);
+      SweepSchedule up = build_sweep(sub, false, Rb);
+      upload_sweep(h, lo, L.lower, avg_half);
+      upload_sweep(h, up, L.upper, avg_half);
+      L.fgs = build_pack(h, sub, sub.v, lo, 0, nullptr);
+      L.bgs = build_pack(h, sub, sub.v, up, 2, nullptr);
+      if (d == 0) {
+        h->ilu_l = build_pack(h, sub, h->lu_host, lo, 0, &L.fgs);
+        h->ilu_u = build_pack(h, sub, h->lu_host, up, 1, nullptr);
+      }
+      L.r = valloc(h, rows);
+    }
+    if (d > 0) {
+      L.f = valloc(h, ntot[d]);
+      L.u = valloc(h, ntot[d]);
+    }
+  }
+  return CPC_OK;
+}
+
+static MatDev smoothed(const DevCsr& A, int nS, bool f32) {
+  MatDev m = A.mat(f32);
+  m.n = nS;
+  return m;
+}
+
 static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done) {
   Level& L = h->lev[d];
   const bool f32 = h->f32;
-  if (d == (int)h->lev.size() - 1) {
-    launch_dense_matvec(h->stream, L.A.n, h->coarse_inv, f, f32, u, f32, done);
-    return;
+  if (L.nS > 0 && d + 1 < (int)h->lev.size()) {
+    Level& C = h->lev[d + 1];
+    const MatDev A = smoothed(L.A, L.nS, f32);
+    // (1) pre-smoothing from zero: u = (D+L)^{-1} f
+    run_sweep(h, SWEEP_FGS0, L.lower, L.fgs, f, u, nullptr, nullptr, done);
+    // (2a) f_c = R (f - A u)
+    spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);
+    spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
+    // (2b) coarse correction
+    vcycle(h, d + 1, C.f, C.u, done);
+    // (2c) u += P e
+    spmv_or_throw(h, L.P.mat(f32), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);
+    // (3) post-smoothing: one backward Gauss-Seidel sweep in place (S_l^T)
+    run_sweep(h, SWEEP_BGS_IP, L.upper, L.bgs, f, u, nullptr, nullptr, done);
   }
-  Level& C = h->lev[d + 1];
-  const MatDev A = L.A.mat(f32);
-  // (1) pre-smoothing from zero: u = (D+L)^{-1} f
-  run_sweep(h, SWEEP_FGS0, L.lower, L.fgs, f, u, nullptr, nullptr, done);
-  // (2a) f_c = R (f - A u)
-  spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);
-  spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
-  // (2b) coarse correction
-  vcycle(h, d + 1, C.f, C.u, done);
-  // (2c) u += P e
-  spmv_or_throw(h, L.P.mat(f32), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);
-  // (3) post-smoothing: one backward Gauss-Seidel sweep in place (S_l^T)
-  run_sweep(h, SWEEP_BGS_IP, L.upper, L.bgs, f, u, nullptr, nullptr, done);
+  // systems whose coarsest level is this one: e = A_0^{-1} f (FP64 inverse)
+  if (L.dense.nblk > 0) launch_bdense(h->stream, L.dense, f, u, f32, done);
 }
 
 // z = (LU)^{-1} f (out = nullptr) or out = base + (LU)^{-1} f
@@ -498,18 +720,20 @@ static double vcycle_bytes(const cpc_solver* h) {
   const double vb = h->f32 ? 4.0 : 8.0;           // vector element
   const double mb = h->f32 ? 8.0 : 12.0;          // matrix entry (value + column)
   double b = 0.0;
-  for (size_t d = 0; d + 1 < h->lev.size(); ++d) {
-    const double nz = (double)h->lev[d].A.nnz, n = h->lev[d].A.n, nc = h->lev[d + 1].A.n;
-    const double p = (double)h->lev[d].P.nnz;
-    const double half = 0.5 * (nz - n);
-    b += (half + n) * mb + 4.0 * n + 3.0 * vb * n;          // forward GS from zero
-    b += nz * mb + 4.0 * n + 3.0 * vb * n;                  // residual
-    b += p * mb + 4.0 * nc + vb * n + vb * nc;              // restriction
-    b += p * mb + 4.0 * n + 2.0 * vb * n + vb * nc;         // prolongation + correction
-    b += nz * mb + 4.0 * n + 3.0 * vb * n;                  // backward GS in place
+  for (size_t d = 0; d < h->lev.size(); ++d) {
+    const Level& L = h->lev[d];
+    if (L.nS > 0 && d + 1 < h->lev.size()) {
+      const double nz = (double)L.nnzS, n = L.nS, nc = h->lev[d + 1].A.n;
+      const double p = (double)L.P.nnz;
+      const double half = 0.5 * (nz - n);
+      b += (half + n) * mb + 4.0 * n + 3.0 * vb * n;          // forward GS from zero
+      b += nz * mb + 4.0 * n + 3.0 * vb * n;                  // residual
+      b += p * mb + 4.0 * nc + vb * n + vb * nc;              // restriction
+      b += p * mb + 4.0 * n + 2.0 * vb * n + vb * nc;         // prolongation + correction
+      b += nz * mb + 4.0 * n + 3.0 * vb * n;                  // backward GS in place
+    }
+    for (int n0 : L.dense_n) b += 8.0 * n0 * n0 + 2.0 * vb * n0;  // exact coarsest solves
   }
-  const double n0 = h->lev.back().A.n;
-  b += 8.0 * n0 * n0 + 2.0 * vb * n0;
   return b;
 }
 
@@ -518,7 +742,8 @@ static double kernel_bytes(const cpc_solver* h, int kernel, int d) {
   const double vb = h->f32 ? 4.0 : 8.0;
   const double mb = h->f32 ? 8.0 : 12.0;
   const Level& L = h->lev[d];
-  const double nz = (double)L.A.nnz, n = L.A.n;
+  const bool fine = (kernel == CPC_K_SPMV_PQ || kernel == CPC_K_ILU_L || kernel == CPC_K_ILU_U);
+  const double nz = fine ? (double)L.A.nnz : (double)L.nnzS, n = fine ? (double)L.A.n : (double)L.nS;
   const double half = 0.5 * (nz - n);
   const double nc = (d + 1 < (int)h->lev.size()) ? (double)h->lev[d + 1].A.n : 0.0;
   const double p = (double)L.P.nnz;
@@ -703,16 +928,17 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
   h->f32 = (o.precision == CPC_FP32_PRECOND);
   try {
     // host-only work first: the input contract and ILU(0) are decided before any GPU call
-    h->lev.emplace_back();
+    std::vector<SysHier> sys(1);
     {
-      HostCsr& A0 = h->lev[0].A_host;
+      HostCsr A0;
       A0.n = n;
       A0.ncols = n;
       A0.rp.assign(row_ptr, row_ptr + n + 1);
       A0.ci.assign(col_idx, col_idx + row_ptr[n]);
       A0.v.assign(val, val + row_ptr[n]);
+      sys[0].A.push_back(std::move(A0));
     }
-    int st = ilu0_factor(h->lev[0].A_host, h->lu_host, &msg);
+    int st = ilu0_factor(sys[0].A[0], sys[0].lu, &msg);
     if (st != CPC_OK) return set_err((cpc_status)st, msg);
     if (hip_stream) {
       h->stream = (hipStream_t)hip_stream;
@@ -720,81 +946,11 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
       HIPCHK(hipStreamCreate(&h->stream));
       h->own_stream = true;
     }
-    upload_csr(h.get(), h->lev[0].A_host, h->lev[0].A, true);
-    // AMG SETUP
-    for (int d = 0;; ++d) {
-      Level& L = h->lev[d];
-      if (L.A_host.n <= o.max_coarse || d + 1 >= o.max_levels) break;
-      std::vector<int> cf;
-      const int nc = rs_coarsen(L.A_host, o.theta, cf);
-      if (nc == 0 || (double)nc > 0.9 * (double)L.A_host.n) break;
-      L.cf = cf;
-      rs_interpolation(L.A_host, o.theta, cf, nc, L.P_host);
-      HostCsr R_host = transpose(L.P_host);
-      upload_csr(h.get(), L.P_host, L.P, false);
-      upload_csr(h.get(), R_host, L.R, false);
-      // Galerkin: A P, then R (A P)
-      HostCsr AP_host;
-      DevCsr AP;
-      if (!gpu_spgemm(h.get(), L.A, L.P, nc, AP_host, AP, &msg)) return set_err(CPC_E_NOMEM, msg);
-      h->lev.emplace_back();
-      Level& C = h->lev[d + 1];
-      DevCsr Ac;
-      if (!gpu_spgemm(h.get(), h->lev[d].R, AP, nc, C.A_host, Ac, &msg)) return set_err(CPC_E_NOMEM, msg);
-      C.A = Ac;
-      {
-        std::vector<int> dp(C.A_host.n, -1);
-        for (int i = 0; i < C.A_host.n; ++i)
-          for (int k = C.A_host.rp[i]; k < C.A_host.rp[i + 1]; ++k)
-            if (C.A_host.ci[k] == i) dp[i] = k;
-        for (int i = 0; i < C.A_host.n; ++i)
-          if (dp[i] < 0) return set_err(CPC_E_NOT_SPD, "coarse matrix lost its diagonal");
-        C.A.dpos = dupload(dp, h->owned, h->stream);
-        C.A.tpr = pick_tpr(C.A.n ? (double)C.A.nnz / C.A.n : 1.0);
-        if (h->f32) {
-          C.A.v32 = dalloc<float>((size_t)C.A.nnz, h->owned);
-          launch_to_f32(h->stream, C.A.nnz, C.A.v, C.A.v32);
-        }
-      }
-    }
-    // coarsest level: dense inverse (FP64)
-    {
-      Level& Lc = h->lev.back();
-      h->n0 = Lc.A_host.n;
-      if (h->n0 > 8192) return set_err(CPC_E_NOMEM, "coarsening stalled with " + std::to_string(h->n0) + " rows");
-      std::vector<double> inv;
-      st = dense_spd_inverse(Lc.A_host, inv, &msg);
-      if (st != CPC_OK) return set_err((cpc_status)st, msg);
-      h->coarse_inv = dupload(inv, h->owned, h->stream);
-    }
-    // sweep schedules for every smoothed level (and ILU on the finest)
-    for (size_t d = 0; d < h->lev.size(); ++d) {
-      Level& L = h->lev[d];
-      const bool smoothed = (d + 1 < h->lev.size()) || d == 0;
-      if (!smoothed) continue;
-      const double avg_half = 0.5 * ((double)L.A.nnz / std::max(1, L.A.n) - 1.0) + 1.0;
-      const int R = o.sweep_block_rows > 0 ? std::min(o.sweep_block_rows, 8192) : choose_block_rows(L.A.n, avg_half);
-      SweepSchedule lo = build_sweep(L.A_host, true, R);
-      SweepSchedule up = build_sweep(L.A_host, false, R);
-      upload_sweep(h.get(), lo, L.lower, avg_half);
-      upload_sweep(h.get(), up, L.upper, avg_half);
-      L.fgs = build_pack(h.get(), L.A_host, L.A_host.v, lo, 0, nullptr);
-      L.bgs = build_pack(h.get(), L.A_host, L.A_host.v, up, 2, nullptr);
-      if (d == 0) {
-        h->ilu_l = build_pack(h.get(), L.A_host, h->lu_host, lo, 0, &L.fgs);
-        h->ilu_u = build_pack(h.get(), L.A_host, h->lu_host, up, 1, nullptr);
-      }
-      if (d > 0) {
-        L.f = valloc(h.get(), L.A.n);
-        L.u = valloc(h.get(), L.A.n);
-      }
-      L.r = valloc(h.get(), L.A.n);
-    }
-    if (h->lev.size() > 1) {
-      Level& Lc = h->lev.back();
-      Lc.f = valloc(h.get(), Lc.A.n);
-      Lc.u = valloc(h.get(), Lc.A.n);
-    }
+    st = build_sys_hier(h.get(), sys[0], o, &msg);
+    if (st != CPC_OK) return set_err((cpc_status)st, msg);
+    st = assemble_levels(h.get(), sys, o, &msg);
+    if (st != CPC_OK) return set_err((cpc_status)st, msg);
+    sys.clear();
     // ILU(0) values
     h->lu = dupload(h->lu_host, h->owned, h->stream);
     if (h->f32) {
@@ -824,9 +980,11 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
       HIPCHK(hipMemsetAsync(v, 0, esz_of(h.get()) * (size_t)n, h->stream));
     for (void* v : {(void*)h->r, (void*)h->z, (void*)h->p, (void*)h->q, (void*)h->z64tmp})
       HIPCHK(hipMemsetAsync(v, 0, sizeof(double) * (size_t)n, h->stream));
-    for (auto& L : h->lev)
-      for (void* v : {L.f, L.u, L.r})
+    for (auto& L : h->lev) {
+      for (void* v : {L.f, L.u})
         if (v) HIPCHK(hipMemsetAsync(v, 0, esz_of(h.get()) * (size_t)L.A.n, h->stream));
+      if (L.r) HIPCHK(hipMemsetAsync(L.r, 0, esz_of(h.get()) * (size_t)L.lower.d.n, h->stream));
+    }
     HIPCHK(hipMemsetAsync(h->st, 0, sizeof(PcgState), h->stream));
     HIPCHK(hipMemsetAsync(h->sync.ticket, 0, sizeof(unsigned), h->stream));
     HIPCHK(hipMemsetAsync(h->sync.exited, 0, sizeof(unsigned), h->stream));
@@ -993,7 +1151,7 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         run_sweep(h, SWEEP_ILU_U, L.upper, h->ilu_u, h->y, h->w, h->u1, h->u2, nullptr);
         break;
       case CPC_K_RESIDUAL:
-        spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, nullptr);
+        spmv_or_throw(h, smoothed(L.A, L.nS, f32), 1, u, f32, f, f32, L.r, f32, L.A.tpr, nullptr);
         break;
       case CPC_K_RESTRICT:
         spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, h->lev[d + 1].f, f32, L.R.tpr, nullptr);

@@ -4,16 +4,19 @@
 // Each sweep has a packed copy of the rows it touches, in processing order: the
 // p-th processed row is row[p], its dependency-side entries are col/val[ptr[p] ..
 // ptr[p+1]) in column order, its diagonal is diag[p]. A workgroup (4 waves) takes
-// blocks of contiguous rows from a ticket counter in dependency order. Wave 0 is
-// the coordinator: it waits on other blocks' progress counters (relaxed polls, then
-// one agent-scope acquire fence) and publishes this block's progress (one
-// agent-scope release store) after levels another block waits for. Waves 1-3 are
-// workers: groups of TPR lanes solve the rows of one level set per step, with the
-// block's solved values in LDS. The row data of the next level (entries into
-// registers) and of the level after (row index, entry range, diagonal) are loaded
-// before the current level's wait and barrier, so their HBM latency overlaps the
-// synchronisation instead of sitting on the dependency chain. Keeping loads out of
-// the coordinator wave matters: its release/acquire waits drain only its own loads.
+// blocks of contiguous rows from a ticket counter in dependency order. Waves 1-3
+// are workers: groups of TPR lanes solve the rows of one level set per step and
+// keep the block's solved values in LDS only. The row data of the next level
+// (entries into registers) and of the level after (row index, entry range,
+// diagonal) are loaded before the current level's wait and barrier, so their HBM
+// latency overlaps the synchronisation instead of sitting on the dependency chain.
+// Wave 0 is the coordinator. It waits on other blocks' progress counters, and
+// after levels another block waits for (and at the end of the block) it copies the
+// rows solved since its last copy from LDS to the global vector with agent-scope
+// (write-through) stores, waits for their completion, and then advances the block's
+// progress counter. Readers of another block's rows use agent-scope loads. No
+// cache-wide release/acquire fences are used: with hundreds of workgroups
+// synchronising every level, L2-wide write-backs and invalidations would dominate.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -55,7 +58,8 @@ __global__ __launch_bounds__(kNT) void sweep3_kernel(SweepDev sw, SweepPackDev p
   constexpr int NGRP = kWorkers / TPR;
   extern __shared__ unsigned char smem_raw[];
   XT* xs = reinterpret_cast<XT*>(smem_raw);
-  int* lvt = reinterpret_cast<int*>(smem_raw + ((sw.R * (int)sizeof(XT) + 15) & ~15));
+  int* rows_l = reinterpret_cast<int*>(smem_raw + ((sw.R * (int)sizeof(XT) + 15) & ~15));
+  int* lvt = rows_l + ((sw.R + 3) & ~3);
   __shared__ int s_tick;
   __shared__ int s_last;
   if (done && *done) return;  // before taking a ticket: the counters stay untouched
@@ -79,7 +83,10 @@ __global__ __launch_bounds__(kNT) void sweep3_kernel(SweepDev sw, SweepPackDev p
     const int lb = sw.blk_beg[b], le = sw.blk_end[b];
     const int nl = le - lb;
     for (int q = tid; q <= nl && q <= kLvCap; q += kNT) lvt[q] = sw.lvl_ptr[lb + q];
+    const int P0 = sw.lvl_ptr[lb];
+    for (int q = tid; q < r1 - r0; q += kNT) rows_l[q] = pk.row[P0 + q];
     __syncthreads();
+    int copied = 0;  // rows (in processing order) already copied to the global vector
     auto LP = [&](int m) -> int { return m <= kLvCap ? lvt[m] : sw.lvl_ptr[lb + m]; };
     auto load_meta = [&](int m, Meta<VT>& mt) {
       mt.row = -1;
@@ -112,11 +119,19 @@ __global__ __launch_bounds__(kNT) void sweep3_kernel(SweepDev sw, SweepPackDev p
       }
     };
     auto xval = [&](int j, int i) -> double {
-      bool local;
-      if (OP == SWEEP_FGS0 || OP == SWEEP_ILU_L) local = (j >= r0);
-      else if (OP == SWEEP_ILU_U) local = (j < r1);
-      else local = (j > i && j < r1);
-      return local ? (double)xs[j - r0] : (double)x[j];
+      // solved in this block: LDS; solved by an earlier block: agent-scope load;
+      // in-place backward sweep, j < i: the value from before the sweep
+      if (OP == SWEEP_FGS0 || OP == SWEEP_ILU_L) {
+        if (j >= r0) return (double)xs[j - r0];
+        return (double)__hip_atomic_load(x + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (OP == SWEEP_ILU_U) {
+        if (j < r1) return (double)xs[j - r0];
+        return (double)__hip_atomic_load(x + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (j < i) return (double)x[j];
+        if (j < r1) return (double)xs[j - r0];
+        return (double)__hip_atomic_load(x + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     };
     auto finish = [&](int i, double s, double fv, double diag, double bv) {
       double xi;
@@ -124,8 +139,20 @@ __global__ __launch_bounds__(kNT) void sweep3_kernel(SweepDev sw, SweepPackDev p
       else xi = (fv - s) / diag;
       const XT xo = (XT)xi;
       xs[i - r0] = xo;
-      x[i] = xo;
       if (OP == SWEEP_ILU_U && out) out[i] = (XT)(bv + (double)xo);
+    };
+    // coordinator: copy rows solved up to level m (processing order) to the global
+    // vector, wait for the stores to complete, then publish progress m + 1
+    auto publish = [&](int m, bool advance) {
+      const int upto = LP(m + 1) - P0;
+      for (int q = copied + tid; q < upto; q += 64) {
+        const int i = rows_l[q];
+        __hip_atomic_store(x + i, xs[i - r0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      copied = upto;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if (advance && tid == 0)
+        __hip_atomic_store(sy.progress + b, (unsigned)(m + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
 
     Meta<VT> ma, mb;
@@ -156,8 +183,10 @@ __global__ __launch_bounds__(kNT) void sweep3_kernel(SweepDev sw, SweepPackDev p
             }
             if ((spins & 1023) == 0 && __hip_atomic_load(sy.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
           }
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
+        // the workers' agent-scope loads are issued after this barrier, i.e. after
+        // the counters showed the producers' stores complete
+        asm volatile("" ::: "memory");
       }
       __syncthreads();
       if (!coord) {
@@ -187,14 +216,14 @@ __global__ __launch_bounds__(kNT) void sweep3_kernel(SweepDev sw, SweepPackDev p
         }
       }
       __syncthreads();
-      if (tid == 0 && sw.publish[lv])
-        __hip_atomic_store(sy.progress + b, (unsigned)(m + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (coord && (sw.publish[lv] || m + 1 == nl)) publish(m, sw.publish[lv] != 0);
       if (!coord) {
         ma = mb;
         ea = eb;
         mb = mc;
       }
     }
+    __syncthreads();  // the coordinator's final copy reads LDS the next block overwrites
   }
   if (tid == 0) s_last = (atomicAdd(sy.exited, 1u) == gridDim.x - 1);
   __syncthreads();
@@ -211,7 +240,8 @@ __global__ __launch_bounds__(kNT) void sweep3_kernel(SweepDev sw, SweepPackDev p
 template <int OP, int TPR, typename VT, typename XT>
 void launch_one(hipStream_t s, const SweepDev& sw, const SweepPackDev& pk, int n, const void* f, void* x,
                 const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit) {
-  const size_t lds = (size_t)((sw.R * sizeof(XT) + 15) & ~size_t(15)) + sizeof(int) * (kLvCap + 1);
+  const size_t lds = (size_t)((sw.R * sizeof(XT) + 15) & ~size_t(15)) + sizeof(int) * ((sw.R + 3) & ~3) +
+                     sizeof(int) * (kLvCap + 1);
   static size_t attr = 65536;  // dynamic LDS the kernel may use without an attribute
   if (lds > attr) {
     if (hipFuncSetAttribute((const void*)sweep3_kernel<OP, TPR, VT, XT>, hipFuncAttributeMaxDynamicSharedMemorySize,
