@@ -217,6 +217,31 @@ typedef enum {
 cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t reps, double* avg_ms,
                            double* bytes_per_launch, int32_t* launches);
 
+/* ---- Batched form: independent systems of different sizes solved together ------
+ * cpc_setup_batch builds each system's own hierarchy (exactly what cpc_setup would
+ * build for it alone) and concatenates them level by level; cpc_solve_batch runs PCG
+ * on all systems at once, one HIP-graph replay per iteration, with per-system
+ * scalars and stopping, so each system's iterates are those of its own solve.
+ *   nsys                      : number of systems (>= 1); every system needs more than
+ *                               max_coarse rows when nsys > 1.
+ *   n[s], row_ptr[s], col_idx[s], val[s] : host CSR of system s (copied).
+ * Vectors of a batch are concatenated in system order: system s occupies entries
+ * [offset_s, offset_s + n[s]) (offsets from cpc_batch_info). */
+cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const* row_ptr,
+                           const int32_t* const* col_idx, const double* const* val, const cpc_options* opt,
+                           void* hip_stream, cpc_handle* out);
+
+/* PCG on every system of a batch handle from x = 0 with the handle's preconditioner.
+ * b_dev, x_dev: concatenated device FP64 vectors. iters[nsys], relres[nsys]: host
+ * outputs per system (may be NULL). Returns CPC_OK when every system converged,
+ * CPC_E_MAXIT when one did not, CPC_E_BREAKDOWN on a breakdown. */
+cpc_status cpc_solve_batch(cpc_handle h, const double* b_dev, double* x_dev, double tol, int32_t maxit,
+                           int32_t* iters, double* relres);
+
+/* Number of systems and, per system, rows and offset in the concatenated vectors
+ * (caller arrays of nsys entries; a single-system handle reports one system). */
+cpc_status cpc_batch_info(cpc_handle h, int32_t* nsys, int32_t* n, int32_t* offset);
+
 /* Destroy the handle and free its device and host memory (NULL is ignored). */
 void cpc_destroy(cpc_handle h);
 

@@ -22,7 +22,8 @@ PRECISION = {"fp64": 0, "fp32": 1}
 EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "cpc_apply_op", "cpc_spmv",
            "cpc_hierarchy_info", "cpc_get_level", "cpc_get_prolongation", "cpc_get_ilu", "cpc_get_stats",
            "cpc_neg_outer_on_pattern", "cpc_time_kernel", "cpc_destroy", "cpc_last_error", "cpc_tpfa_pattern",
-           "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values")
+           "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values", "cpc_setup_batch",
+           "cpc_solve_batch", "cpc_batch_info")
 KERNEL = {"spmv_pq": 0, "fgs": 1, "bgs": 2, "ilu_l": 3, "ilu_u": 4, "residual": 5, "restrict": 6, "prolong": 7,
           "vcycle": 8, "precond": 9, "iteration": 10}
 
@@ -94,6 +95,12 @@ def load():
     lib.cpc_tpfa_logk_grad.restype = I32
     lib.cpc_set_operator_values.argtypes = [P, P]
     lib.cpc_set_operator_values.restype = I32
+    lib.cpc_setup_batch.argtypes = [I32, P, P, P, P, ctypes.POINTER(Options), P, ctypes.POINTER(P)]
+    lib.cpc_setup_batch.restype = I32
+    lib.cpc_solve_batch.argtypes = [P, P, P, D, I32, P, P]
+    lib.cpc_solve_batch.restype = I32
+    lib.cpc_batch_info.argtypes = [P, ctypes.POINTER(I32), P, P]
+    lib.cpc_batch_info.restype = I32
     lib.cpc_destroy.argtypes = [P]
     lib.cpc_destroy.restype = None
     lib.cpc_last_error.argtypes = []

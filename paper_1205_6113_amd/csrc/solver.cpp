@@ -147,11 +147,23 @@ struct cpc_solver {
   double* graph_x[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // x bound into each graph
   int max_nblk = 1;
   const double* op_vals = nullptr;  // values PCG multiplies by (null: the setup matrix)
+  // batch of independent systems (cpc_setup_batch)
+  bool batch = false;
+  int nsys = 1;
+  std::vector<int> sys_n, sys_off;
+  cpc::BatchDev bd{};
+  double* btol = nullptr;
+  int* bmaxit = nullptr;
+  hipGraphExec_t bgraph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t bgraph_src[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* bgraph_x[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 
   ~cpc_solver() {
     for (int i = 0; i < 5; ++i) {
       if (graph[i]) (void)hipGraphExecDestroy(graph[i]);
       if (graph_src[i]) (void)hipGraphDestroy(graph_src[i]);
+      if (bgraph[i]) (void)hipGraphExecDestroy(bgraph[i]);
+      if (bgraph_src[i]) (void)hipGraphDestroy(bgraph_src[i]);
     }
     for (void* ptr : owned) (void)hipFree(ptr);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -572,6 +584,86 @@ static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_o
   return CPC_OK;
 }
 
+// Vectors, device state and sweep counters of a handle whose levels are assembled.
+static void allocate_work(cpc_solver* h) {
+  const int n = h->n;
+  h->lu = dupload(h->lu_host, h->owned, h->stream);
+  if (h->f32) {
+    h->lu32 = dalloc<float>(h->lu_host.size(), h->owned);
+    launch_to_f32(h->stream, (int64_t)h->lu_host.size(), h->lu, h->lu32);
+  }
+  h->r = dalloc<double>(n, h->owned);
+  h->z = dalloc<double>(n, h->owned);
+  h->p = dalloc<double>(n, h->owned);
+  h->q = dalloc<double>(n, h->owned);
+  h->z64tmp = dalloc<double>(n, h->owned);
+  h->pin = valloc(h, n);
+  h->u1 = valloc(h, n);
+  h->u2 = valloc(h, n);
+  h->res = valloc(h, n);
+  h->y = valloc(h, n);
+  h->w = valloc(h, n);
+  h->t = valloc(h, n);
+  h->st = dalloc<PcgState>(1, h->owned);
+  h->partials = dalloc<double>(4096, h->owned);
+  h->sync.ticket = dalloc<unsigned>(1, h->owned);
+  h->sync.exited = dalloc<unsigned>(1, h->owned);
+  h->sync.err = dalloc<unsigned>(1, h->owned);
+  h->sync.progress = dalloc<unsigned>(h->max_nblk, h->owned);
+  for (void* v : {h->pin, h->u1, h->u2, h->res, h->y, h->w, h->t})
+    HIPCHK(hipMemsetAsync(v, 0, esz_of(h) * (size_t)n, h->stream));
+  for (void* v : {(void*)h->r, (void*)h->z, (void*)h->p, (void*)h->q, (void*)h->z64tmp})
+    HIPCHK(hipMemsetAsync(v, 0, sizeof(double) * (size_t)n, h->stream));
+  for (auto& L : h->lev) {
+    for (void* v : {L.f, L.u})
+      if (v) HIPCHK(hipMemsetAsync(v, 0, esz_of(h) * (size_t)L.A.n, h->stream));
+    if (L.r) HIPCHK(hipMemsetAsync(L.r, 0, esz_of(h) * (size_t)L.lower.d.n, h->stream));
+  }
+  HIPCHK(hipMemsetAsync(h->st, 0, sizeof(PcgState), h->stream));
+  HIPCHK(hipMemsetAsync(h->sync.ticket, 0, sizeof(unsigned), h->stream));
+  HIPCHK(hipMemsetAsync(h->sync.exited, 0, sizeof(unsigned), h->stream));
+  HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
+  HIPCHK(hipMemsetAsync(h->sync.progress, 0, sizeof(unsigned) * h->max_nblk, h->stream));
+}
+
+// Per-system scalars and chunk tables of a batch.
+static void allocate_batch(cpc_solver* h) {
+  const int ns = h->nsys;
+  constexpr int kChunk = 2048;
+  std::vector<int> chunk_sys, chunk_row, sys_chunk(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) {
+    sys_chunk[s] = (int)chunk_sys.size();
+    for (int r = 0; r < h->sys_n[s]; r += kChunk) {
+      chunk_sys.push_back(s);
+      chunk_row.push_back(h->sys_off[s] + r);
+    }
+  }
+  sys_chunk[ns] = (int)chunk_sys.size();
+  chunk_row.push_back(h->n);
+  BatchDev& bd = h->bd;
+  bd.nsys = ns;
+  bd.nchunks = (int)chunk_sys.size();
+  bd.chunk_sys = dupload(chunk_sys, h->owned, h->stream);
+  bd.chunk_row = dupload(chunk_row, h->owned, h->stream);
+  bd.sys_chunk = dupload(sys_chunk, h->owned, h->stream);
+  bd.partials = dalloc<double>((size_t)4 * bd.nchunks, h->owned);
+  bd.cnt = dalloc<unsigned>((size_t)4 * ns, h->owned);
+  HIPCHK(hipMemsetAsync(bd.cnt, 0, sizeof(unsigned) * 4 * ns, h->stream));
+  double** dv[] = {&bd.rz, &bd.pq, &bd.alpha, &bd.beta, &bd.rr, &bd.bb, &bd.relres};
+  for (double** p : dv) {
+    *p = dalloc<double>(ns, h->owned);
+    HIPCHK(hipMemsetAsync(*p, 0, sizeof(double) * ns, h->stream));
+  }
+  bd.iters = dalloc<int>(ns, h->owned);
+  bd.done = dalloc<int>(ns, h->owned);
+  HIPCHK(hipMemsetAsync(bd.iters, 0, sizeof(int) * ns, h->stream));
+  HIPCHK(hipMemsetAsync(bd.done, 0, sizeof(int) * ns, h->stream));
+  h->btol = dalloc<double>(1, h->owned);
+  h->bmaxit = dalloc<int>(1, h->owned);
+  bd.tol_dev = h->btol;
+  bd.maxit_dev = h->bmaxit;
+}
+
 static MatDev smoothed(const DevCsr& A, int nS, bool f32) {
   MatDev m = A.mat(f32);
   m.n = nS;
@@ -787,6 +879,7 @@ static double iteration_bytes(const cpc_solver* h, int prec) {
 static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x, int use_x0, double tol, int maxit,
                             int32_t* iters, double* relres) {
   if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (h->batch) return set_err(CPC_E_ARG, "batch handle: use cpc_solve_batch");
   if (!b || !x) return set_err(CPC_E_ARG, "null vector");
   if (maxit < 0 || !(tol >= 0.0)) return set_err(CPC_E_ARG, "maxit must be >= 0 and tol >= 0");
   if (prec < 0 || prec > CPC_PREC_NONE) return set_err(CPC_E_ARG, "unknown preconditioner");
@@ -878,6 +971,117 @@ static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x,
   }
 }
 
+static void enqueue_batch_iteration(cpc_solver* h, int prec, double* x) {
+  const DevCsr& A = h->lev[0].A;
+  launch_bspmv_pq(h->stream, h->bd, A.mat(false), h->p, h->q, A.tpr);
+  launch_bupdate_xr(h->stream, h->bd, x, h->r, h->p, h->q);
+  apply_op(h, prec_to_op(prec), h->r, h->z, nullptr);
+  launch_bdot_rz(h->stream, h->bd, h->r, h->z, h->p, false);
+  launch_bupdate_p(h->stream, h->bd, h->z, h->p);
+}
+
+static cpc_status run_solve_batch(cpc_solver* h, int prec, const double* b, double* x, double tol, int maxit,
+                                  int32_t* iters, double* relres) {
+  if (!h || !h->batch) return set_err(CPC_E_ARG, "not a batch handle");
+  if (!b || !x) return set_err(CPC_E_ARG, "null vector");
+  if (maxit < 0 || !(tol >= 0.0)) return set_err(CPC_E_ARG, "maxit must be >= 0 and tol >= 0");
+  const double t0 = now_s();
+  const int ns = h->nsys;
+  try {
+    HIPCHK(hipMemcpyAsync(h->btol, &tol, sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->bmaxit, &maxit, sizeof(int), hipMemcpyHostToDevice, h->stream));
+    launch_binit(h->stream, h->bd, b, x, h->r);
+    apply_op(h, prec_to_op(prec), h->r, h->z, nullptr);
+    launch_bdot_rz(h->stream, h->bd, h->r, h->z, h->p, true);
+    HIPCHK(hipGetLastError());
+    std::vector<int> done(ns, 0);
+    HIPCHK(hipMemcpyAsync(done.data(), h->bd.done, sizeof(int) * ns, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    auto all_done = [&]() {
+      for (int v : done)
+        if (!v) return false;
+      return true;
+    };
+    const bool use_graph = h->opt.use_graph != 0;
+    if (use_graph && (!h->bgraph[prec] || h->bgraph_x[prec] != x)) {
+      if (h->bgraph[prec]) {
+        (void)hipGraphExecDestroy(h->bgraph[prec]);
+        (void)hipGraphDestroy(h->bgraph_src[prec]);
+        h->bgraph[prec] = nullptr;
+        h->bgraph_src[prec] = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_batch_iteration(h, prec, x);
+      } catch (...) {
+        (void)hipStreamEndCapture(h->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      HIPCHK(hipStreamEndCapture(h->stream, &g));
+      hipGraphExec_t ge = nullptr;
+      hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        throw HipError{e, "hipGraphInstantiate"};
+      }
+      h->bgraph_src[prec] = g;
+      h->bgraph[prec] = ge;
+      h->bgraph_x[prec] = x;
+    }
+    const int every = std::max(1, (int)h->opt.check_every);
+    int launched = 0;
+    while (!all_done() && launched < maxit) {
+      const int k = std::min(every, maxit - launched);
+      for (int i = 0; i < k; ++i) {
+        if (use_graph) HIPCHK(hipGraphLaunch(h->bgraph[prec], h->stream));
+        else enqueue_batch_iteration(h, prec, x);
+      }
+      launched += k;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(done.data(), h->bd.done, sizeof(int) * ns, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    std::vector<int> it(ns);
+    std::vector<double> rel(ns);
+    unsigned herr = 0;
+    HIPCHK(hipMemcpyAsync(it.data(), h->bd.iters, sizeof(int) * ns, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(rel.data(), h->bd.relres, sizeof(double) * ns, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(done.data(), h->bd.done, sizeof(int) * ns, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&herr, h->sync.err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    int maxits = 0;
+    for (int s = 0; s < ns; ++s) {
+      if (iters) iters[s] = it[s];
+      if (relres) relres[s] = rel[s];
+      maxits = std::max(maxits, it[s]);
+    }
+    h->stats.iters = maxits;
+    h->stats.solve_s = now_s() - t0;
+    h->stats.bytes_per_iter = iteration_bytes(h, prec);
+    h->stats.bytes_initial = (12.0 * h->lev[0].A.nnz + 40.0 * h->n) + prec_bytes(h, prec) + 24.0 * h->n;
+    if (herr) {
+      HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
+      HIPCHK(hipStreamSynchronize(h->stream));
+      return set_err(CPC_E_DEVICE, "a sweep wait exceeded its bound");
+    }
+    cpc_status status = CPC_OK;
+    for (int s = 0; s < ns; ++s) {
+      if (done[s] == DONE_BREAKDOWN) {
+        status = set_err(CPC_E_BREAKDOWN, "PCG breakdown in system " + std::to_string(s));
+        break;
+      }
+      if (done[s] != DONE_CONVERGED && done[s] != DONE_ZERO_RHS)
+        status = set_err(CPC_E_MAXIT, "system " + std::to_string(s) + " did not converge within maxit");
+    }
+    h->stats.status = status;
+    return status;
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+}
+
 }  // namespace cpc
 
 using namespace cpc;
@@ -903,11 +1107,7 @@ void cpc_default_options(cpc_options* o) {
 
 const char* cpc_last_error(void) { return g_last_error.c_str(); }
 
-cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* val,
-                     const cpc_options* opt, void* hip_stream, cpc_handle* out) {
-  if (!out) return set_err(CPC_E_ARG, "null output handle");
-  *out = nullptr;
-  cpc_options o;
+static cpc_status read_options(const cpc_options* opt, cpc_options& o) {
   cpc_default_options(&o);
   if (opt) {
     if (opt->struct_size != (int32_t)sizeof(cpc_options)) return set_err(CPC_E_ARG, "cpc_options.struct_size mismatch");
@@ -917,6 +1117,15 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
   if (o.precision != CPC_FP64 && o.precision != CPC_FP32_PRECOND) return set_err(CPC_E_ARG, "unknown precision");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1) return set_err(CPC_E_ARG, "bad level limits");
   if (!(o.theta >= 0.0 && o.theta <= 1.0)) return set_err(CPC_E_ARG, "theta must lie in [0, 1]");
+  return CPC_OK;
+}
+
+cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                     const cpc_options* opt, void* hip_stream, cpc_handle* out) {
+  if (!out) return set_err(CPC_E_ARG, "null output handle");
+  *out = nullptr;
+  cpc_options o;
+  if (cpc_status os = read_options(opt, o)) return os;
   std::string msg;
   const double t0 = now_s();
   int vs = validate_csr(n, row_ptr, col_idx, val, o.check_symmetry != 0, &msg);
@@ -951,45 +1160,7 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
     st = assemble_levels(h.get(), sys, o, &msg);
     if (st != CPC_OK) return set_err((cpc_status)st, msg);
     sys.clear();
-    // ILU(0) values
-    h->lu = dupload(h->lu_host, h->owned, h->stream);
-    if (h->f32) {
-      h->lu32 = dalloc<float>(h->lu_host.size(), h->owned);
-      launch_to_f32(h->stream, (int64_t)h->lu_host.size(), h->lu, h->lu32);
-    }
-    // vectors and state
-    h->r = dalloc<double>(n, h->owned);
-    h->z = dalloc<double>(n, h->owned);
-    h->p = dalloc<double>(n, h->owned);
-    h->q = dalloc<double>(n, h->owned);
-    h->z64tmp = dalloc<double>(n, h->owned);
-    h->pin = valloc(h.get(), n);
-    h->u1 = valloc(h.get(), n);
-    h->u2 = valloc(h.get(), n);
-    h->res = valloc(h.get(), n);
-    h->y = valloc(h.get(), n);
-    h->w = valloc(h.get(), n);
-    h->t = valloc(h.get(), n);
-    h->st = dalloc<PcgState>(1, h->owned);
-    h->partials = dalloc<double>(4096, h->owned);
-    h->sync.ticket = dalloc<unsigned>(1, h->owned);
-    h->sync.exited = dalloc<unsigned>(1, h->owned);
-    h->sync.err = dalloc<unsigned>(1, h->owned);
-    h->sync.progress = dalloc<unsigned>(h->max_nblk, h->owned);
-    for (void* v : {h->pin, h->u1, h->u2, h->res, h->y, h->w, h->t})
-      HIPCHK(hipMemsetAsync(v, 0, esz_of(h.get()) * (size_t)n, h->stream));
-    for (void* v : {(void*)h->r, (void*)h->z, (void*)h->p, (void*)h->q, (void*)h->z64tmp})
-      HIPCHK(hipMemsetAsync(v, 0, sizeof(double) * (size_t)n, h->stream));
-    for (auto& L : h->lev) {
-      for (void* v : {L.f, L.u})
-        if (v) HIPCHK(hipMemsetAsync(v, 0, esz_of(h.get()) * (size_t)L.A.n, h->stream));
-      if (L.r) HIPCHK(hipMemsetAsync(L.r, 0, esz_of(h.get()) * (size_t)L.lower.d.n, h->stream));
-    }
-    HIPCHK(hipMemsetAsync(h->st, 0, sizeof(PcgState), h->stream));
-    HIPCHK(hipMemsetAsync(h->sync.ticket, 0, sizeof(unsigned), h->stream));
-    HIPCHK(hipMemsetAsync(h->sync.exited, 0, sizeof(unsigned), h->stream));
-    HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
-    HIPCHK(hipMemsetAsync(h->sync.progress, 0, sizeof(unsigned) * h->max_nblk, h->stream));
+    allocate_work(h.get());
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError& e) {
@@ -1002,9 +1173,91 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
   return CPC_OK;
 }
 
+cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const* row_ptr,
+                           const int32_t* const* col_idx, const double* const* val, const cpc_options* opt,
+                           void* hip_stream, cpc_handle* out) {
+  if (!out) return set_err(CPC_E_ARG, "null output handle");
+  *out = nullptr;
+  if (nsys < 1 || !n || !row_ptr || !col_idx || !val) return set_err(CPC_E_ARG, "bad batch arguments");
+  cpc_options o;
+  if (cpc_status os = read_options(opt, o)) return os;
+  std::string msg;
+  const double t0 = now_s();
+  int64_t total = 0;
+  for (int s = 0; s < nsys; ++s) {
+    int vs = validate_csr(n[s], row_ptr[s], col_idx[s], val[s], o.check_symmetry != 0, &msg);
+    if (vs != CPC_OK) return set_err((cpc_status)vs, "system " + std::to_string(s) + ": " + msg);
+    total += n[s];
+  }
+  if (total > 2147483647LL) return set_err(CPC_E_ARG, "batch exceeds 2^31 rows");
+  auto h = std::make_unique<cpc_solver>();
+  h->opt = o;
+  h->batch = true;
+  h->nsys = nsys;
+  h->f32 = (o.precision == CPC_FP32_PRECOND);
+  try {
+    std::vector<SysHier> sys(nsys);
+    for (int s = 0; s < nsys; ++s) {
+      HostCsr A0;
+      A0.n = A0.ncols = n[s];
+      A0.rp.assign(row_ptr[s], row_ptr[s] + n[s] + 1);
+      A0.ci.assign(col_idx[s], col_idx[s] + row_ptr[s][n[s]]);
+      A0.v.assign(val[s], val[s] + row_ptr[s][n[s]]);
+      sys[s].A.push_back(std::move(A0));
+      int st = ilu0_factor(sys[s].A[0], sys[s].lu, &msg);
+      if (st != CPC_OK) return set_err((cpc_status)st, "system " + std::to_string(s) + ": " + msg);
+      h->sys_n.push_back(n[s]);
+      h->sys_off.push_back(s == 0 ? 0 : h->sys_off[s - 1] + n[s - 1]);
+    }
+    h->n = (int)total;
+    if (hip_stream) {
+      h->stream = (hipStream_t)hip_stream;
+    } else {
+      HIPCHK(hipStreamCreate(&h->stream));
+      h->own_stream = true;
+    }
+    for (int s = 0; s < nsys; ++s) {
+      int st = build_sys_hier(h.get(), sys[s], o, &msg);
+      if (st != CPC_OK) return set_err((cpc_status)st, "system " + std::to_string(s) + ": " + msg);
+    }
+    int st = assemble_levels(h.get(), sys, o, &msg);
+    if (st != CPC_OK) return set_err((cpc_status)st, msg);
+    h->nnz = h->lev[0].A.nnz;
+    sys.clear();
+    allocate_work(h.get());
+    allocate_batch(h.get());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    return set_err(CPC_E_NOMEM, "host allocation failed");
+  }
+  h->stats.setup_s = now_s() - t0;
+  *out = h.release();
+  return CPC_OK;
+}
+
+cpc_status cpc_solve_batch(cpc_handle h, const double* b_dev, double* x_dev, double tol, int32_t maxit,
+                           int32_t* iters, double* relres) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  return run_solve_batch(h, h->opt.prec, b_dev, x_dev, tol, maxit, iters, relres);
+}
+
+cpc_status cpc_batch_info(cpc_handle h, int32_t* nsys, int32_t* n, int32_t* offset) {
+  if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (nsys) *nsys = h->nsys;
+  for (int s = 0; s < h->nsys; ++s) {
+    if (n) n[s] = h->batch ? h->sys_n[s] : h->n;
+    if (offset) offset[s] = h->batch ? h->sys_off[s] : 0;
+  }
+  return CPC_OK;
+}
+
 cpc_status cpc_solve(cpc_handle h, const double* b_dev, double* x_dev, int32_t use_x0, double tol, int32_t maxit,
                      int32_t* iters, double* relres) {
   if (!h) return set_err(CPC_E_ARG, "null handle");
+  if (h->batch) return set_err(CPC_E_ARG, "batch handle: use cpc_solve_batch");
   return run_solve(h, h->opt.prec, b_dev, x_dev, use_x0, tol, maxit, iters, relres);
 }
 

@@ -194,6 +194,76 @@ class Solver:
         return {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
 
 
+class BatchSolver:
+    """Independent systems of different sizes set up and solved together
+    (cpc_setup_batch / cpc_solve_batch). Vectors are concatenated in system order."""
+
+    def __init__(self, systems, device="cuda", **opts):
+        lib = load()
+        self._lib = lib
+        self.device = torch.device(device)
+        mats = [(int(n), _host(rp, np.int32), _host(ci, np.int32), _host(v, np.float64)) for n, rp, ci, v in systems]
+        self.nsys = len(mats)
+        ns = np.array([m[0] for m in mats], np.int32)
+        P = ctypes.c_void_p
+        rps = (P * self.nsys)(*[m[1].ctypes.data for m in mats])
+        cis = (P * self.nsys)(*[m[2].ctypes.data for m in mats])
+        vals = (P * self.nsys)(*[m[3].ctypes.data for m in mats])
+        self._keep = mats
+        self._opts = options(**opts)
+        h = ctypes.c_void_p()
+        stream = None
+        if self.device.type == "cuda" and torch.cuda.is_available():
+            stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream or None)
+        check(lib.cpc_setup_batch(self.nsys, _ptr(ns), rps, cis, vals, ctypes.byref(self._opts), stream,
+                                  ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+        nsys = ctypes.c_int32(0)
+        self.sizes = np.zeros(self.nsys, np.int32)
+        self.offsets = np.zeros(self.nsys, np.int32)
+        check(lib.cpc_batch_info(h, ctypes.byref(nsys), _ptr(self.sizes), _ptr(self.offsets)))
+        self.n = int(self.sizes.sum())
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.cpc_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-8, maxit: int = 10000):
+        """Returns (x, iters[nsys], relres[nsys], status)."""
+        b = _dev_vec(b, self.n, "b")
+        x = torch.empty_like(b) if x is None else _dev_vec(x, self.n, "x")
+        it = np.zeros(self.nsys, np.int32)
+        rel = np.zeros(self.nsys, np.float64)
+        st = self._lib.cpc_solve_batch(self._h, b.data_ptr(), x.data_ptr(), float(tol), int(maxit), _ptr(it),
+                                       _ptr(rel))
+        check(st, allow=(_lib.CPC_OK, _lib.CPC_E_MAXIT, _lib.CPC_E_BREAKDOWN))
+        return x, it, rel, st
+
+    def hierarchy(self) -> dict:
+        return Solver.hierarchy(self)
+
+    def time_kernel(self, kernel, level=-1, reps=10):
+        return Solver.time_kernel(self, kernel, level, reps)
+
+    def stats(self) -> dict:
+        return Solver.stats(self)
+
+
 def setup_status(n, row_ptr, col, val, **opts) -> tuple[int, str]:
     """Run cpc_setup and return (status, message) without raising (host-side checks)."""
     lib = load()
@@ -208,4 +278,4 @@ def setup_status(n, row_ptr, col, val, **opts) -> tuple[int, str]:
     return st, _lib.last_error()
 
 
-__all__ = ["Solver", "CpcError", "options", "setup_status"]
+__all__ = ["Solver", "BatchSolver", "CpcError", "options", "setup_status"]
