@@ -54,7 +54,8 @@ long cpch_rs_interp(int n, const int* rp, const int* ci, const double* v, double
 // Sweep schedule: sizes[0..5] = nblk, nlev_total, nwait, global_depth, max_local_levels, R.
 // Arrays may be null on a first call that only asks for sizes.
 int cpch_sweep(int n, const int* rp, const int* ci, const double* v, int forward, int R, int* sizes, int* perm,
-               int* blk_beg, int* blk_end, int* lvl_ptr, int* wait_ptr, int* wait_blk, int* wait_need, int* publish) {
+               int* blk_beg, int* blk_end, int* lvl_ptr, int* wait_ptr, int* wait_blk, int* wait_need, int* publish,
+               int* blk_row) {
   HostCsr a = make_csr(n, rp, ci, v);
   cpc::SweepSchedule s = cpc::build_sweep(a, forward != 0, R);
   const int nl = (int)s.lvl_ptr.size() - 1;
@@ -72,6 +73,7 @@ int cpch_sweep(int n, const int* rp, const int* ci, const double* v, int forward
   if (wait_blk) std::memcpy(wait_blk, s.wait_blk.data(), sizeof(int) * s.wait_blk.size());
   if (wait_need) std::memcpy(wait_need, s.wait_need.data(), sizeof(int) * s.wait_need.size());
   if (publish) std::memcpy(publish, s.publish.data(), sizeof(int) * nl);
+  if (blk_row) std::memcpy(blk_row, s.blk_row.data(), sizeof(int) * (s.nblk + 1));
   return 0;
 }
 

@@ -366,15 +366,42 @@ int lower_depth(const HostCsr& a) {
   return depth;
 }
 
+std::vector<int> sweep_block_starts(const HostCsr& a, int R) {
+  const int n = a.n;
+  R = std::max(1, std::min(R, n));
+  std::vector<int> starts{0};
+  while (starts.back() + R < n) {
+    const int s0 = starts.back();
+    int cut = s0 + R;
+    // prefer a row with no coupling to its predecessor
+    for (int i = s0 + R; i > s0 + R / 2; --i) {
+      bool coupled = false;
+      for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < i; ++p) coupled |= (a.ci[p] == i - 1);
+      if (!coupled) {
+        cut = i;
+        break;
+      }
+    }
+    starts.push_back(cut);
+  }
+  starts.push_back(n);
+  return starts;
+}
+
 SweepSchedule build_sweep(const HostCsr& a, bool forward, int R) {
   SweepSchedule s;
   const int n = a.n;
   s.n = n;
   s.forward = forward;
-  s.R = std::max(1, std::min(R, n));
-  s.nblk = (n + s.R - 1) / s.R;
+  s.blk_row = sweep_block_starts(a, R);
+  s.nblk = (int)s.blk_row.size() - 1;
+  s.R = 0;
+  for (int b = 0; b < s.nblk; ++b) s.R = std::max(s.R, s.blk_row[b + 1] - s.blk_row[b]);
+  std::vector<int> blk_of(n);
+  for (int b = 0; b < s.nblk; ++b)
+    for (int i = s.blk_row[b]; i < s.blk_row[b + 1]; ++i) blk_of[i] = b;
   std::vector<int> lev(n, 0), glev(n, 0);
-  // global depth (for reporting) in the sweep's own direction
+  // global depth of every row in the sweep's own direction
   if (forward) {
     for (int i = 0; i < n; ++i) {
       int g = 0;
@@ -396,7 +423,7 @@ SweepSchedule build_sweep(const HostCsr& a, bool forward, int R) {
   s.lvl_ptr.push_back(0);
   s.wait_ptr.push_back(0);
   std::vector<int> last_need(s.nblk, 0);  // running maximum of waits of the current block
-  std::vector<int> touched;
+  std::vector<int> touched, uniq;
   std::vector<std::vector<int>> rows_at;
   // per-level: list of (block, need) candidates
   std::vector<std::vector<std::pair<int, int>>> waits_at;
@@ -404,25 +431,17 @@ SweepSchedule build_sweep(const HostCsr& a, bool forward, int R) {
   for (int t = 0; t < s.nblk; ++t) {
     // blocks in processing order: increasing rows forward, decreasing backward
     const int b = forward ? t : s.nblk - 1 - t;
-    const int r0 = b * s.R, r1 = std::min(n, r0 + s.R);
-    int nl = 0;
-    if (forward) {
-      for (int i = r0; i < r1; ++i) {
-        int l = 0;
-        for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < i; ++p)
-          if (a.ci[p] >= r0) l = std::max(l, lev[a.ci[p]] + 1);
-        lev[i] = l;
-        nl = std::max(nl, l + 1);
-      }
-    } else {
-      for (int i = r1 - 1; i >= r0; --i) {
-        int l = 0;
-        for (int p = a.rp[i + 1] - 1; p >= a.rp[i] && a.ci[p] > i; --p)
-          if (a.ci[p] < r1) l = std::max(l, lev[a.ci[p]] + 1);
-        lev[i] = l;
-        nl = std::max(nl, l + 1);
-      }
-    }
+    const int r0 = s.blk_row[b], r1 = s.blk_row[b + 1];
+    // Local levels: the distinct global depths of the block's rows, in increasing
+    // order. A row then waits for nothing that the global level schedule would not
+    // also wait for, so blocks that run side by side advance in step; levels built
+    // from the block's own rows alone let an early local level stall on a deep
+    // external row and serialise the blocks behind it.
+    uniq.assign(glev.begin() + r0, glev.begin() + r1);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    const int nl = (int)uniq.size();
+    for (int i = r0; i < r1; ++i) lev[i] = (int)(std::lower_bound(uniq.begin(), uniq.end(), glev[i]) - uniq.begin());
     rows_at.assign(nl, {});
     waits_at.assign(nl, {});
     for (int i = r0; i < r1; ++i) rows_at[lev[i]].push_back(i);
@@ -430,12 +449,12 @@ SweepSchedule build_sweep(const HostCsr& a, bool forward, int R) {
       if (forward) {
         for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < r0; ++p) {
           const int j = a.ci[p];
-          waits_at[lev[i]].push_back({j / s.R, lev[j] + 1});
+          waits_at[lev[i]].push_back({blk_of[j], lev[j] + 1});
         }
       } else {
         for (int p = a.rp[i + 1] - 1; p >= a.rp[i] && a.ci[p] >= r1; --p) {
           const int j = a.ci[p];
-          waits_at[lev[i]].push_back({j / s.R, lev[j] + 1});
+          waits_at[lev[i]].push_back({blk_of[j], lev[j] + 1});
         }
       }
     }

@@ -42,8 +42,9 @@ HostCsr transpose(const HostCsr& a);
 // earlier blocks (later blocks for the backward direction) before a level whose
 // rows depend on them.
 struct SweepSchedule {
-  int n = 0, R = 0, nblk = 0;
+  int n = 0, R = 0, nblk = 0;  // R: largest block
   bool forward = true;
+  std::vector<int> blk_row;   // nblk+1: first row of each block
   std::vector<int> perm;      // rows in processing order, block after block in processing order
   std::vector<int> blk_beg;   // nblk: first global level of block b (b in row order)
   std::vector<int> blk_end;   // nblk: one past the last global level of block b
@@ -56,8 +57,14 @@ struct SweepSchedule {
   int max_local_levels = 0;
 };
 
-// Build the schedule of the lower (forward) or upper (backward) sweep of a.
+// Build the schedule of the lower (forward) or upper (backward) sweep of a with
+// blocks of at most R rows. Block boundaries are moved back (by at most R/2) to a
+// row that is not coupled to the row before it, so that a block's first rows do not
+// depend on the last (deepest) rows of the previous block.
 SweepSchedule build_sweep(const HostCsr& a, bool forward, int R);
+
+// Block starts used by build_sweep (size nblk + 1, last = n).
+std::vector<int> sweep_block_starts(const HostCsr& a, int R);
 
 // Depth of the lower-triangular dependency graph (number of level sets).
 int lower_depth(const HostCsr& a);

@@ -7,12 +7,8 @@
 //    workgroup writes one partial, the last workgroup to arrive sums the
 //    partials in index order and updates the scalars (alpha, beta, relres,
 //    convergence flag) on the device.
-//  * A persistent, block-pipelined, level-scheduled triangular sweep (forward and
-//    backward Gauss-Seidel, ILU(0) L and U solves). Rows are cut into contiguous
-//    blocks; a workgroup takes blocks in dependency order from a ticket counter,
-//    keeps the block's solved values in LDS, walks the block's own level sets with
-//    workgroup barriers, and waits on per-block progress counters (agent-scope
-//    acquire/release) only where a level depends on another block.
+//  * Dense coarsest-level matvec, elementwise vector kernels, FP64->FP32 copies.
+//  The level-scheduled sweeps live in sweep.hip.
 #include "kernels.hpp"
 
 #include <hip/hip_runtime.h>
@@ -248,110 +244,6 @@ __global__ __launch_bounds__(kNT) void pcg_init_kernel(int n, const int* __restr
   (void)lastb;
 }
 
-// ----------------------------------------------------------------------------
-// Persistent block-pipelined sweep.
-template <int OP, int TPR, typename VT, typename XT>
-__global__ __launch_bounds__(256) void sweep_kernel(SweepDev sw, int n, const int* __restrict__ rp,
-                                                    const int* __restrict__ ci, const int* __restrict__ dpos,
-                                                    const VT* __restrict__ val, const XT* __restrict__ f, XT* x,
-                                                    const XT* __restrict__ base, XT* __restrict__ out, SweepSync sy,
-                                                    const int* __restrict__ done, long spin_limit) {
-  constexpr bool FWD = (OP == SWEEP_FGS0 || OP == SWEEP_ILU_L);
-  extern __shared__ unsigned char smem_raw[];
-  XT* xs = reinterpret_cast<XT*>(smem_raw);
-  __shared__ int s_tick;
-  __shared__ int s_last;
-  if (done && *done) return;  // before taking a ticket: the counters stay untouched
-  const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  const int lane = tid % TPR;
-  const int grp = tid / TPR;
-  const int ngrp = nt / TPR;
-  for (;;) {
-    if (tid == 0) s_tick = (int)atomicAdd(sy.ticket, 1u);
-    __syncthreads();
-    const int t = s_tick;
-    __syncthreads();
-    if (t >= sw.nblk) break;
-    const int b = FWD ? t : sw.nblk - 1 - t;
-    const int r0 = b * sw.R;
-    const int r1 = min(n, r0 + sw.R);
-    const int lb = sw.blk_beg[b], le = sw.blk_end[b];
-    for (int lv = lb; lv < le; ++lv) {
-      const int w0 = sw.wait_ptr[lv], w1 = sw.wait_ptr[lv + 1];
-      if (w0 < w1) {
-        // poll with relaxed agent-scope loads; one acquire fence once the value is seen
-        for (int w = w0 + tid; w < w1; w += nt) {
-          const unsigned need = (unsigned)sw.wait_need[w];
-          unsigned* pp = sy.progress + sw.wait_blk[w];
-          long spins = 0;
-          while (__hip_atomic_load(pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > spin_limit) {
-              atomicOr(sy.err, 1u);
-              break;
-            }
-            if ((spins & 1023) == 0 && __hip_atomic_load(sy.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        __syncthreads();
-      }
-      const int p0 = sw.lvl_ptr[lv], p1 = sw.lvl_ptr[lv + 1];
-      for (int p = p0 + grp; p < p1; p += ngrp) {
-        const int i = sw.perm[p];
-        const int rb = rp[i], re = rp[i + 1], dp = dpos[i];
-        double s = 0.0;
-        if (OP == SWEEP_FGS0 || OP == SWEEP_ILU_L) {
-          for (int k = rb + lane; k < dp; k += TPR) {
-            const int j = ci[k];
-            const double xj = (j >= r0) ? (double)xs[j - r0] : (double)x[j];
-            s += (double)val[k] * xj;
-          }
-        } else if (OP == SWEEP_ILU_U) {
-          for (int k = dp + 1 + lane; k < re; k += TPR) {
-            const int j = ci[k];
-            const double xj = (j < r1) ? (double)xs[j - r0] : (double)x[j];
-            s += (double)val[k] * xj;
-          }
-        } else {  // SWEEP_BGS_IP: j > i new values, j < i old values (global)
-          for (int k = rb + lane; k < re; k += TPR) {
-            if (k == dp) continue;
-            const int j = ci[k];
-            const double xj = (j > i && j < r1) ? (double)xs[j - r0] : (double)x[j];
-            s += (double)val[k] * xj;
-          }
-        }
-        s = group_sum<TPR>(s);
-        if (lane == 0) {
-          double xi;
-          if (OP == SWEEP_ILU_L) xi = (double)f[i] - s;
-          else xi = ((double)f[i] - s) / (double)val[dp];
-          const XT xo = (XT)xi;
-          xs[i - r0] = xo;
-          x[i] = xo;
-          if (OP == SWEEP_ILU_U && out) out[i] = (XT)((double)base[i] + (double)xo);
-        }
-      }
-      __syncthreads();
-      // another block waits for this level: release the block's stores (they
-      // happen-before this point through the barrier) with the progress counter
-      if (tid == 0 && sw.publish[lv])
-        __hip_atomic_store(sy.progress + b, (unsigned)(lv - lb + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-  if (tid == 0) s_last = (atomicAdd(sy.exited, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    for (int i = tid; i < sw.nblk; i += nt) sy.progress[i] = 0u;
-    if (tid == 0) {
-      *sy.ticket = 0u;
-      *sy.exited = 0u;
-    }
-  }
-}
-
 template <typename FT, typename ET>
 __global__ __launch_bounds__(kNT) void dense_matvec_kernel(int n, const double* __restrict__ inv,
                                                            const FT* __restrict__ f, ET* __restrict__ e,
@@ -471,39 +363,6 @@ void launch_pcg_init(hipStream_t s, const MatDev& A, const double* b, double* x,
   pcg_init_kernel<T><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const double*)A.v, b, x, r, use_x0, partials, stt)
   CPC_TPR_DISPATCH(tpr, CPC_INIT_CALL)
 #undef CPC_INIT_CALL
-}
-
-template <int OP, typename VT, typename XT>
-static void sweep_typed(hipStream_t s, const SweepDev& sw, const MatDev& M, const void* vals, const void* f, void* x,
-                        const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit) {
-  const size_t lds = (size_t)sw.R * sizeof(XT);
-#define CPC_SWEEP_CALL(T)                                                                                       \
-  sweep_kernel<OP, T, VT, XT><<<sw.grid, sw.nthreads, lds, s>>>(sw, M.n, M.rp, M.ci, M.dpos, (const VT*)vals, \
-                                                                (const XT*)f, (XT*)x, (const XT*)base, (XT*)out, \
-                                                                sync, done, spin_limit)
-  CPC_TPR_DISPATCH(sw.tpr, CPC_SWEEP_CALL)
-#undef CPC_SWEEP_CALL
-}
-
-void launch_sweep(hipStream_t s, int op, const SweepDev& sw, const MatDev& M, const void* vals, bool fp32,
-                  const void* f, void* x, const void* base, void* out, const SweepSync& sync, const int* done,
-                  long spin_limit) {
-  if (sw.n <= 0) return;
-  if (!fp32) {
-    switch (op) {
-      case SWEEP_FGS0: sweep_typed<SWEEP_FGS0, double, double>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
-      case SWEEP_BGS_IP: sweep_typed<SWEEP_BGS_IP, double, double>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
-      case SWEEP_ILU_L: sweep_typed<SWEEP_ILU_L, double, double>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
-      default: sweep_typed<SWEEP_ILU_U, double, double>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
-    }
-  } else {
-    switch (op) {
-      case SWEEP_FGS0: sweep_typed<SWEEP_FGS0, float, float>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
-      case SWEEP_BGS_IP: sweep_typed<SWEEP_BGS_IP, float, float>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
-      case SWEEP_ILU_L: sweep_typed<SWEEP_ILU_L, float, float>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
-      default: sweep_typed<SWEEP_ILU_U, float, float>(s, sw, M, vals, f, x, base, out, sync, done, spin_limit); break;
-    }
-  }
 }
 
 void launch_dense_matvec(hipStream_t s, int n, const double* inv, const void* f, bool ff32, void* e, bool ef32,

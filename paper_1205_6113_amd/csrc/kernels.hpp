@@ -35,8 +35,9 @@ struct SweepSync {
 
 // One level-scheduled sweep over a matrix (see SweepSchedule in host_setup.hpp).
 struct SweepDev {
-  int n, R, nblk, nlev;
+  int n, R, nblk, nlev;  // R: rows of the largest block
   const int* perm;
+  const int* blk_row;   // nblk + 1 row starts of the blocks
   const int* blk_beg;
   const int* blk_end;
   const int* lvl_ptr;
@@ -137,11 +138,7 @@ void launch_sweep_packed(hipStream_t s, int op, const SweepDev& sw, const SweepP
                          const void* f, void* x, const void* base, void* out, const SweepSync& sync,
                          const int* done, long spin_limit);
 int sweep_max_rows_per_block();
-
-// Persistent level-scheduled sweep (CSR rows through perm).
-void launch_sweep(hipStream_t s, int op, const SweepDev& sw, const MatDev& M, const void* vals, bool fp32,
-                  const void* f, void* x, const void* base, void* out, const SweepSync& sync, const int* done,
-                  long spin_limit);
+int sweep_entries_per_lane();
 
 // e = inv f with a dense row-major inverse (coarsest level, FP64).
 void launch_dense_matvec(hipStream_t s, int n, const double* inv, const void* f, bool ff32, void* e, bool ef32,

@@ -294,15 +294,12 @@ static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncol
 }
 
 static int choose_block_rows(int n, double avg_row) {
-  // One workgroup per block. Small matrices: a single block (all dependencies stay
-  // inside one workgroup). Larger ones: about 2 blocks per compute unit, capped by
-  // the LDS the block's values need.
-  if (n <= 4096) return n;
-  int R = (n + 511) / 512;
-  R = std::max(R, 256);
-  R = std::min(R, 8192);
+  // One workgroup per block. Up to the LDS limit a single block keeps every
+  // dependency inside one workgroup; beyond it, the largest blocks that fit, since a
+  // block of 8192 rows already holds more rows per level than its workers take in
+  // one pass and fewer blocks means fewer cross-workgroup hand-offs.
   (void)avg_row;
-  return R;
+  return std::min(n, sweep_max_rows_per_block());
 }
 
 static void upload_sweep(cpc_solver* h, const SweepSchedule& s, DevSweepSched& d, double avg_half_row) {
@@ -313,6 +310,7 @@ static void upload_sweep(cpc_solver* h, const SweepSchedule& s, DevSweepSched& d
   sd.nblk = s.nblk;
   sd.nlev = (int)s.lvl_ptr.size() - 1;
   sd.perm = dupload(s.perm, h->owned, h->stream);
+  sd.blk_row = dupload(s.blk_row, h->owned, h->stream);
   sd.blk_beg = dupload(s.blk_beg, h->owned, h->stream);
   sd.blk_end = dupload(s.blk_end, h->owned, h->stream);
   sd.lvl_ptr = dupload(s.lvl_ptr, h->owned, h->stream);
@@ -384,8 +382,9 @@ static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vecto
     pk.diag = dupload(diag, h->owned, h->stream);
   }
   const double avg = n ? (double)ptr[n] / n : 0.0;
+  // enough lanes that an average row fits the entries each lane prefetches
   int t = 1;
-  while (t < 64 && t * 6 < avg) t <<= 1;
+  while (t < 64 && t * sweep_entries_per_lane() < avg) t <<= 1;
   pk.tpr = t;
   return pk;
 }

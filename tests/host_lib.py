@@ -25,7 +25,7 @@ def lib():
         L.cpch_rs_coarsen.argtypes = [I, P, P, P, D, P]
         L.cpch_rs_interp.argtypes = [I, P, P, P, D, P, P, P, P]
         L.cpch_rs_interp.restype = ctypes.c_long
-        L.cpch_sweep.argtypes = [I, P, P, P, I, I, P, P, P, P, P, P, P, P, P]
+        L.cpch_sweep.argtypes = [I, P, P, P, I, I, P, P, P, P, P, P, P, P, P, P]
         L.cpch_dense_inverse.argtypes = [I, P, P, P, P]
         _lib = L
     return _lib
@@ -66,17 +66,17 @@ def sweep(n, rp, ci, v, forward, R):
     sizes = np.zeros(6, np.int32)
     L = lib()
     L.cpch_sweep(n, _p(rp), _p(ci), _p(v), int(forward), int(R), _p(sizes), None, None, None, None, None, None,
-                 None, None)
+                 None, None, None)
     nblk, nl, nw = int(sizes[0]), int(sizes[1]), int(sizes[2])
     out = {
         "perm": np.empty(n, np.int32), "blk_beg": np.empty(nblk, np.int32), "blk_end": np.empty(nblk, np.int32),
         "lvl_ptr": np.empty(nl + 1, np.int32), "wait_ptr": np.empty(nl + 1, np.int32),
         "wait_blk": np.empty(max(nw, 1), np.int32), "wait_need": np.empty(max(nw, 1), np.int32),
-        "publish": np.empty(max(nl, 1), np.int32),
+        "publish": np.empty(max(nl, 1), np.int32), "blk_row": np.empty(nblk + 1, np.int32),
     }
     L.cpch_sweep(n, _p(rp), _p(ci), _p(v), int(forward), int(R), _p(sizes), _p(out["perm"]), _p(out["blk_beg"]),
                  _p(out["blk_end"]), _p(out["lvl_ptr"]), _p(out["wait_ptr"]), _p(out["wait_blk"]),
-                 _p(out["wait_need"]), _p(out["publish"]))
+                 _p(out["wait_need"]), _p(out["publish"]), _p(out["blk_row"]))
     out.update(nblk=nblk, nlev=nl, nwait=nw, global_depth=int(sizes[3]), max_local=int(sizes[4]),
                R=int(sizes[5]))
     out["wait_blk"] = out["wait_blk"][:nw]
@@ -97,8 +97,9 @@ def check_sweep_schedule(n, rp, ci, s, forward):
     earlier local level of the same block or a row of a block taken earlier whose
     completion the block has waited for, and (c) every wait can be met (the awaited
     block publishes a progress value at least as large). Returns the number of waits."""
-    R, nblk = s["R"], s["nblk"]
+    nblk = s["nblk"]
     perm, lp = s["perm"], s["lvl_ptr"]
+    blk_of = np.repeat(np.arange(nblk), np.diff(s["blk_row"]))
     row_blk = np.full(n, -1, np.int64)
     row_lev = np.full(n, -1, np.int64)
     final_pub = np.zeros(nblk, np.int64)
@@ -107,7 +108,7 @@ def check_sweep_schedule(n, rp, ci, s, forward):
             m = lv - s["blk_beg"][b]
             rows = perm[lp[lv]:lp[lv + 1]]
             assert rows.size > 0
-            assert np.all(rows // R == b), "row outside its block"
+            assert np.all(blk_of[rows] == b), "row outside its block"
             assert np.all(row_blk[rows] == -1), "row processed twice"
             row_blk[rows] = b
             row_lev[rows] = m
