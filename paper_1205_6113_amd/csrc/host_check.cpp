@@ -51,13 +51,14 @@ long cpch_rs_interp(int n, const int* rp, const int* ci, const double* v, double
   return (long)P.nnz();
 }
 
-// Sweep schedule: sizes[0..5] = nblk, nlev_total, nwait, global_depth, max_local_levels, R.
-// Arrays may be null on a first call that only asks for sizes.
-int cpch_sweep(int n, const int* rp, const int* ci, const double* v, int forward, int R, int* sizes, int* perm,
+// Sweep schedule: sizes[0..6] = nblk, nlev_total, nwait, global_depth, max_local_levels, R,
+// max_level_entries. Arrays may be null on a first call that only asks for sizes.
+int cpch_sweep(int n, const int* rp, const int* ci, const double* v, int forward, int R, int max_entries,
+               int* sizes, int* perm,
                int* blk_beg, int* blk_end, int* lvl_ptr, int* wait_ptr, int* wait_blk, int* wait_need, int* publish,
                int* blk_row) {
   HostCsr a = make_csr(n, rp, ci, v);
-  cpc::SweepSchedule s = cpc::build_sweep(a, forward != 0, R);
+  cpc::SweepSchedule s = cpc::build_sweep(a, forward != 0, R, max_entries);
   const int nl = (int)s.lvl_ptr.size() - 1;
   sizes[0] = s.nblk;
   sizes[1] = nl;
@@ -65,6 +66,7 @@ int cpch_sweep(int n, const int* rp, const int* ci, const double* v, int forward
   sizes[3] = s.global_depth;
   sizes[4] = s.max_local_levels;
   sizes[5] = s.R;
+  sizes[6] = (int)s.max_level_entries;
   if (perm) std::memcpy(perm, s.perm.data(), sizeof(int) * s.perm.size());
   if (blk_beg) std::memcpy(blk_beg, s.blk_beg.data(), sizeof(int) * s.nblk);
   if (blk_end) std::memcpy(blk_end, s.blk_end.data(), sizeof(int) * s.nblk);

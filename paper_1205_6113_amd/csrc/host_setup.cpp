@@ -388,7 +388,7 @@ std::vector<int> sweep_block_starts(const HostCsr& a, int R) {
   return starts;
 }
 
-SweepSchedule build_sweep(const HostCsr& a, bool forward, int R) {
+SweepSchedule build_sweep(const HostCsr& a, bool forward, int R, int64_t max_entries) {
   SweepSchedule s;
   const int n = a.n;
   s.n = n;
@@ -400,7 +400,9 @@ SweepSchedule build_sweep(const HostCsr& a, bool forward, int R) {
   std::vector<int> blk_of(n);
   for (int b = 0; b < s.nblk; ++b)
     for (int i = s.blk_row[b]; i < s.blk_row[b + 1]; ++i) blk_of[i] = b;
-  std::vector<int> lev(n, 0), glev(n, 0);
+  std::vector<int> lev(n, 0), glev(n, 0), ndep(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) ndep[i] += forward ? (a.ci[p] < i) : (a.ci[p] > i);
   // global depth of every row in the sweep's own direction
   if (forward) {
     for (int i = 0; i < n; ++i) {
@@ -440,11 +442,38 @@ SweepSchedule build_sweep(const HostCsr& a, bool forward, int R) {
     uniq.assign(glev.begin() + r0, glev.begin() + r1);
     std::sort(uniq.begin(), uniq.end());
     uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-    const int nl = (int)uniq.size();
+    const int nu = (int)uniq.size();
     for (int i = r0; i < r1; ++i) lev[i] = (int)(std::lower_bound(uniq.begin(), uniq.end(), glev[i]) - uniq.begin());
-    rows_at.assign(nl, {});
-    waits_at.assign(nl, {});
+    rows_at.assign(nu, {});
     for (int i = r0; i < r1; ++i) rows_at[lev[i]].push_back(i);
+    // cut levels with too many dependency entries (rows of one level are independent)
+    {
+      std::vector<std::vector<int>> cut;
+      for (auto& rows : rows_at) {
+        cut.emplace_back();
+        int64_t ent = 0;
+        for (int i : rows) {
+          const int64_t e = ndep[i];
+          if (max_entries > 0 && !cut.back().empty() && ent + e > max_entries) {
+            cut.emplace_back();
+            ent = 0;
+          }
+          cut.back().push_back(i);
+          ent += e;
+        }
+      }
+      rows_at.swap(cut);
+      for (auto& rows : rows_at) {
+        if (rows.size() < 2) continue;
+        int64_t ent = 0;
+        for (int i : rows) ent += ndep[i];
+        s.max_level_entries = std::max(s.max_level_entries, ent);
+      }
+    }
+    const int nl = (int)rows_at.size();
+    for (int m = 0; m < nl; ++m)
+      for (int i : rows_at[m]) lev[i] = m;
+    waits_at.assign(nl, {});
     for (int i = r0; i < r1; ++i) {
       if (forward) {
         for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < r0; ++p) {

@@ -55,13 +55,18 @@ struct SweepSchedule {
   std::vector<int> publish;   // nlev: 1 if some block waits for this level's completion
   int global_depth = 0;       // number of level sets of the whole dependency graph
   int max_local_levels = 0;
+  int64_t max_level_entries = 0;  // most dependency entries of one level with two or more rows
 };
 
 // Build the schedule of the lower (forward) or upper (backward) sweep of a with
 // blocks of at most R rows. Block boundaries are moved back (by at most R/2) to a
 // row that is not coupled to the row before it, so that a block's first rows do not
-// depend on the last (deepest) rows of the previous block.
-SweepSchedule build_sweep(const HostCsr& a, bool forward, int R);
+// depend on the last (deepest) rows of the previous block. With max_entries > 0, a
+// level whose rows hold more dependency entries (entries left of the diagonal for the
+// forward direction, right of it for the backward one) is cut into consecutive levels
+// of at most max_entries entries each; a single row longer than that forms a level of
+// its own.
+SweepSchedule build_sweep(const HostCsr& a, bool forward, int R, int64_t max_entries = 0);
 
 // Block starts used by build_sweep (size nblk + 1, last = n).
 std::vector<int> sweep_block_starts(const HostCsr& a, int R);

@@ -27,34 +27,35 @@ enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_MAXIT = 2, DONE_BREAKDOWN = 3,
 
 // Device counters shared by every persistent sweep launch (self-resetting).
 struct SweepSync {
-  unsigned* ticket;    // [1]
-  unsigned* exited;    // [1]
-  unsigned* err;       // [1] set when a wait exceeded its bound
-  unsigned* progress;  // [max blocks]
+  unsigned* ticket;  // [1]
+  unsigned* exited;  // [1]
+  unsigned* err;     // [1] set when a wait for another block's row exceeded its bound
 };
 
-// One level-scheduled sweep over a matrix (see SweepSchedule in host_setup.hpp).
+// Not-yet-solved marker of a sweep's output: signalling-NaN bit patterns, which no
+// arithmetic result takes (arithmetic only produces quiet NaNs).
+constexpr unsigned long long kSentinel64 = 0x7FF4DEADBEEF0001ull;
+constexpr unsigned kSentinel32 = 0x7FA5DEADu;
+
+// One level-scheduled triangular solve (see SweepSchedule in host_setup.hpp).
 struct SweepDev {
   int n, R, nblk, nlev;  // R: rows of the largest block
-  const int* perm;
-  const int* blk_row;   // nblk + 1 row starts of the blocks
-  const int* blk_beg;
+  const int* blk_row;    // nblk + 1 row starts of the blocks
+  const int* blk_beg;    // first level of each block
   const int* blk_end;
-  const int* lvl_ptr;
-  const int* wait_ptr;
-  const int* wait_blk;
-  const int* wait_need;
-  const int* publish;
-  int tpr;      // lanes per row
-  int nthreads; // threads per workgroup
-  int grid;     // workgroups launched
+  const int* lvl_ptr;    // level -> first position in processing order
+  int pcap;              // product slots per workgroup (largest entry count of a level with two or more rows)
+  int maxl;              // most levels of one block
+  int lds;               // dynamic LDS bytes of one workgroup
+  int off_xs, off_rows, off_ptr, off_lvt;  // byte offsets of the LDS arrays (products start at 0)
+  int grid;              // workgroups launched
 };
 
 enum SweepOp {
-  SWEEP_FGS0 = 0,    // x = (D+L)^{-1} f                           (forward)
-  SWEEP_BGS_IP = 1,  // one backward Gauss-Seidel sweep on A x = f in place (backward)
-  SWEEP_ILU_L = 2,   // y = L^{-1} f, L unit lower                  (forward)
-  SWEEP_ILU_U = 3    // w = U^{-1} f, out = base + w                (backward)
+  SWEEP_LOWER = 0,       // x = (D+L)^{-1} f                         (forward)
+  SWEEP_UPPER = 1,       // x = (D+U)^{-1} f                         (backward)
+  SWEEP_UNIT_LOWER = 2,  // x = (I+L)^{-1} f                         (forward)
+  SWEEP_UPPER_OUT = 3    // x = (D+U)^{-1} f, out = base + x         (backward)
 };
 
 struct MatDev {  // CSR on the device; values of type T
@@ -123,22 +124,26 @@ void launch_bupdate_p(hipStream_t s, const BatchDev& bd, const double* z, double
 void launch_binit(hipStream_t s, const BatchDev& bd, const double* b, double* x, double* r);
 void launch_bdense(hipStream_t s, const DenseListDev& dl, const void* f, void* e, bool fp32, const int* done);
 
-// Rows of one sweep packed in processing order (see sweep.hip).
+// Rows of one triangular solve packed in processing order (see sweep.hip).
 struct SweepPackDev {
   const int* row;    // [n] row of the p-th processed row
-  const int* ptr;    // [n+1] entries of processed row p: [ptr[p], ptr[p+1])
-  const int* col;    // entry columns
+  const int* ptr;    // [n+1] dependency entries of processed row p: [ptr[p], ptr[p+1])
+  const int* col;    // entry column: j - (first row of the block) for a column in the row's own
+                     // block, -(j + 1) for a column in another block
   const void* val;   // entry values (FP64 or FP32)
-  const void* diag;  // [n] diagonal of processed row p (unused by the ILU L solve)
-  int tpr;           // lanes per row for this sweep
+  const void* diag;  // [n] diagonal of processed row p (unused by the unit lower solve)
+  int tb;            // lanes that sum one row's products
 };
 
-// Persistent block-pipelined sweep over packed rows with prefetching (sweep.hip).
-void launch_sweep_packed(hipStream_t s, int op, const SweepDev& sw, const SweepPackDev& pk, int n, bool fp32,
+// Persistent block-pipelined triangular solve over packed rows (sweep.hip). x must
+// hold the sentinel in rows [0, sw.n) (launch_fill_sentinel) when it starts.
+void launch_sweep_packed(hipStream_t s, int op, const SweepDev& sw, const SweepPackDev& pk, bool fp32,
                          const void* f, void* x, const void* base, void* out, const SweepSync& sync,
                          const int* done, long spin_limit);
+void launch_fill_sentinel(hipStream_t s, int n, void* x, bool fp32, const int* done);
 int sweep_max_rows_per_block();
-int sweep_entries_per_lane();
+int sweep_lds_budget();      // dynamic LDS bytes a sweep workgroup may use
+int sweep_threads();         // threads per sweep workgroup
 
 // e = inv f with a dense row-major inverse (coarsest level, FP64).
 void launch_dense_matvec(hipStream_t s, int n, const double* inv, const void* f, bool ff32, void* e, bool ef32,

@@ -106,7 +106,8 @@ struct Level {
   std::vector<int> cf;
   DevCsr A, P, R;
   DevSweepSched lower, upper;
-  SweepPackDev fgs{}, bgs{};  // forward GS (lower entries), backward GS (all off-diagonal entries)
+  SweepPackDev fgs{}, bgs{};  // (D+L) and (D+U) solves of the smoothed rows
+  DevCsr Ls;                  // strict lower triangle of the smoothed rows
   int nS = 0;                 // leading rows that are smoothed (systems not at their coarsest level)
   int64_t nnzS = 0;           // nonzeros of those rows
   DenseListDev dense{};       // systems whose coarsest level is this one (exact solve)
@@ -114,6 +115,7 @@ struct Level {
   void* f = nullptr;  // level vectors (coarse levels), element type = preconditioner precision
   void* u = nullptr;
   void* r = nullptr;
+  void* t = nullptr;  // right-hand side of the backward sweep
 };
 
 }  // namespace cpc
@@ -145,7 +147,6 @@ struct cpc_solver {
   hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph_src[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   double* graph_x[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // x bound into each graph
-  int max_nblk = 1;
   const double* op_vals = nullptr;  // values PCG multiplies by (null: the setup matrix)
   // batch of independent systems (cpc_setup_batch)
   bool batch = false;
@@ -293,35 +294,67 @@ static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncol
   return ok;
 }
 
-static int choose_block_rows(int n, double avg_row) {
-  // One workgroup per block. Up to the LDS limit a single block keeps every
-  // dependency inside one workgroup; beyond it, the largest blocks that fit, since a
-  // block of 8192 rows already holds more rows per level than its workers take in
-  // one pass and fewer blocks means fewer cross-workgroup hand-offs.
-  (void)avg_row;
-  return std::min(n, sweep_max_rows_per_block());
+static size_t esz_of(const cpc_solver* h) { return h->f32 ? sizeof(float) : sizeof(double); }
+
+static void* valloc(cpc_solver* h, int n) {
+  if (h->f32) return dalloc<float>(n, h->owned);
+  return dalloc<double>(n, h->owned);
 }
 
-static void upload_sweep(cpc_solver* h, const SweepSchedule& s, DevSweepSched& d, double avg_half_row) {
-  d.global_depth = s.global_depth;
-  SweepDev& sd = d.d;
+static int choose_block_rows(int n) {
+  // One workgroup per block. Up to 8192 rows a single block keeps every dependency
+  // inside one workgroup; beyond that, blocks of 4096 rows leave LDS room for the
+  // products of a level and give larger levels a workgroup per compute unit.
+  return n <= sweep_max_rows_per_block() ? n : 4096;
+}
+
+// LDS layout of a sweep workgroup: products | solved values | rows | entry offsets |
+// level table. Returns the bytes used.
+static int sweep_layout(const SweepSchedule& s, int esz, int pcap, SweepDev& sd) {
+  auto al = [](int64_t v) { return (int)((v + 15) & ~int64_t(15)); };
+  sd.pcap = pcap;
+  sd.off_xs = al(8 * (int64_t)pcap);
+  sd.off_rows = sd.off_xs + al((int64_t)esz * s.R);
+  sd.off_ptr = sd.off_rows + al(4 * (int64_t)s.R);
+  sd.off_lvt = sd.off_ptr + al(4 * ((int64_t)s.R + 1));
+  sd.lds = sd.off_lvt + al(4 * ((int64_t)s.max_local_levels + 1));
+  return sd.lds;
+}
+
+// Schedule of one triangular solve of `a` (forward: lower, backward: upper) in blocks
+// of at most R rows, uploaded, with levels cut so that their products fit the LDS the
+// block's other arrays leave.
+static SweepSchedule make_sweep(cpc_solver* h, const HostCsr& a, bool forward, int R, DevSweepSched& d) {
+  const int esz = (int)esz_of(h);
+  const int budget = sweep_lds_budget();
+  const int nt = sweep_threads();
+  SweepSchedule s = build_sweep(a, forward, R, 0);
+  SweepDev sd{};
+  int room = (budget - 16 - sweep_layout(s, esz, 0, sd)) / 8;
+  if (room < nt) throw HipError{hipErrorInvalidValue, "sweep block too large for LDS"};
+  int64_t cap = s.max_level_entries;
+  for (int tries = 0; cap > room; ++tries) {
+    // cutting levels adds levels to the level table: leave some slack and retry
+    cap = std::max<int64_t>(nt, (int64_t)(0.9 * room));
+    s = build_sweep(a, forward, R, cap);
+    room = (budget - 16 - sweep_layout(s, esz, 0, sd)) / 8;
+    if (room < nt || tries > 6) throw HipError{hipErrorInvalidValue, "sweep levels do not fit LDS"};
+  }
+  const int pcap = (int)std::max<int64_t>(nt, std::max<int64_t>(cap, s.max_level_entries));
+  if (sweep_layout(s, esz, pcap, sd) > budget) throw HipError{hipErrorInvalidValue, "sweep LDS layout over budget"};
   sd.n = s.n;
   sd.R = s.R;
   sd.nblk = s.nblk;
   sd.nlev = (int)s.lvl_ptr.size() - 1;
-  sd.perm = dupload(s.perm, h->owned, h->stream);
+  sd.maxl = s.max_local_levels;
   sd.blk_row = dupload(s.blk_row, h->owned, h->stream);
   sd.blk_beg = dupload(s.blk_beg, h->owned, h->stream);
   sd.blk_end = dupload(s.blk_end, h->owned, h->stream);
   sd.lvl_ptr = dupload(s.lvl_ptr, h->owned, h->stream);
-  sd.wait_ptr = dupload(s.wait_ptr, h->owned, h->stream);
-  sd.wait_blk = dupload(s.wait_blk, h->owned, h->stream);
-  sd.wait_need = dupload(s.wait_need, h->owned, h->stream);
-  sd.publish = dupload(s.publish, h->owned, h->stream);
-  sd.tpr = pick_tpr(avg_half_row);
-  sd.nthreads = 256;
   sd.grid = std::min(s.nblk, 1024);
-  h->max_nblk = std::max(h->max_nblk, s.nblk);
+  d.d = sd;
+  d.global_depth = s.global_depth;
+  return s;
 }
 
 static void spmv_or_throw(cpc_solver* h, const MatDev& A, int mode, const void* x, bool xf32, const void* f,
@@ -330,13 +363,15 @@ static void spmv_or_throw(cpc_solver* h, const MatDev& A, int mode, const void* 
     throw HipError{hipErrorInvalidValue, "unsupported SpMV precision combination"};
 }
 
-// Pack the rows a sweep touches in its processing order. kind 0: entries left of the
-// diagonal; 1: right of the diagonal; 2: every off-diagonal entry. share: reuse the
-// row/ptr/col arrays of a pack with the same schedule and kind (values differ).
+// Pack the rows of a triangular solve in its processing order: the dependency entries
+// (left of the diagonal forward, right of it backward) with columns in the row's own
+// block stored block-relative and the others as -(j + 1). share: reuse the row/ptr/col
+// arrays of a pack with the same schedule and direction (values differ).
 static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vector<double>& vals,
-                               const SweepSchedule& s, int kind, const SweepPackDev* share) {
+                               const SweepSchedule& s, const SweepPackDev* share) {
   SweepPackDev pk{};
   const int n = a.n;
+  const bool fwd = s.forward;
   std::vector<int> ptr(n + 1, 0);
   std::vector<double> diag(n, 1.0);
   for (int p = 0; p < n; ++p) {
@@ -345,20 +380,25 @@ static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vecto
     for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
       const int j = a.ci[q];
       if (j == i) diag[p] = vals[q];
-      else if ((kind == 0 && j < i) || (kind == 1 && j > i) || kind == 2) ++c;
+      else if (fwd ? j < i : j > i) ++c;
     }
     ptr[p + 1] = ptr[p] + c;
   }
-  std::vector<int> col((size_t)ptr[n]);
-  std::vector<double> v((size_t)ptr[n]);
-  for (int p = 0; p < n; ++p) {
-    const int i = s.perm[p];
-    int w = ptr[p];
-    for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
-      const int j = a.ci[q];
-      if (j == i) continue;
-      if ((kind == 0 && j < i) || (kind == 1 && j > i) || kind == 2) {
-        col[w] = j;
+  const int64_t ne = ptr[n];
+  std::vector<int> col((size_t)std::max<int64_t>(ne, 1), 0);
+  std::vector<double> v((size_t)std::max<int64_t>(ne, 1), 0.0);
+  {
+    std::vector<int> blk_of(n);
+    for (int b = 0; b < s.nblk; ++b)
+      for (int i = s.blk_row[b]; i < s.blk_row[b + 1]; ++i) blk_of[i] = b;
+    for (int p = 0; p < n; ++p) {
+      const int i = s.perm[p];
+      const int b = blk_of[i];
+      int w = ptr[p];
+      for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
+        const int j = a.ci[q];
+        if (j == i || !(fwd ? j < i : j > i)) continue;
+        col[w] = (blk_of[j] == b) ? j - s.blk_row[b] : -(j + 1);
         v[w] = vals[q];
         ++w;
       }
@@ -381,26 +421,37 @@ static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vecto
     pk.val = dupload(v, h->owned, h->stream);
     pk.diag = dupload(diag, h->owned, h->stream);
   }
-  const double avg = n ? (double)ptr[n] / n : 0.0;
-  // enough lanes that an average row fits the entries each lane prefetches
+  // lanes per row in the summing phase: about eight products per lane
+  const double avg = n ? (double)ne / n : 0.0;
   int t = 1;
-  while (t < 64 && t * sweep_entries_per_lane() < avg) t <<= 1;
-  pk.tpr = t;
+  while (t < 64 && t * 8 < avg) t <<= 1;
+  pk.tb = t;
   return pk;
 }
 
+// x = T^{-1} f for the triangular factor the pack holds (out = base + x for
+// SWEEP_UPPER_OUT). x is first filled with the not-yet-solved marker.
 static void run_sweep(cpc_solver* h, int op, const DevSweepSched& sch, const SweepPackDev& pk, const void* f,
                       void* x, const void* base, void* out, const int* done) {
-  SweepDev sd = sch.d;
-  sd.tpr = pk.tpr;
-  launch_sweep_packed(h->stream, op, sd, pk, sd.n, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
+  launch_fill_sentinel(h->stream, sch.d.n, x, h->f32, done);
+  launch_sweep_packed(h->stream, op, sch.d, pk, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
 }
 
-static size_t esz_of(const cpc_solver* h) { return h->f32 ? sizeof(float) : sizeof(double); }
-
-static void* valloc(cpc_solver* h, int n) {
-  if (h->f32) return dalloc<float>(n, h->owned);
-  return dalloc<double>(n, h->owned);
+// Strict lower triangle of a (the old-value part of a backward Gauss-Seidel sweep).
+static HostCsr strict_lower(const HostCsr& a) {
+  HostCsr t;
+  t.n = a.n;
+  t.ncols = a.ncols;
+  t.rp.assign(1, 0);
+  for (int i = 0; i < a.n; ++i) {
+    for (int q = a.rp[i]; q < a.rp[i + 1]; ++q)
+      if (a.ci[q] < i) {
+        t.ci.push_back(a.ci[q]);
+        t.v.push_back(a.v[q]);
+      }
+    t.rp.push_back((int)t.ci.size());
+  }
+  return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -561,18 +612,18 @@ static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_o
     const int rows = (d == 0) ? ntot[0] : L.nS;
     if (rows > 0) {
       HostCsr sub = (rows == ntot[d]) ? A : leading_rows(A, rows);
-      const double avg_half = 0.5 * ((double)sub.nnz() / std::max(1, rows) - 1.0) + 1.0;
-      const int Rb = o.sweep_block_rows > 0 ? std::min(o.sweep_block_rows, 8192) : choose_block_rows(rows, avg_half);
-      SweepSchedule lo = build_sweep(sub, true, Rb);
-      SweepSchedule up = build_sweep(sub, false, Rb);
-      upload_sweep(h, lo, L.lower, avg_half);
-      upload_sweep(h, up, L.upper, avg_half);
-      L.fgs = build_pack(h, sub, sub.v, lo, 0, nullptr);
-      L.bgs = build_pack(h, sub, sub.v, up, 2, nullptr);
+      const int Rb = o.sweep_block_rows > 0 ? std::min(o.sweep_block_rows, sweep_max_rows_per_block())
+                                            : choose_block_rows(rows);
+      SweepSchedule lo = make_sweep(h, sub, true, Rb, L.lower);
+      SweepSchedule up = make_sweep(h, sub, false, Rb, L.upper);
+      L.fgs = build_pack(h, sub, sub.v, lo, nullptr);
+      L.bgs = build_pack(h, sub, sub.v, up, nullptr);
       if (d == 0) {
-        h->ilu_l = build_pack(h, sub, h->lu_host, lo, 0, &L.fgs);
-        h->ilu_u = build_pack(h, sub, h->lu_host, up, 1, nullptr);
+        h->ilu_l = build_pack(h, sub, h->lu_host, lo, &L.fgs);
+        h->ilu_u = build_pack(h, sub, h->lu_host, up, &L.bgs);
       }
+      upload_csr(h, strict_lower(sub), L.Ls, false);
+      L.t = valloc(h, rows);
       L.r = valloc(h, rows);
     }
     if (d > 0) {
@@ -608,7 +659,6 @@ static void allocate_work(cpc_solver* h) {
   h->sync.ticket = dalloc<unsigned>(1, h->owned);
   h->sync.exited = dalloc<unsigned>(1, h->owned);
   h->sync.err = dalloc<unsigned>(1, h->owned);
-  h->sync.progress = dalloc<unsigned>(h->max_nblk, h->owned);
   for (void* v : {h->pin, h->u1, h->u2, h->res, h->y, h->w, h->t})
     HIPCHK(hipMemsetAsync(v, 0, esz_of(h) * (size_t)n, h->stream));
   for (void* v : {(void*)h->r, (void*)h->z, (void*)h->p, (void*)h->q, (void*)h->z64tmp})
@@ -616,13 +666,13 @@ static void allocate_work(cpc_solver* h) {
   for (auto& L : h->lev) {
     for (void* v : {L.f, L.u})
       if (v) HIPCHK(hipMemsetAsync(v, 0, esz_of(h) * (size_t)L.A.n, h->stream));
-    if (L.r) HIPCHK(hipMemsetAsync(L.r, 0, esz_of(h) * (size_t)L.lower.d.n, h->stream));
+    for (void* v : {L.r, L.t})
+      if (v) HIPCHK(hipMemsetAsync(v, 0, esz_of(h) * (size_t)L.lower.d.n, h->stream));
   }
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(PcgState), h->stream));
   HIPCHK(hipMemsetAsync(h->sync.ticket, 0, sizeof(unsigned), h->stream));
   HIPCHK(hipMemsetAsync(h->sync.exited, 0, sizeof(unsigned), h->stream));
   HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
-  HIPCHK(hipMemsetAsync(h->sync.progress, 0, sizeof(unsigned) * h->max_nblk, h->stream));
 }
 
 // Per-system scalars and chunk tables of a batch.
@@ -676,7 +726,7 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
     Level& C = h->lev[d + 1];
     const MatDev A = smoothed(L.A, L.nS, f32);
     // (1) pre-smoothing from zero: u = (D+L)^{-1} f
-    run_sweep(h, SWEEP_FGS0, L.lower, L.fgs, f, u, nullptr, nullptr, done);
+    run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, done);
     // (2a) f_c = R (f - A u)
     spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);
     spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
@@ -684,8 +734,10 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
     vcycle(h, d + 1, C.f, C.u, done);
     // (2c) u += P e
     spmv_or_throw(h, L.P.mat(f32), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);
-    // (3) post-smoothing: one backward Gauss-Seidel sweep in place (S_l^T)
-    run_sweep(h, SWEEP_BGS_IP, L.upper, L.bgs, f, u, nullptr, nullptr, done);
+    // (3) post-smoothing, one backward Gauss-Seidel sweep (S_l^T): the new u solves
+    //     (D+U) u = f - L u_old, the strict lower part taken at the old values
+    spmv_or_throw(h, L.Ls.mat(f32), 1, u, f32, f, f32, L.t, f32, L.Ls.tpr, done);
+    run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, L.t, u, nullptr, nullptr, done);
   }
   // systems whose coarsest level is this one: e = A_0^{-1} f (FP64 inverse)
   if (L.dense.nblk > 0) launch_bdense(h->stream, L.dense, f, u, f32, done);
@@ -694,8 +746,8 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
 // z = (LU)^{-1} f (out = nullptr) or out = base + (LU)^{-1} f
 static void ilu_apply(cpc_solver* h, const void* f, void* w, const void* base, void* out, const int* done) {
   Level& L = h->lev[0];
-  run_sweep(h, SWEEP_ILU_L, L.lower, h->ilu_l, f, h->y, nullptr, nullptr, done);
-  run_sweep(h, SWEEP_ILU_U, L.upper, h->ilu_u, h->y, w, base, out, done);
+  run_sweep(h, SWEEP_UNIT_LOWER, L.lower, h->ilu_l, f, h->y, nullptr, nullptr, done);
+  run_sweep(h, out ? SWEEP_UPPER_OUT : SWEEP_UPPER, L.upper, h->ilu_u, h->y, w, base, out, done);
 }
 
 // res = r - A u with FP64 A and FP64 r (outer residual of Algorithm 2.1)
@@ -761,15 +813,9 @@ static void apply_op(cpc_solver* h, int op, const double* r, double* z, const in
     case CPC_OP_FGS:
     case CPC_OP_BGS: {
       Level& L = h->lev[0];
-      const MatDev A = L.A.mat(f32);
-      (void)A;
-      if (op == CPC_OP_FGS) {
-        run_sweep(h, SWEEP_FGS0, L.lower, L.fgs, rin, h->u1, nullptr, nullptr, done);
-      } else {
-        // (D+U)^{-1} f = one backward sweep in place from a zero start
-        launch_vec(h->stream, 3, n, nullptr, false, nullptr, false, h->u1, f32, done);
-        run_sweep(h, SWEEP_BGS_IP, L.upper, L.bgs, rin, h->u1, nullptr, nullptr, done);
-      }
+      // (D+L)^{-1} f and (D+U)^{-1} f: one forward or backward sweep from a zero start
+      if (op == CPC_OP_FGS) run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, rin, h->u1, nullptr, nullptr, done);
+      else run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, rin, h->u1, nullptr, nullptr, done);
       launch_vec(h->stream, 2, n, h->u1, f32, nullptr, false, z, false, done);
       break;
     }
@@ -817,11 +863,12 @@ static double vcycle_bytes(const cpc_solver* h) {
       const double nz = (double)L.nnzS, n = L.nS, nc = h->lev[d + 1].A.n;
       const double p = (double)L.P.nnz;
       const double half = 0.5 * (nz - n);
-      b += (half + n) * mb + 4.0 * n + 3.0 * vb * n;          // forward GS from zero
-      b += nz * mb + 4.0 * n + 3.0 * vb * n;                  // residual
-      b += p * mb + 4.0 * nc + vb * n + vb * nc;              // restriction
-      b += p * mb + 4.0 * n + 2.0 * vb * n + vb * nc;         // prolongation + correction
-      b += nz * mb + 4.0 * n + 3.0 * vb * n;                  // backward GS in place
+      b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + forward GS from zero
+      b += nz * mb + 4.0 * n + 3.0 * vb * n;                   // residual
+      b += p * mb + 4.0 * nc + vb * n + vb * nc;               // restriction
+      b += p * mb + 4.0 * n + 2.0 * vb * n + vb * nc;          // prolongation + correction
+      b += half * mb + 4.0 * n + 3.0 * vb * n;                 // f - L u (old values)
+      b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + (D+U) solve
     }
     for (int n0 : L.dense_n) b += 8.0 * n0 * n0 + 2.0 * vb * n0;  // exact coarsest solves
   }
@@ -840,8 +887,8 @@ static double kernel_bytes(const cpc_solver* h, int kernel, int d) {
   const double p = (double)L.P.nnz;
   switch (kernel) {
     case CPC_K_SPMV_PQ: return 12.0 * nz + 4.0 * n + 16.0 * n;
-    case CPC_K_FGS: return (half + n) * mb + 4.0 * n + 3.0 * vb * n;
-    case CPC_K_BGS: return nz * mb + 4.0 * n + 3.0 * vb * n;
+    case CPC_K_FGS: return (half + n) * mb + 4.0 * n + 2.0 * vb * n;
+    case CPC_K_BGS: return (half + n) * mb + 4.0 * n + 2.0 * vb * n;
     case CPC_K_ILU_L: return half * mb + 4.0 * n + 2.0 * vb * n;
     case CPC_K_ILU_U: return (half + n) * mb + 4.0 * n + 4.0 * vb * n;
     case CPC_K_RESIDUAL: return nz * mb + 4.0 * n + 3.0 * vb * n;
@@ -856,7 +903,8 @@ static double prec_bytes(const cpc_solver* h, int prec) {
   const double mb = h->f32 ? 8.0 : 12.0;
   const double nz = (double)h->lev[0].A.nnz, n = h->n;
   const double half = 0.5 * (nz - n);
-  const double ilu = (half * mb + 4.0 * n + 2.0 * vb * n) + ((half + n) * mb + 4.0 * n + 4.0 * vb * n);
+  const double ilu = (half * mb + 4.0 * n + 2.0 * vb * n) + ((half + n) * mb + 4.0 * n + 4.0 * vb * n) +
+                     2.0 * vb * n;  // L and U solves, marker fills
   const double outer = nz * 12.0 + 4.0 * n + 8.0 * n + 2.0 * vb * n;
   const double V = vcycle_bytes(h);
   const double conv = h->f32 ? 12.0 * n : 0.0;
@@ -1381,6 +1429,18 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
     levels.push_back(0);
   }
   const bool f32 = h->f32;
+  const bool tri = kernel == CPC_K_FGS || kernel == CPC_K_BGS || kernel == CPC_K_ILU_L || kernel == CPC_K_ILU_U;
+  // triangular solves are timed launch by launch (event pairs); the rest as one span
+  std::vector<hipEvent_t> evs;
+  bool timing = false;
+  auto ev_begin = [&]() {
+    if (!timing) return;
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    evs.push_back(e);
+    HIPCHK(hipEventRecord(e, h->stream));
+  };
+  auto ev_end = ev_begin;
   auto launch_once = [&](int d) {
     Level& L = h->lev[d];
     const MatDev A = L.A.mat(f32);
@@ -1390,17 +1450,34 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
       case CPC_K_SPMV_PQ:
         launch_spmv_pq(h->stream, L.A.mat(false), h->p, h->q, h->partials, h->st, L.A.tpr);
         break;
+      // triangular solves: the sentinel fill before each launch is not timed
       case CPC_K_FGS:
-        run_sweep(h, SWEEP_FGS0, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
+        launch_fill_sentinel(h->stream, L.lower.d.n, u, f32, nullptr);
+        ev_begin();
+        launch_sweep_packed(h->stream, SWEEP_LOWER, L.lower.d, L.fgs, f32, f, u, nullptr, nullptr, h->sync,
+                            nullptr, h->spin_limit);
+        ev_end();
         break;
       case CPC_K_BGS:
-        run_sweep(h, SWEEP_BGS_IP, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
+        launch_fill_sentinel(h->stream, L.upper.d.n, u, f32, nullptr);
+        ev_begin();
+        launch_sweep_packed(h->stream, SWEEP_UPPER, L.upper.d, L.bgs, f32, f, u, nullptr, nullptr, h->sync,
+                            nullptr, h->spin_limit);
+        ev_end();
         break;
       case CPC_K_ILU_L:
-        run_sweep(h, SWEEP_ILU_L, L.lower, h->ilu_l, h->res, h->y, nullptr, nullptr, nullptr);
+        launch_fill_sentinel(h->stream, L.lower.d.n, h->y, f32, nullptr);
+        ev_begin();
+        launch_sweep_packed(h->stream, SWEEP_UNIT_LOWER, L.lower.d, h->ilu_l, f32, h->res, h->y, nullptr, nullptr,
+                            h->sync, nullptr, h->spin_limit);
+        ev_end();
         break;
       case CPC_K_ILU_U:
-        run_sweep(h, SWEEP_ILU_U, L.upper, h->ilu_u, h->y, h->w, h->u1, h->u2, nullptr);
+        launch_fill_sentinel(h->stream, L.upper.d.n, h->w, f32, nullptr);
+        ev_begin();
+        launch_sweep_packed(h->stream, SWEEP_UPPER_OUT, L.upper.d, h->ilu_u, f32, h->y, h->w, h->u1, h->u2,
+                            h->sync, nullptr, h->spin_limit);
+        ev_end();
         break;
       case CPC_K_RESIDUAL:
         spmv_or_throw(h, smoothed(L.A, L.nS, f32), 1, u, f32, f, f32, L.r, f32, L.A.tpr, nullptr);
@@ -1434,18 +1511,20 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
       HIPCHK(hipStreamSynchronize(h->stream));
     }
     for (int d : levels) launch_once(d);  // warm-up
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, h->stream));
+    timing = true;
+    if (!tri) ev_begin();
     for (int r = 0; r < reps; ++r)
       for (int d : levels) launch_once(d);
-    HIPCHK(hipEventRecord(e1, h->stream));
-    HIPCHK(hipEventSynchronize(e1));
+    if (!tri) ev_end();
+    HIPCHK(hipEventSynchronize(evs.back()));
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (size_t k = 0; k + 1 < evs.size(); k += 2) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, evs[k], evs[k + 1]));
+      ms += t;
+    }
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    evs.clear();
     HIPCHK(hipGetLastError());
     double b = 0.0;
     for (int d : levels) {

@@ -1,28 +1,31 @@
-// Persistent, block-pipelined, level-scheduled triangular sweep with prefetched
-// row data (forward/backward Gauss-Seidel, ILU(0) L and U solves).
+// Persistent, block-pipelined, level-scheduled triangular solve over packed rows:
+// forward (D+L) and (I+L) solves, backward (D+U) solves, the building blocks of the
+// Gauss-Seidel smoother and of ILU(0) application.
 //
-// Each sweep has a packed copy of the rows it touches, in processing order: the
-// p-th processed row is row[p], its dependency-side entries are col/val[ptr[p] ..
-// ptr[p+1]) in column order, its diagonal is diag[p]. A workgroup (4 waves) takes
-// blocks of contiguous rows from a ticket counter in dependency order and stages
-// the block's level table, row list and entry offsets in LDS.
+// Rows are cut into contiguous blocks; a workgroup takes blocks from a ticket counter
+// in dependency order and walks the block's levels (sets of rows whose dependencies
+// all lie in earlier levels or in blocks taken earlier). The block's level table, row
+// list and entry offsets are staged in LDS, and the block's solved values are kept in
+// LDS for the block's own later levels.
 //
-// Waves 1-3 are workers: groups of TPR lanes solve the rows of one level set per
-// step and keep the block's solved values in LDS only. Row data are prefetched
-// kDepth levels ahead into a ring of register slots. Their addresses come from LDS,
-// not from loads still in flight, because the vector-memory counter completes in
-// order: a dependent load chain would drain every younger prefetch. The in-place
-// backward sweep also needs the pre-sweep values of a row's lower neighbours; those
-// are gathered one level ahead.
+// One level takes two phases. Phase A: the level's dependency entries are contiguous
+// in the pack, so the 256 lanes split them evenly, each multiplying its entries by the
+// solved values and writing the products to LDS. Phase B: groups of TB lanes add up
+// one row's products in a fixed order, and the group's first lane divides by the
+// diagonal and stores the value in LDS and in the global vector.
 //
-// Wave 0 is the coordinator. It waits on other blocks' progress counters. After
-// levels another block waits for, and at the end of the block, it copies the rows
-// solved since its last copy from LDS to the global vector with agent-scope
-// (write-through) stores, waits for their completion, and then advances the block's
-// progress counter. Readers of another block's rows use agent-scope loads. No
-// cache-wide release/acquire fences are used: with hundreds of workgroups
-// synchronising every level, L2-wide write-backs and invalidations would dominate.
+// Entry data are prefetched four levels ahead into a ring of register slots, with
+// addresses taken from LDS (the vector-memory counter completes in order, so a load
+// whose address comes from another load in flight would drain every younger
+// prefetch). Values from other blocks are read with agent-scope loads issued two
+// levels ahead. The output vector starts filled with a sentinel bit pattern, so a
+// value that is not the sentinel is final; a read that still finds the sentinel polls
+// the same address until the other block has stored the value (bounded: past the
+// spin limit the error flag is set). No progress counters, cache-wide fences or
+// extra hand-off loads are needed.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "kernels.hpp"
 
@@ -30,48 +33,73 @@ namespace cpc {
 
 namespace {
 
-constexpr int kNT = 256;        // threads per workgroup
-constexpr int kWorkers = 192;   // waves 1-3
-constexpr int kK = 4;           // entries per lane held in a prefetch slot
-constexpr int kLvCap = 4096;    // block level-table entries staged in LDS
+constexpr int kNT = 256;  // threads per workgroup
+constexpr int kKP = 4;    // prefetched entries per lane and level
+constexpr int kBudget = 150 * 1024;
 
+__device__ __forceinline__ bool is_sentinel(double v) {
+  return (unsigned long long)__double_as_longlong(v) == kSentinel64;
+}
+__device__ __forceinline__ bool is_sentinel(float v) { return __float_as_uint(v) == kSentinel32; }
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of W lanes; the total is valid in each group's first lane.
+// Lane exchanges: xor 1, xor 2 (quad permutations), mirror within 8 and within 16
+// (DPP), xor 16 within 32 (swizzle), lane 32 read into lane 0.
 template <int W>
 __device__ __forceinline__ double gsum(double v) {
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+  if constexpr (W >= 2) v += dpp<0xB1>(v);
+  if constexpr (W >= 4) v += dpp<0x4E>(v);
+  if constexpr (W >= 8) v += dpp<0x141>(v);
+  if constexpr (W >= 16) v += dpp<0x140>(v);
+  if constexpr (W >= 32) {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+    v += __hiloint2double(hi, lo);
+  }
+  if constexpr (W >= 64)
+    v += __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                          __builtin_amdgcn_readlane(__double2loint(v), 32));
   return v;
 }
 
 template <typename VT, typename XT>
 struct Slot {
-  int row, e0, e1;
-  VT diag;
-  int col[kK];
-  VT val[kK];
+  int E0, E1, q0, q1;  // level's entry range and row range (block-relative positions)
+  int col[kKP];
+  VT val[kKP];
+  XT xr[kKP];  // values from other blocks (possibly still the sentinel)
+  int row;     // the first-pass row of this lane's group
   XT fv, bv;
-  XT xo[kK];  // pre-sweep values of lower neighbours (in-place backward sweep)
+  VT dg;
 };
 
-template <int OP, int TPR, typename VT, typename XT>
-__global__ __launch_bounds__(kNT) void sweep_kernel5(SweepDev sw, SweepPackDev pk, int n, const XT* __restrict__ f,
-                                                     XT* x, const XT* __restrict__ base, XT* __restrict__ out,
-                                                     SweepSync sy, const int* __restrict__ done, long spin_limit) {
-  constexpr bool FWD = (OP == SWEEP_FGS0 || OP == SWEEP_ILU_L);
-  constexpr bool BGS = (OP == SWEEP_BGS_IP);
-  constexpr int NGRP = kWorkers / TPR;
+template <int OP, int TB, typename VT, typename XT>
+__global__ __launch_bounds__(kNT) void tri_sweep_kernel(SweepDev sw, SweepPackDev pk, const XT* __restrict__ f,
+                                                        XT* x, const XT* __restrict__ base, XT* __restrict__ out,
+                                                        SweepSync sy, const int* __restrict__ done,
+                                                        long spin_limit) {
+  constexpr bool FWD = (OP == SWEEP_LOWER || OP == SWEEP_UNIT_LOWER);
+  constexpr bool UNIT = (OP == SWEEP_UNIT_LOWER);
+  constexpr bool OUT = (OP == SWEEP_UPPER_OUT);
+  constexpr int NG = kNT / TB;
   extern __shared__ unsigned char smem_raw[];
-  XT* xs = reinterpret_cast<XT*>(smem_raw);
-  int* rows_l = reinterpret_cast<int*>(smem_raw + ((sw.R * (int)sizeof(XT) + 15) & ~15));
-  int* ptr_l = rows_l + ((sw.R + 3) & ~3);
-  int* lvt = ptr_l + ((sw.R + 4) & ~3);
+  double* prod = reinterpret_cast<double*>(smem_raw);
+  XT* xs = reinterpret_cast<XT*>(smem_raw + sw.off_xs);
+  int* rows_l = reinterpret_cast<int*>(smem_raw + sw.off_rows);
+  int* ptr_l = reinterpret_cast<int*>(smem_raw + sw.off_ptr);
+  int* lvt = reinterpret_cast<int*>(smem_raw + sw.off_lvt);
   __shared__ int s_tick;
   __shared__ int s_last;
   if (done && *done) return;  // before taking a ticket: the counters stay untouched
   const int tid = threadIdx.x;
-  const bool coord = tid < 64;
-  const int wt = tid - 64;
-  const int lane = coord ? 0 : wt % TPR;
-  const int grp = coord ? 0 : wt / TPR;
+  const int g = tid / TB, lane = tid % TB;
   const VT* __restrict__ pval = reinterpret_cast<const VT*>(pk.val);
   const VT* __restrict__ pdiag = reinterpret_cast<const VT*>(pk.diag);
 
@@ -82,136 +110,137 @@ __global__ __launch_bounds__(kNT) void sweep_kernel5(SweepDev sw, SweepPackDev p
     __syncthreads();
     if (t >= sw.nblk) break;
     const int b = FWD ? t : sw.nblk - 1 - t;
-    const int r0 = sw.blk_row[b];
-    const int r1 = sw.blk_row[b + 1];
+    const int r0 = sw.blk_row[b], r1 = sw.blk_row[b + 1];
     const int nb = r1 - r0;
-    const int lb = sw.blk_beg[b], le = sw.blk_end[b];
-    const int nl = le - lb;
+    const int lb = sw.blk_beg[b];
+    const int nl = sw.blk_end[b] - lb;
     const int P0 = sw.lvl_ptr[lb];
-    for (int q = tid; q <= nl && q <= kLvCap; q += kNT) lvt[q] = sw.lvl_ptr[lb + q] - P0;
+    for (int q = tid; q <= nl; q += kNT) lvt[q] = sw.lvl_ptr[lb + q] - P0;
     for (int q = tid; q < nb; q += kNT) rows_l[q] = pk.row[P0 + q];
     for (int q = tid; q <= nb; q += kNT) ptr_l[q] = pk.ptr[P0 + q];
     __syncthreads();
-    int copied = 0;  // rows (processing order within the block) already copied out
 
-    auto LP = [&](int m) -> int { return m <= kLvCap ? lvt[m] : sw.lvl_ptr[lb + m] - P0; };
-    // issue the loads of this group's first row of level m (addresses from LDS)
+    // loads of level m's entries and of the first-pass row data (addresses from LDS;
+    // out-of-range lanes load a valid dummy address so that every step issues the same
+    // number of loads)
     auto issue = [&](Slot<VT, XT>& s, int m) {
-      s.row = -1;
-      if (coord || m >= nl) return;
-      const int q = LP(m) + grp;
-      if (q >= LP(m + 1)) return;
-      s.row = rows_l[q];
-      s.e0 = ptr_l[q];
-      s.e1 = ptr_l[q + 1];
-      if (OP != SWEEP_ILU_L) s.diag = pdiag[P0 + q];
+      int q0 = 0, q1 = 0, E0 = 0, E1 = 0;
+      if (m < nl) {
+        q0 = lvt[m];
+        q1 = lvt[m + 1];
+        E0 = ptr_l[q0];
+        E1 = ptr_l[q1];
+      }
+      s.E0 = E0;
+      s.E1 = E1;
+      s.q0 = q0;
+      s.q1 = q1;
 #pragma unroll
-      for (int k = 0; k < kK; ++k) {
-        const int e = s.e0 + lane + k * TPR;
-        s.col[k] = -1;
-        if (e < s.e1) {
-          s.col[k] = pk.col[e];
-          s.val[k] = pval[e];
+      for (int k = 0; k < kKP; ++k) {
+        const int e = E0 + tid + k * kNT;
+        const int ec = e < E1 ? e : 0;
+        s.col[k] = pk.col[ec];
+        s.val[k] = pval[ec];
+      }
+      const int q = q0 + g;
+      const int qc = q < q1 ? q : 0;
+      s.row = rows_l[qc];
+      s.fv = f[s.row];
+      if (!UNIT) s.dg = pdiag[P0 + qc];
+      if (OUT) s.bv = base[s.row];
+    };
+    // loads of the values a level reads from other blocks
+    auto issue_remote = [&](Slot<VT, XT>& s) {
+#pragma unroll
+      for (int k = 0; k < kKP; ++k) {
+        const int e = s.E0 + tid + k * kNT;
+        const int c = s.col[k];
+        const int j = (e < s.E1 && c < 0) ? -(c + 1) : 0;
+        s.xr[k] = __hip_atomic_load(x + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    };
+    auto ready = [&](XT v, int j) -> double {
+      long spins = 0;
+      while (is_sentinel(v)) {
+        __builtin_amdgcn_s_sleep(1);
+        v = __hip_atomic_load(x + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (++spins > spin_limit) {
+          atomicOr(sy.err, 1u);
+          return 0.0;
         }
+        if ((spins & 255) == 0 && __hip_atomic_load(sy.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          return 0.0;
       }
-      if (lane == 0) {
-        s.fv = f[s.row];
-        if (OP == SWEEP_ILU_U && out) s.bv = base[s.row];
-      }
+      return (double)v;
     };
-    // in-place backward sweep: pre-sweep values of the row's lower neighbours
-    auto gather_old = [&](Slot<VT, XT>& s) {
-      if (!BGS || coord || s.row < 0) return;
-#pragma unroll
-      for (int k = 0; k < kK; ++k)
-        if (s.col[k] >= 0 && s.col[k] < s.row) s.xo[k] = x[s.col[k]];
-    };
-    auto xnew = [&](int j) -> double {
-      // solved in this block: LDS; solved by an earlier block: agent-scope load
-      const bool local = FWD ? (j >= r0) : (j < r1);
-      if (local) return (double)xs[j - r0];
-      return (double)__hip_atomic_load(x + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    };
-    auto xval = [&](int j, int i) -> double {
-      if (BGS && j < i) return (double)x[j];  // value from before the sweep
-      return xnew(j);
-    };
-    auto finish = [&](int i, double s, double fv, double diag, double bv) {
-      double xi;
-      if (OP == SWEEP_ILU_L) xi = fv - s;
-      else xi = (fv - s) / diag;
+    auto finish = [&](int i, double sum, double fv, double dg, double bv) {
+      const double xi = UNIT ? fv - sum : (fv - sum) / dg;
       const XT xo = (XT)xi;
       xs[i - r0] = xo;
-      if (OP == SWEEP_ILU_U && out) out[i] = (XT)(bv + (double)xo);
+      __hip_atomic_store(x + i, xo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (OUT) out[i] = (XT)(bv + (double)xo);
     };
-    auto consume = [&](const Slot<VT, XT>& s, int m) {
-      if (s.row >= 0) {
-        const int i = s.row;
-        double acc = 0.0;
+    auto consume = [&](const Slot<VT, XT>& s) {
+      const int E0 = s.E0, E1 = s.E1;
+      const bool lng = (E1 - E0) > sw.pcap;  // a level of one row longer than the product slots
+      double part = 0.0;
 #pragma unroll
-        for (int k = 0; k < kK; ++k) {
-          if (s.col[k] < 0) continue;
-          const double xj = (BGS && s.col[k] < i) ? (double)s.xo[k] : xnew(s.col[k]);
-          acc += (double)s.val[k] * xj;
+      for (int k = 0; k < kKP; ++k) {
+        const int e = E0 + tid + k * kNT;
+        if (e < E1) {
+          const int c = s.col[k];
+          const double xv = c >= 0 ? (double)xs[c] : ready(s.xr[k], -(c + 1));
+          const double pr = (double)s.val[k] * xv;
+          if (lng) part += pr;
+          else prod[e - E0] = pr;
         }
-        for (int e = s.e0 + lane + kK * TPR; e < s.e1; e += TPR) acc += (double)pval[e] * xval(pk.col[e], i);
-        acc = gsum<TPR>(acc);
-        if (lane == 0)
-          finish(i, acc, (double)s.fv, OP == SWEEP_ILU_L ? 1.0 : (double)s.diag,
-                 OP == SWEEP_ILU_U ? (double)s.bv : 0.0);
       }
-      // rows beyond the first NGRP of this level (not prefetched)
-      const int q1 = LP(m + 1);
-      for (int q = LP(m) + grp + NGRP; q < q1; q += NGRP) {
-        const int i = rows_l[q];
-        double acc = 0.0;
-        for (int e = ptr_l[q] + lane; e < ptr_l[q + 1]; e += TPR) acc += (double)pval[e] * xval(pk.col[e], i);
-        acc = gsum<TPR>(acc);
-        if (lane == 0)
-          finish(i, acc, (double)f[i], OP == SWEEP_ILU_L ? 1.0 : (double)pdiag[P0 + q],
-                 (OP == SWEEP_ILU_U && out) ? (double)base[i] : 0.0);
+      for (int e = E0 + tid + kKP * kNT; e < E1; e += kNT) {
+        const int c = pk.col[e];
+        double xv;
+        if (c >= 0) xv = (double)xs[c];
+        else xv = ready(__hip_atomic_load(x + (-(c + 1)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), -(c + 1));
+        const double pr = (double)pval[e] * xv;
+        if (lng) part += pr;
+        else prod[e - E0] = pr;
       }
-    };
-    auto wait_level = [&](int lv) {
-      const int w0 = sw.wait_ptr[lv], w1 = sw.wait_ptr[lv + 1];
-      for (int w = w0 + tid; w < w1; w += 64) {
-        const unsigned need = (unsigned)sw.wait_need[w];
-        unsigned* pp = sy.progress + sw.wait_blk[w];
-        long spins = 0;
-        while (__hip_atomic_load(pp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-          __builtin_amdgcn_s_sleep(1);
-          if (++spins > spin_limit) {
-            atomicOr(sy.err, 1u);
-            break;
+      if (lng) prod[tid] = part;
+      __syncthreads();
+      if (lng) {
+        if (g == 0) {
+          double acc = 0.0;
+          for (int j = lane; j < kNT; j += TB) acc += prod[j];
+          acc = gsum<TB>(acc);
+          if (lane == 0) finish(s.row, acc, (double)s.fv, UNIT ? 1.0 : (double)s.dg, OUT ? (double)s.bv : 0.0);
+        }
+      } else {
+        // first pass: the rows whose data were prefetched
+        const int q = s.q0 + g;
+        if (q < s.q1) {
+          const int a = ptr_l[q] - E0, len = ptr_l[q + 1] - ptr_l[q];
+          double acc = 0.0;
+          for (int j = lane; j < len; j += TB) acc += prod[a + j];
+          acc = gsum<TB>(acc);
+          if (lane == 0) finish(s.row, acc, (double)s.fv, UNIT ? 1.0 : (double)s.dg, OUT ? (double)s.bv : 0.0);
+        }
+        // levels with more rows than groups
+        for (int q2 = q + NG; q2 < s.q1; q2 += NG) {
+          const int a = ptr_l[q2] - E0, len = ptr_l[q2 + 1] - ptr_l[q2];
+          double acc = 0.0;
+          for (int j = lane; j < len; j += TB) acc += prod[a + j];
+          acc = gsum<TB>(acc);
+          if (lane == 0) {
+            const int i = rows_l[q2];
+            finish(i, acc, (double)f[i], UNIT ? 1.0 : (double)pdiag[P0 + q2], OUT ? (double)base[i] : 0.0);
           }
-          if ((spins & 1023) == 0 && __hip_atomic_load(sy.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         }
       }
-      asm volatile("" ::: "memory");
-    };
-    // copy rows solved up to level m to the global vector, wait for the stores to
-    // complete, then publish progress m + 1
-    auto publish = [&](int m, bool advance) {
-      const int upto = LP(m + 1);
-      for (int q = copied + tid; q < upto; q += 64) {
-        const int i = rows_l[q];
-        __hip_atomic_store(x + i, xs[i - r0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      copied = upto;
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      if (advance && tid == 0)
-        __hip_atomic_store(sy.progress + b, (unsigned)(m + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    };
-    // one level: wait, solve, publish; then refill this slot four levels ahead and
-    // gather the pre-sweep neighbour values of the next slot
-    auto step = [&](Slot<VT, XT>& s, Slot<VT, XT>& next, int m) {
-      const int lv = lb + m;
-      if (coord) wait_level(lv);
-      else gather_old(next);
       __syncthreads();
-      if (!coord) consume(s, m);
-      __syncthreads();
-      if (coord && (sw.publish[lv] || m + 1 == nl)) publish(m, sw.publish[lv] != 0);
+    };
+    // one level; then the other-block values of level m + 2 and the entries of m + 4
+    auto step = [&](Slot<VT, XT>& s, Slot<VT, XT>& s2, int m) {
+      consume(s);
+      issue_remote(s2);
       issue(s, m + 4);
     };
 
@@ -220,78 +249,89 @@ __global__ __launch_bounds__(kNT) void sweep_kernel5(SweepDev sw, SweepPackDev p
     issue(s1, 1);
     issue(s2, 2);
     issue(s3, 3);
-    gather_old(s0);
-    for (int m = 0; m < nl; m += 4) {
-      step(s0, s1, m);
-      if (m + 1 < nl) step(s1, s2, m + 1);
-      if (m + 2 < nl) step(s2, s3, m + 2);
-      if (m + 3 < nl) step(s3, s0, m + 3);
+    issue_remote(s0);
+    issue_remote(s1);
+    for (int m = 0; m < nl; m += 4) {  // every step runs (levels past nl are empty) so that
+      step(s0, s2, m);                 // each iteration issues the same loads
+      step(s1, s3, m + 1);
+      step(s2, s0, m + 2);
+      step(s3, s1, m + 3);
     }
-    __syncthreads();  // the coordinator's final copy reads LDS the next block overwrites
   }
   if (tid == 0) s_last = (atomicAdd(sy.exited, 1u) == gridDim.x - 1);
   __syncthreads();
-  if (s_last) {
-    __threadfence();
-    for (int i = tid; i < sw.nblk; i += kNT) sy.progress[i] = 0u;
-    if (tid == 0) {
-      *sy.ticket = 0u;
-      *sy.exited = 0u;
-    }
+  if (s_last && tid == 0) {
+    *sy.ticket = 0u;
+    *sy.exited = 0u;
   }
 }
 
-template <int OP, int TPR, typename VT, typename XT>
-void launch_one(hipStream_t s, const SweepDev& sw, const SweepPackDev& pk, int n, const void* f, void* x,
+template <typename XT>
+__global__ __launch_bounds__(kNT) void fill_sentinel_kernel(int n, XT* __restrict__ x, const int* __restrict__ done) {
+  if (done && *done) return;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
+    if constexpr (sizeof(XT) == 8) reinterpret_cast<unsigned long long*>(x)[i] = kSentinel64;
+    else reinterpret_cast<unsigned*>(x)[i] = kSentinel32;
+  }
+}
+
+template <int OP, int TB, typename VT, typename XT>
+void launch_one(hipStream_t s, const SweepDev& sw, const SweepPackDev& pk, const void* f, void* x,
                 const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit) {
-  const size_t lds = (size_t)((sw.R * sizeof(XT) + 15) & ~size_t(15)) + sizeof(int) * ((sw.R + 3) & ~3) +
-                     sizeof(int) * ((sw.R + 4) & ~3) + sizeof(int) * (kLvCap + 1);
-  static size_t attr = 65536;  // dynamic LDS the kernel may use without an attribute
-  if (lds > attr) {
-    if (hipFuncSetAttribute((const void*)sweep_kernel5<OP, TPR, VT, XT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess) {
+  static int attr = 65536;  // dynamic LDS the kernel may use without an attribute
+  if (sw.lds > attr) {
+    if (hipFuncSetAttribute((const void*)tri_sweep_kernel<OP, TB, VT, XT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kBudget) != hipSuccess) {
       (void)hipGetLastError();  // leave no sticky error; the launch below reports the failure
     } else {
-      attr = lds;
+      attr = kBudget;
     }
   }
-  sweep_kernel5<OP, TPR, VT, XT><<<sw.grid, kNT, lds, s>>>(sw, pk, n, (const XT*)f, (XT*)x, (const XT*)base,
-                                                          (XT*)out, sync, done, spin_limit);
+  tri_sweep_kernel<OP, TB, VT, XT><<<sw.grid, kNT, sw.lds, s>>>(sw, pk, (const XT*)f, (XT*)x, (const XT*)base,
+                                                                (XT*)out, sync, done, spin_limit);
 }
 
 template <int OP, typename VT, typename XT>
-void dispatch_tpr(hipStream_t s, const SweepDev& sw, const SweepPackDev& pk, int n, const void* f, void* x,
-                  const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit) {
-  switch (sw.tpr) {
-    case 1: launch_one<OP, 1, VT, XT>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit); break;
-    case 2: launch_one<OP, 2, VT, XT>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit); break;
-    case 4: launch_one<OP, 4, VT, XT>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit); break;
-    case 8: launch_one<OP, 8, VT, XT>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit); break;
-    case 16: launch_one<OP, 16, VT, XT>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit); break;
-    case 32: launch_one<OP, 32, VT, XT>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit); break;
-    default: launch_one<OP, 64, VT, XT>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit); break;
+void dispatch_tb(hipStream_t s, const SweepDev& sw, const SweepPackDev& pk, const void* f, void* x,
+                 const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit) {
+  switch (pk.tb) {
+    case 1: launch_one<OP, 1, VT, XT>(s, sw, pk, f, x, base, out, sync, done, spin_limit); break;
+    case 2: launch_one<OP, 2, VT, XT>(s, sw, pk, f, x, base, out, sync, done, spin_limit); break;
+    case 4: launch_one<OP, 4, VT, XT>(s, sw, pk, f, x, base, out, sync, done, spin_limit); break;
+    case 8: launch_one<OP, 8, VT, XT>(s, sw, pk, f, x, base, out, sync, done, spin_limit); break;
+    case 16: launch_one<OP, 16, VT, XT>(s, sw, pk, f, x, base, out, sync, done, spin_limit); break;
+    case 32: launch_one<OP, 32, VT, XT>(s, sw, pk, f, x, base, out, sync, done, spin_limit); break;
+    default: launch_one<OP, 64, VT, XT>(s, sw, pk, f, x, base, out, sync, done, spin_limit); break;
   }
 }
 
 }  // namespace
 
 int sweep_max_rows_per_block() { return 8192; }
-int sweep_entries_per_lane() { return kK; }
+int sweep_lds_budget() { return kBudget; }
+int sweep_threads() { return kNT; }
 
-void launch_sweep_packed(hipStream_t s, int op, const SweepDev& sw, const SweepPackDev& pk, int n, bool fp32,
+void launch_sweep_packed(hipStream_t s, int op, const SweepDev& sw, const SweepPackDev& pk, bool fp32,
                          const void* f, void* x, const void* base, void* out, const SweepSync& sync,
                          const int* done, long spin_limit) {
   if (sw.n <= 0) return;
-#define CPC_SW(OPC)                                                                                        \
-  if (fp32) dispatch_tpr<OPC, float, float>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit);     \
-  else dispatch_tpr<OPC, double, double>(s, sw, pk, n, f, x, base, out, sync, done, spin_limit);
+#define CPC_SW(OPC)                                                                                    \
+  if (fp32) dispatch_tb<OPC, float, float>(s, sw, pk, f, x, base, out, sync, done, spin_limit);     \
+  else dispatch_tb<OPC, double, double>(s, sw, pk, f, x, base, out, sync, done, spin_limit);
   switch (op) {
-    case SWEEP_FGS0: CPC_SW(SWEEP_FGS0) break;
-    case SWEEP_BGS_IP: CPC_SW(SWEEP_BGS_IP) break;
-    case SWEEP_ILU_L: CPC_SW(SWEEP_ILU_L) break;
-    default: CPC_SW(SWEEP_ILU_U) break;
+    case SWEEP_LOWER: CPC_SW(SWEEP_LOWER) break;
+    case SWEEP_UPPER: CPC_SW(SWEEP_UPPER) break;
+    case SWEEP_UNIT_LOWER: CPC_SW(SWEEP_UNIT_LOWER) break;
+    default: CPC_SW(SWEEP_UPPER_OUT) break;
   }
 #undef CPC_SW
+}
+
+void launch_fill_sentinel(hipStream_t s, int n, void* x, bool fp32, const int* done) {
+  if (n <= 0) return;
+  const int grid = std::min((n + kNT - 1) / kNT, 2048);
+  if (fp32) fill_sentinel_kernel<float><<<grid, kNT, 0, s>>>(n, (float*)x, done);
+  else fill_sentinel_kernel<double><<<grid, kNT, 0, s>>>(n, (double*)x, done);
 }
 
 }  // namespace cpc

@@ -25,7 +25,7 @@ def lib():
         L.cpch_rs_coarsen.argtypes = [I, P, P, P, D, P]
         L.cpch_rs_interp.argtypes = [I, P, P, P, D, P, P, P, P]
         L.cpch_rs_interp.restype = ctypes.c_long
-        L.cpch_sweep.argtypes = [I, P, P, P, I, I, P, P, P, P, P, P, P, P, P, P]
+        L.cpch_sweep.argtypes = [I, P, P, P, I, I, I, P, P, P, P, P, P, P, P, P, P]
         L.cpch_dense_inverse.argtypes = [I, P, P, P, P]
         _lib = L
     return _lib
@@ -61,12 +61,12 @@ def rs_interp(n, rp, ci, v, cf, theta=0.25):
     return prp, pci[:nnz], pv[:nnz]
 
 
-def sweep(n, rp, ci, v, forward, R):
+def sweep(n, rp, ci, v, forward, R, max_entries=0):
     rp, ci, v = _csr(rp, ci, v)
-    sizes = np.zeros(6, np.int32)
+    sizes = np.zeros(7, np.int32)
     L = lib()
-    L.cpch_sweep(n, _p(rp), _p(ci), _p(v), int(forward), int(R), _p(sizes), None, None, None, None, None, None,
-                 None, None, None)
+    L.cpch_sweep(n, _p(rp), _p(ci), _p(v), int(forward), int(R), int(max_entries), _p(sizes), None, None, None,
+                 None, None, None, None, None, None)
     nblk, nl, nw = int(sizes[0]), int(sizes[1]), int(sizes[2])
     out = {
         "perm": np.empty(n, np.int32), "blk_beg": np.empty(nblk, np.int32), "blk_end": np.empty(nblk, np.int32),
@@ -74,11 +74,12 @@ def sweep(n, rp, ci, v, forward, R):
         "wait_blk": np.empty(max(nw, 1), np.int32), "wait_need": np.empty(max(nw, 1), np.int32),
         "publish": np.empty(max(nl, 1), np.int32), "blk_row": np.empty(nblk + 1, np.int32),
     }
-    L.cpch_sweep(n, _p(rp), _p(ci), _p(v), int(forward), int(R), _p(sizes), _p(out["perm"]), _p(out["blk_beg"]),
+    L.cpch_sweep(n, _p(rp), _p(ci), _p(v), int(forward), int(R), int(max_entries), _p(sizes), _p(out["perm"]),
+                 _p(out["blk_beg"]),
                  _p(out["blk_end"]), _p(out["lvl_ptr"]), _p(out["wait_ptr"]), _p(out["wait_blk"]),
                  _p(out["wait_need"]), _p(out["publish"]), _p(out["blk_row"]))
     out.update(nblk=nblk, nlev=nl, nwait=nw, global_depth=int(sizes[3]), max_local=int(sizes[4]),
-               R=int(sizes[5]))
+               R=int(sizes[5]), max_level_entries=int(sizes[6]))
     out["wait_blk"] = out["wait_blk"][:nw]
     out["wait_need"] = out["wait_need"][:nw]
     return out
@@ -91,7 +92,7 @@ def dense_inverse(n, rp, ci, v):
     return inv, st
 
 
-def check_sweep_schedule(n, rp, ci, s, forward):
+def check_sweep_schedule(n, rp, ci, s, forward, cap=0):
     """Simulate the persistent sweep's protocol and check that (a) every row is
     processed exactly once in its own block, (b) every dependency is either an
     earlier local level of the same block or a row of a block taken earlier whose
@@ -115,6 +116,19 @@ def check_sweep_schedule(n, rp, ci, s, forward):
             if s["publish"][lv]:
                 final_pub[b] = m + 1
     assert np.all(row_blk >= 0), "row never processed"
+    rp_ = np.asarray(rp)
+    ci_ = np.asarray(ci)
+    ndep = np.array([np.count_nonzero(ci_[rp_[i]:rp_[i + 1]] < i) if forward else
+                     np.count_nonzero(ci_[rp_[i]:rp_[i + 1]] > i) for i in range(n)])
+    worst = 0
+    for lv in range(len(lp) - 1):
+        rows = perm[lp[lv]:lp[lv + 1]]
+        ent = int(ndep[rows].sum())
+        if rows.size > 1:
+            worst = max(worst, ent)
+            if cap > 0:
+                assert ent <= cap, "level over the entry cap"
+    assert worst == s["max_level_entries"]
     order = {b: (b if forward else nblk - 1 - b) for b in range(nblk)}  # ticket of each block
     rp = np.asarray(rp)
     ci = np.asarray(ci)

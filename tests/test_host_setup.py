@@ -70,15 +70,17 @@ def test_coarsening_random_m_matrices(seed):
 @pytest.mark.parametrize("key", ["c1", "c2s", "c5s"])
 @pytest.mark.parametrize("forward", [True, False])
 @pytest.mark.parametrize("R", [1, 7, 64, 300, 100000])
-def test_sweep_schedule_protocol(hiers, key, forward, R):
+@pytest.mark.parametrize("cap", [0, 40])
+def test_sweep_schedule_protocol(hiers, key, forward, R, cap):
     """The persistent sweep's schedule: every dependency is met and every wait can
-    be met, on the finest level and on a dense coarse level."""
+    be met, on the finest level and on a dense coarse level; with an entry cap, every
+    level of two or more rows holds at most cap dependency entries."""
     p, h = hiers[key]
     for d in sorted({0, min(2, h.nlev - 1)}):
         rp, ci, v = h.level(d)
         n = rp.size - 1
-        s = host_lib.sweep(n, rp, ci, v, forward, R)
-        host_lib.check_sweep_schedule(n, rp, ci, s, forward)
+        s = host_lib.sweep(n, rp, ci, v, forward, R, cap)
+        host_lib.check_sweep_schedule(n, rp, ci, s, forward, cap)
 
 
 def test_sweep_depth_matches_grid_formula():
