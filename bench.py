@@ -116,7 +116,7 @@ def main():
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": f"sweep_kernel (backward Gauss-Seidel, all levels of one V-cycle)",
+                "kernel": "tri_sweep_kernel (backward (D+U) solve of the Gauss-Seidel smoother, every smoothed level)",
                 "avg_launch_us": round(1000.0 * tk["avg_ms"], 3), "bytes_per_launch": tk["bytes"],
                 "launches_timed": tk["launches"]}
     log(f"roofline {ROOFLINE_KERNEL}: {1000 * tk['avg_ms']:.2f} us/launch, {tk['bytes'] / 1e6:.2f} MB/launch "

@@ -84,6 +84,7 @@ typedef struct {
   int32_t check_every;    /* PCG iterations between host reads of the convergence flag (4)  */
   int32_t rap_on_gpu;     /* 1: Galerkin products on the GPU (default); 0 is not offered     */
   int32_t sweep_block_rows; /* rows per workgroup block of the triangular sweeps (0 = auto)  */
+  int32_t sweep_threads;  /* threads per sweep workgroup: 64 (one wave) or 256; 0 = auto     */
   double theta;           /* strength threshold of the classical coarsening (0.25)          */
 } cpc_options;
 

@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("prec", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_coarse", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("swap_roles", ctypes.c_int32),
                 ("check_symmetry", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("rap_on_gpu", ctypes.c_int32), ("sweep_block_rows", ctypes.c_int32), ("theta", ctypes.c_double)]
+                ("rap_on_gpu", ctypes.c_int32), ("sweep_block_rows", ctypes.c_int32),
+                ("sweep_threads", ctypes.c_int32), ("theta", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

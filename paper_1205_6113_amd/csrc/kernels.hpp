@@ -47,8 +47,9 @@ struct SweepDev {
   int pcap;              // product slots per workgroup (largest entry count of a level with two or more rows)
   int maxl;              // most levels of one block
   int lds;               // dynamic LDS bytes of one workgroup
-  int off_xs, off_rows, off_ptr, off_lvt;  // byte offsets of the LDS arrays (products start at 0)
+  int off_xs, off_rows, off_ptr, off_meta;  // byte offsets of the LDS arrays (products start at 0)
   int grid;              // workgroups launched
+  int nt;                // threads per workgroup: 64 or 256
 };
 
 enum SweepOp {
@@ -131,7 +132,7 @@ struct SweepPackDev {
   const int* col;    // entry column: j - (first row of the block) for a column in the row's own
                      // block, -(j + 1) for a column in another block
   const void* val;   // entry values (FP64 or FP32)
-  const void* diag;  // [n] diagonal of processed row p (unused by the unit lower solve)
+  const void* diag;  // [n] reciprocal diagonal of processed row p (unused by the unit lower solve)
   int tb;            // lanes that sum one row's products
 };
 

@@ -309,15 +309,15 @@ static int choose_block_rows(int n) {
 }
 
 // LDS layout of a sweep workgroup: products | solved values | rows | entry offsets |
-// level table. Returns the bytes used.
+// per-level ranges (16 bytes a level). Returns the bytes used.
 static int sweep_layout(const SweepSchedule& s, int esz, int pcap, SweepDev& sd) {
   auto al = [](int64_t v) { return (int)((v + 15) & ~int64_t(15)); };
   sd.pcap = pcap;
   sd.off_xs = al(8 * (int64_t)pcap);
   sd.off_rows = sd.off_xs + al((int64_t)esz * s.R);
   sd.off_ptr = sd.off_rows + al(4 * (int64_t)s.R);
-  sd.off_lvt = sd.off_ptr + al(4 * ((int64_t)s.R + 1));
-  sd.lds = sd.off_lvt + al(4 * ((int64_t)s.max_local_levels + 1));
+  sd.off_meta = sd.off_ptr + al(4 * ((int64_t)s.R + 1));
+  sd.lds = sd.off_meta + al(16 * (int64_t)s.max_local_levels);
   return sd.lds;
 }
 
@@ -352,6 +352,10 @@ static SweepSchedule make_sweep(cpc_solver* h, const HostCsr& a, bool forward, i
   sd.blk_end = dupload(s.blk_end, h->owned, h->stream);
   sd.lvl_ptr = dupload(s.lvl_ptr, h->owned, h->stream);
   sd.grid = std::min(s.nblk, 1024);
+  // four waves per block; a one-wave workgroup (no cross-wave barriers) measured
+  // slower even where one block covers the matrix, since a level's entries then take
+  // four times as many steps per lane
+  sd.nt = h->opt.sweep_threads == 64 ? 64 : 256;
   d.d = sd;
   d.global_depth = s.global_depth;
   return s;
@@ -373,13 +377,13 @@ static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vecto
   const int n = a.n;
   const bool fwd = s.forward;
   std::vector<int> ptr(n + 1, 0);
-  std::vector<double> diag(n, 1.0);
+  std::vector<double> diag(n, 1.0);  // reciprocal diagonal
   for (int p = 0; p < n; ++p) {
     const int i = s.perm[p];
     int c = 0;
     for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
       const int j = a.ci[q];
-      if (j == i) diag[p] = vals[q];
+      if (j == i) diag[p] = 1.0 / vals[q];
       else if (fwd ? j < i : j > i) ++c;
     }
     ptr[p + 1] = ptr[p] + c;
@@ -1149,6 +1153,7 @@ void cpc_default_options(cpc_options* o) {
   o->check_every = 4;
   o->rap_on_gpu = 1;
   o->sweep_block_rows = 0;
+  o->sweep_threads = 0;
   o->theta = 0.25;
 }
 
@@ -1164,6 +1169,8 @@ static cpc_status read_options(const cpc_options* opt, cpc_options& o) {
   if (o.precision != CPC_FP64 && o.precision != CPC_FP32_PRECOND) return set_err(CPC_E_ARG, "unknown precision");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1) return set_err(CPC_E_ARG, "bad level limits");
   if (!(o.theta >= 0.0 && o.theta <= 1.0)) return set_err(CPC_E_ARG, "theta must lie in [0, 1]");
+  if (o.sweep_threads != 0 && o.sweep_threads != 64 && o.sweep_threads != 256)
+    return set_err(CPC_E_ARG, "sweep_threads must be 0, 64 or 256");
   return CPC_OK;
 }
 

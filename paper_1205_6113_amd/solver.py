@@ -34,7 +34,8 @@ def _dev_vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
 
 
 def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, theta=0.25, swap_roles=False,
-            check_symmetry=True, use_graph=True, check_every=4, sweep_block_rows=0) -> _lib.Options:
+            check_symmetry=True, use_graph=True, check_every=4, sweep_block_rows=0,
+            sweep_threads=0) -> _lib.Options:
     lib = load()
     o = _lib.Options()
     lib.cpc_default_options(ctypes.byref(o))
@@ -48,6 +49,7 @@ def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, th
     o.use_graph = int(bool(use_graph))
     o.check_every = int(check_every)
     o.sweep_block_rows = int(sweep_block_rows)
+    o.sweep_threads = int(sweep_threads)
     return o
 
 
