@@ -85,6 +85,9 @@ typedef struct {
   int32_t rap_on_gpu;     /* 1: Galerkin products on the GPU (default); 0 is not offered     */
   int32_t sweep_block_rows; /* rows per workgroup block of the triangular sweeps (0 = auto)  */
   int32_t sweep_threads;  /* threads per sweep workgroup: 64 (one wave) or 256; 0 = auto     */
+  int32_t dense_smoother; /* Gauss-Seidel on levels of <= 65536 rows through an explicit
+                             inverse of D+L: 0 = where measured faster at setup, 1 = never,
+                             2 = wherever it fits                                           */
   double theta;           /* strength threshold of the classical coarsening (0.25)          */
 } cpc_options;
 
@@ -139,6 +142,12 @@ cpc_status cpc_spmv(cpc_handle h, int32_t level, const double* x_dev, double* y_
  * n_l[l], nnz_l[l] for each level l (0 = finest); depth_l[l] = number of
  * level sets of the lower-triangular dependency graph of A_l. */
 cpc_status cpc_hierarchy_info(cpc_handle h, int32_t* nlev, int32_t* n_l, int64_t* nnz_l, int32_t* depth_l);
+
+/* How the Gauss-Seidel smoother of Algorithm 3.2 is applied on level `level`:
+ * *kind = 0 level-scheduled triangular sweeps, 1 products with the explicit inverse of
+ * D+L (forward sweep) and its transpose (backward sweep, D+U = (D+L)^T for symmetric
+ * A), -1 the level is not smoothed (coarsest). CPC_E_ARG for a level out of range. */
+cpc_status cpc_smoother_kind(cpc_handle h, int32_t level, int32_t* kind);
 
 /* Copy level `level`'s matrix A_l to host CSR arrays (row_ptr[n_l+1], col_idx and
  * val of nnz_l entries). */

@@ -17,13 +17,14 @@ STATUS_NAMES = {0: "CPC_OK", 1: "CPC_E_ARG", 2: "CPC_E_NOT_SPD", 3: "CPC_E_BREAK
 PREC = {"combined": 0, "amg": 1, "ilu": 2, "additive": 3, "none": 4}
 OP = {"combined": 0, "amg": 1, "ilu": 2, "additive": 3, "none": 4, "vcycle": 5, "fgs": 6, "bgs": 7}
 PRECISION = {"fp64": 0, "fp32": 1}
+DENSE = {"auto": 0, "never": 1, "always": 2}
 
 # every entry point declared in include/cpc.h
 EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "cpc_apply_op", "cpc_spmv",
            "cpc_hierarchy_info", "cpc_get_level", "cpc_get_prolongation", "cpc_get_ilu", "cpc_get_stats",
            "cpc_neg_outer_on_pattern", "cpc_time_kernel", "cpc_destroy", "cpc_last_error", "cpc_tpfa_pattern",
            "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values", "cpc_setup_batch",
-           "cpc_solve_batch", "cpc_batch_info")
+           "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind")
 KERNEL = {"spmv_pq": 0, "fgs": 1, "bgs": 2, "ilu_l": 3, "ilu_u": 4, "residual": 5, "restrict": 6, "prolong": 7,
           "vcycle": 8, "precond": 9, "iteration": 10}
 
@@ -33,7 +34,8 @@ class Options(ctypes.Structure):
                 ("max_coarse", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("swap_roles", ctypes.c_int32),
                 ("check_symmetry", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("rap_on_gpu", ctypes.c_int32), ("sweep_block_rows", ctypes.c_int32),
-                ("sweep_threads", ctypes.c_int32), ("theta", ctypes.c_double)]
+                ("sweep_threads", ctypes.c_int32), ("dense_smoother", ctypes.c_int32),
+                ("theta", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -76,6 +78,8 @@ def load():
     lib.cpc_spmv.restype = I32
     lib.cpc_hierarchy_info.argtypes = [P, ctypes.POINTER(I32), P, P, P]
     lib.cpc_hierarchy_info.restype = I32
+    lib.cpc_smoother_kind.argtypes = [P, I32, ctypes.POINTER(I32)]
+    lib.cpc_smoother_kind.restype = I32
     lib.cpc_get_level.argtypes = [P, I32, P, P, P]
     lib.cpc_get_level.restype = I32
     lib.cpc_get_prolongation.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int64), P, P, P, P]

@@ -33,6 +33,7 @@ SOURCES = [
     ("batch.hip", "hip", []),
     ("rap.hip", "hip", ["-ffp-contract=off"]),
     ("tpfa.hip", "hip", ["-ffp-contract=off"]),
+    ("dense_tri.hip", "hip", []),
     ("host_setup.cpp", "gxx", ["-ffp-contract=off"]),
     ("solver.cpp", "hiphost", []),
 ]
@@ -73,7 +74,7 @@ def build(verbose: bool = False) -> Path:
         msg = "\n".join(f"--- {n}\n{t}" for n, t in failed)
         raise RuntimeError(f"build failed:\n{msg}")
     tmp = LIB.with_suffix(".so.tmp")
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", str(tmp), *map(str, objs)]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", str(tmp), *map(str, objs), "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

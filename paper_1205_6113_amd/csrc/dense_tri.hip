@@ -1,0 +1,285 @@
+// Dense explicit inverses of the Gauss-Seidel factor T = D + L on small levels.
+//
+// On the coarse levels of a classical AMG hierarchy the forward sweep T^{-1} f has a
+// dependency depth close to the number of rows divided by a handful, so a
+// level-scheduled sweep there is bound by the latency of thousands of dependent steps
+// rather than by memory traffic. With hundreds of gigabytes of HBM the inverse of T
+// can be held explicitly instead: the forward sweep becomes the lower-triangular
+// matrix-vector product y = T^{-1} f, and since D + U = T^T for symmetric A the
+// backward sweep (D+U)^{-1} g becomes the transposed product y = T^{-T} g. Both read
+// the n(n+1)/2 stored entries once and are bound by HBM bandwidth.
+//
+// Setup (per system of a level, n rows): T is scattered into a zeroed dense n x n
+// row-major array; the 128 x 128 diagonal blocks are inverted in place by
+// substitution in LDS; then, for spans of 128, 256, 512, ... rows, each pair of
+// adjacent inverted spans [a, a+s) and [a+s, b) gets its off-diagonal block
+// B <- -C^{-1} B A^{-1} from two matrix products (library GEMMs), where A^{-1}, C^{-1}
+// are the inverted diagonal spans. The result is T^{-1}, lower triangular.
+//
+// Products: y = T^{-1} f by one wave per row (coalesced row reads, the vector from
+// L2). y = T^{-T} g: on smaller systems from a stored transpose, row by row like the
+// forward product; on larger ones by items (column block of 512, chunk of 1024 rows)
+// whose partial column sums go to a buffer and are added in chunk order
+// (deterministic), which reads each stored entry once without a second copy.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace cpc {
+
+namespace {
+
+constexpr int kLeaf = 128;  // diagonal blocks inverted by substitution
+constexpr int kNT = 256;
+
+template <int W>
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
+  return v;
+}
+
+// T (rows [0, n) of a CSR whose columns are offset by voff) into the dense row-major
+// array M (leading dimension n): lower triangle only (upper entries stay zero).
+__global__ __launch_bounds__(kNT) void scatter_lower_kernel(int n, int voff, const int* __restrict__ rp,
+                                                           const int* __restrict__ ci,
+                                                           const double* __restrict__ v, double* __restrict__ M) {
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
+    const int r = voff + i;
+    for (int p = rp[r]; p < rp[r + 1]; ++p) {
+      const int j = ci[p] - voff;
+      if (j <= i) M[(long)i * n + j] = v[p];
+    }
+  }
+}
+
+// In-place inverse of the lower-triangular diagonal block of M starting at row and
+// column b * kLeaf (size nb <= kLeaf). Row by row: x_ii = 1 / t_ii and, for j < i,
+// x_ij = -(sum_{k=j}^{i-1} t_ik x_kj) / t_ii, with the finished rows of X in LDS.
+__global__ __launch_bounds__(kLeaf) void leaf_inverse_kernel(int n, double* __restrict__ M) {
+  __shared__ double X[kLeaf][kLeaf + 1];
+  __shared__ double trow[kLeaf];
+  const int b0 = blockIdx.x * kLeaf;
+  const int nb = min(kLeaf, n - b0);
+  const int j = threadIdx.x;
+  for (int i = 0; i < nb; ++i) {
+    if (j < nb) trow[j] = M[(long)(b0 + i) * n + b0 + j];
+    __syncthreads();
+    const double dinv = 1.0 / trow[i];
+    double x = 0.0;
+    if (j < i) {
+      double s0 = 0.0, s1 = 0.0;
+      int k = j;
+      for (; k + 1 < i; k += 2) {
+        s0 += trow[k] * X[k][j];
+        s1 += trow[k + 1] * X[k + 1][j];
+      }
+      if (k < i) s0 += trow[k] * X[k][j];
+      x = -(s0 + s1) * dinv;
+    } else if (j == i) {
+      x = dinv;
+    }
+    if (j < nb) X[i][j] = x;
+    __syncthreads();
+  }
+  for (int i = 0; i < nb; ++i)
+    if (j < nb) M[(long)(b0 + i) * n + b0 + j] = X[i][j];
+}
+
+// Y = X^T for an n x n row-major X, 32 x 32 tiles through LDS.
+template <typename MT>
+__global__ __launch_bounds__(kNT) void transpose_kernel(int n, const MT* __restrict__ X, MT* __restrict__ Y) {
+  __shared__ MT tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int r = ty; r < 32; r += 8) {
+    const int i = by + r, j = bx + tx;
+    if (i < n && j < n) tile[r][tx] = X[(long)i * n + j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = bx + r, j = by + tx;
+    if (i < n && j < n) Y[(long)i * n + j] = tile[tx][r];
+  }
+}
+
+template <typename MT>
+__global__ __launch_bounds__(kNT) void to_type_kernel(long n, const double* __restrict__ a, MT* __restrict__ y) {
+  for (long i = (long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long)gridDim.x * kNT) y[i] = (MT)a[i];
+}
+
+// y = M f with M lower (y = T^{-1} f) or upper (y = T^{-T} g from the stored
+// transpose) triangular: one wave per row, items (system, first row, end row).
+template <bool UPPER, typename MT, typename XT>
+__global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
+                                                            XT* __restrict__ y, const int* __restrict__ done) {
+  if (done && *done) return;
+  const int4 it = dt.item_n[blockIdx.x];
+  const int s = it.x;
+  const int n = dt.n[s];
+  const int voff = dt.voff[s];
+  const MT* __restrict__ M = reinterpret_cast<const MT*>(UPPER ? dt.MT : dt.M) + dt.moff[s];
+  const XT* __restrict__ fs = f + voff;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = it.y + w; i < it.z; i += kNT / 64) {
+    const MT* __restrict__ row = M + (long)i * n;
+    const int jb = UPPER ? i : 0, je = UPPER ? n : i + 1;  // stored entries [jb, je)
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = jb + lane;
+    for (; j + 192 < je; j += 256) {
+      a0 += (double)row[j] * (double)fs[j];
+      a1 += (double)row[j + 64] * (double)fs[j + 64];
+      a2 += (double)row[j + 128] * (double)fs[j + 128];
+      a3 += (double)row[j + 192] * (double)fs[j + 192];
+    }
+    for (; j < je; j += 64) a0 += (double)row[j] * (double)fs[j];
+    double acc = wsum<64>((a0 + a1) + (a2 + a3));
+    if (lane == 0) y[voff + i] = (XT)acc;
+  }
+}
+
+// Partial column sums of T^{-T} g: item (system, first column c0, first row r0, slot);
+// each thread owns columns c0 + 2t, c0 + 2t + 1 and adds rows [max(r0, c0), r0 + chunk).
+template <typename MT, typename XT>
+__global__ __launch_bounds__(kNT) void gemv_lower_t_part_kernel(DenseTriDev dt, const XT* __restrict__ g,
+                                                                const int* __restrict__ done) {
+  if (done && *done) return;
+  const int4 it = dt.item_t[blockIdx.x];
+  const int s = it.x;
+  const int n = dt.n[s];
+  const int voff = dt.voff[s];
+  const MT* __restrict__ M = reinterpret_cast<const MT*>(dt.M) + dt.moff[s];
+  const XT* __restrict__ gs = g + voff;
+  const int c = it.y + 2 * threadIdx.x;
+  const int rbeg = max(it.z, it.y), rend = min(it.z + kTChunk, n);
+  double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+  if (c < n) {
+    const bool two = c + 1 < n;
+    int i = rbeg;
+    for (; i + 1 < rend; i += 2) {
+      const double g0 = (double)gs[i], g1 = (double)gs[i + 1];
+      const MT* r0p = M + (long)i * n + c;
+      const MT* r1p = r0p + n;
+      a0 += (double)r0p[0] * g0;
+      b0 += (double)r1p[0] * g1;
+      if (two) {
+        a1 += (double)r0p[1] * g0;
+        b1 += (double)r1p[1] * g1;
+      }
+    }
+    if (i < rend) {
+      const double g0 = (double)gs[i];
+      const MT* r0p = M + (long)i * n + c;
+      a0 += (double)r0p[0] * g0;
+      if (two) a1 += (double)r0p[1] * g0;
+    }
+  }
+  double* part = dt.part + (long)it.w * kTCols;
+  part[2 * threadIdx.x] = a0 + b0;
+  part[2 * threadIdx.x + 1] = a1 + b1;
+}
+
+// y = T^{-T} g from the partial sums: item (system, c0, first slot, slots), slots in
+// row-chunk order.
+template <typename XT>
+__global__ __launch_bounds__(kNT) void gemv_lower_t_sum_kernel(DenseTriDev dt, XT* __restrict__ y,
+                                                               const int* __restrict__ done) {
+  if (done && *done) return;
+  const int4 it = dt.red[blockIdx.x];
+  const int s = it.x;
+  const int n = dt.n[s];
+  for (int c = threadIdx.x; c < kTCols; c += kNT) {
+    if (it.y + c >= n) break;
+    double acc = 0.0;
+    for (int k = 0; k < it.w; ++k) acc += dt.part[(long)(it.z + k) * kTCols + c];
+    y[dt.voff[s] + it.y + c] = (XT)acc;
+  }
+}
+
+}  // namespace
+
+void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,
+                        const int* done) {
+  if (dt.nitem_n <= 0) return;
+  if (mfp32 && xfp32)
+    gemv_tri_rows_kernel<false, float, float><<<dt.nitem_n, kNT, 0, s>>>(dt, (const float*)f, (float*)y, done);
+  else
+    gemv_tri_rows_kernel<false, double, double><<<dt.nitem_n, kNT, 0, s>>>(dt, (const double*)f, (double*)y, done);
+}
+
+void launch_dense_lower_t(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* g, void* y,
+                          const int* done) {
+  if (dt.MT) {  // stored transpose: row products of the upper-triangular T^{-T}
+    if (dt.nitem_n <= 0) return;
+    if (mfp32 && xfp32)
+      gemv_tri_rows_kernel<true, float, float><<<dt.nitem_n, kNT, 0, s>>>(dt, (const float*)g, (float*)y, done);
+    else
+      gemv_tri_rows_kernel<true, double, double><<<dt.nitem_n, kNT, 0, s>>>(dt, (const double*)g, (double*)y, done);
+    return;
+  }
+  if (dt.nitem_t <= 0) return;
+  if (mfp32 && xfp32) {
+    gemv_lower_t_part_kernel<float, float><<<dt.nitem_t, kNT, 0, s>>>(dt, (const float*)g, done);
+    gemv_lower_t_sum_kernel<float><<<dt.nred, kNT, 0, s>>>(dt, (float*)y, done);
+  } else {
+    gemv_lower_t_part_kernel<double, double><<<dt.nitem_t, kNT, 0, s>>>(dt, (const double*)g, done);
+    gemv_lower_t_sum_kernel<double><<<dt.nred, kNT, 0, s>>>(dt, (double*)y, done);
+  }
+}
+
+void launch_transpose(hipStream_t s, int n, const void* X, void* Y, bool fp32) {
+  const dim3 grid((n + 31) / 32, (n + 31) / 32);
+  if (fp32) transpose_kernel<float><<<grid, kNT, 0, s>>>(n, (const float*)X, (float*)Y);
+  else transpose_kernel<double><<<grid, kNT, 0, s>>>(n, (const double*)X, (double*)Y);
+}
+
+bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int* ci, const double* v, double* M,
+                       double* work, std::string* msg) {
+  rocblas_handle hb = nullptr;
+  if (rocblas_create_handle(&hb) != rocblas_status_success) {
+    if (msg) *msg = "rocblas_create_handle failed";
+    return false;
+  }
+  bool ok = rocblas_set_stream(hb, s) == rocblas_status_success;
+  if (ok && hipMemsetAsync(M, 0, sizeof(double) * (size_t)n * n, s) != hipSuccess) ok = false;
+  if (ok) {
+    scatter_lower_kernel<<<std::min((n + kNT - 1) / kNT, 1024), kNT, 0, s>>>(n, voff, rp, ci, v, M);
+    leaf_inverse_kernel<<<(n + kLeaf - 1) / kLeaf, kLeaf, 0, s>>>(n, M);
+    ok = hipGetLastError() == hipSuccess;
+  }
+  // merge inverted spans: rows/columns [a, a+sp) (A) and [a+sp, e) (C), off-diagonal
+  // block B = M[a+sp:e, a:a+sp]; row-major X is column-major X^T, so the row-major
+  // product W = B A^{-1} is the column-major W^T = A^{-T} B^T
+  const double one = 1.0, zero = 0.0, mone = -1.0;
+  for (int sp = kLeaf; ok && sp < n; sp *= 2) {
+    for (int a = 0; ok && a + sp < n; a += 2 * sp) {
+      const int e = std::min(a + 2 * sp, n);
+      const int m1 = sp, m2 = e - a - sp;
+      double* Ai = M + (long)a * n + a;
+      double* B = M + (long)(a + sp) * n + a;
+      double* Ci = M + (long)(a + sp) * n + a + sp;
+      // W (m2 x m1, row-major, ld m1) = B A^{-1}
+      ok = rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m1, m2, m1, &one, Ai, n, B, n, &zero,
+                         work, m1) == rocblas_status_success;
+      // B = -C^{-1} W
+      if (ok)
+        ok = rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m1, m2, m2, &mone, work, m1, Ci, n,
+                           &zero, B, n) == rocblas_status_success;
+    }
+  }
+  if (!ok && msg && msg->empty()) *msg = "dense triangular inverse failed";
+  rocblas_destroy_handle(hb);
+  return ok;
+}
+
+void launch_to_type(hipStream_t s, long n, const double* a, void* y, bool fp32) {
+  const int grid = (int)std::min<long>((n + kNT - 1) / kNT, 4096);
+  if (fp32) to_type_kernel<float><<<grid, kNT, 0, s>>>(n, a, (float*)y);
+  else to_type_kernel<double><<<grid, kNT, 0, s>>>(n, a, (double*)y);
+}
+
+}  // namespace cpc

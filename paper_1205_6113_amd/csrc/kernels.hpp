@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 namespace cpc {
 
@@ -135,6 +136,34 @@ struct SweepPackDev {
   const void* diag;  // [n] reciprocal diagonal of processed row p (unused by the unit lower solve)
   int tb;            // lanes that sum one row's products
 };
+
+// Dense explicit inverses T^{-1} = (D+L)^{-1} of the systems of one level (dense_tri.hip).
+constexpr int kTCols = 512;    // columns of one item of the transposed product
+constexpr int kTChunk = 1024;  // rows of one item of the transposed product
+struct DenseTriDev {
+  const int* n;        // [nsys] rows of each system
+  const long* moff;    // [nsys] element offset of each system's n x n row-major inverse
+  const int* voff;     // [nsys] first row of each system in the level vector
+  const void* M;       // the inverses (lower triangular; FP64 or FP32)
+  const void* MT;      // their transposes (upper triangular), or null: transposed product by items
+  int nitem_n;         // y = T^{-1} f items: {system, first row, end row, 0}
+  const int4* item_n;
+  int nitem_t;         // partial sums of y = T^{-T} g: {system, first column, first row, slot}
+  const int4* item_t;
+  int nred;            // column sums of the partials: {system, first column, first slot, slots}
+  const int4* red;
+  double* part;        // [slots][kTCols]
+};
+// T^{-1} of rows [voff, voff + n) of the level CSR (columns offset by voff) into the
+// dense n x n array M (FP64), using work (>= the largest off-diagonal product).
+bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int* ci, const double* v, double* M,
+                       double* work, std::string* msg);
+void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,
+                        const int* done);
+void launch_dense_lower_t(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* g, void* y,
+                          const int* done);
+void launch_to_type(hipStream_t s, long n, const double* a, void* y, bool fp32);
+void launch_transpose(hipStream_t s, int n, const void* X, void* Y, bool fp32);
 
 // Persistent block-pipelined triangular solve over packed rows (sweep.hip). x must
 // hold the sentinel in rows [0, sw.n) (launch_fill_sentinel) when it starts.

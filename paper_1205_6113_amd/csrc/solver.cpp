@@ -116,6 +116,12 @@ struct Level {
   void* u = nullptr;
   void* r = nullptr;
   void* t = nullptr;  // right-hand side of the backward sweep
+  // explicit inverses of D+L of the smoothed systems, where they are faster than sweeps
+  DenseTriDev dtri{};
+  void* dense_M = nullptr;     // held here until the setup tuner keeps or drops it
+  void* dense_MT = nullptr;    // its transpose (small systems), same ownership
+  bool dense_smooth = false;   // smooth through dtri instead of the level-scheduled sweeps
+  double dense_entries = 0.0;  // stored lower-triangle entries (byte model)
 };
 
 }  // namespace cpc
@@ -165,6 +171,10 @@ struct cpc_solver {
       if (graph_src[i]) (void)hipGraphDestroy(graph_src[i]);
       if (bgraph[i]) (void)hipGraphExecDestroy(bgraph[i]);
       if (bgraph_src[i]) (void)hipGraphDestroy(bgraph_src[i]);
+    }
+    for (auto& L : lev) {
+      if (L.dense_M) (void)hipFree(L.dense_M);
+      if (L.dense_MT) (void)hipFree(L.dense_MT);
     }
     for (void* ptr : owned) (void)hipFree(ptr);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -527,6 +537,173 @@ static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::
   return status;
 }
 
+// Explicit inverses of T = D + L for the smoothed systems of a level (all of them or
+// none): at most 65536 rows each and 64 GB for the level.
+static constexpr int kDenseMaxRows = 65536;
+static constexpr double kDenseMaxBytes = 64e9;
+static constexpr int kDenseTransRows = 16384;
+
+static long dense_work_need(int n) {
+  long w = 1;
+  for (int sp = 128; sp < n; sp *= 2)
+    for (int a = 0; a + sp < n; a += 2 * sp) w = std::max(w, (long)sp * (std::min(a + 2 * sp, n) - a - sp));
+  return w;
+}
+
+static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, const std::vector<int>& voffs) {
+  if (h->opt.dense_smoother == 1 || ns.empty()) return;
+  double bytes = 0.0;
+  for (int n : ns) {
+    if (n > kDenseMaxRows) return;
+    bytes += 8.0 * n * (double)n;
+  }
+  if (bytes > kDenseMaxBytes) return;
+  std::vector<long> moff(ns.size());
+  long tot = 0, wmax = 1;
+  for (size_t k = 0; k < ns.size(); ++k) {
+    moff[k] = tot;
+    tot += (long)ns[k] * ns[k];
+    wmax = std::max(wmax, dense_work_need(ns[k]));
+  }
+  double* M64 = nullptr;
+  double* work = nullptr;
+  if (hipMalloc(&M64, sizeof(double) * tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (hipMalloc(&work, sizeof(double) * wmax) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(M64);
+    return;
+  }
+  bool ok = true;
+  std::string msg;
+  for (size_t k = 0; ok && k < ns.size(); ++k)
+    ok = dense_tri_inverse(h->stream, ns[k], voffs[k], L.A.rp, L.A.ci, L.A.v, M64 + moff[k], work, &msg);
+  ok = ok && hipStreamSynchronize(h->stream) == hipSuccess;
+  (void)hipFree(work);
+  if (!ok) {
+    (void)hipGetLastError();
+    (void)hipFree(M64);
+    return;
+  }
+  void* M = M64;
+  if (h->f32) {
+    float* M32 = nullptr;
+    if (hipMalloc(&M32, sizeof(float) * tot) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFree(M64);
+      return;
+    }
+    launch_to_type(h->stream, tot, M64, M32, true);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    (void)hipFree(M64);
+    M = M32;
+  }
+  std::vector<int4> itn, itt, red;
+  int slot = 0;
+  double ent = 0.0;
+  for (int k = 0; k < (int)ns.size(); ++k) {
+    const int n = ns[k];
+    ent += 0.5 * (double)n * (n + 1);
+    for (int r = 0; r < n; r += 16) itn.push_back(make_int4(k, r, std::min(r + 16, n), 0));
+    for (int c0 = 0; c0 < n; c0 += kTCols) {
+      const int first = slot;
+      for (int r0 = (c0 / kTChunk) * kTChunk; r0 < n; r0 += kTChunk) itt.push_back(make_int4(k, c0, r0, slot++));
+      red.push_back(make_int4(k, c0, first, slot - first));
+    }
+  }
+  DenseTriDev& dt = L.dtri;
+  dt.n = dupload(ns, h->owned, h->stream);
+  dt.moff = dupload(moff, h->owned, h->stream);
+  dt.voff = dupload(voffs, h->owned, h->stream);
+  dt.M = M;
+  dt.nitem_n = (int)itn.size();
+  dt.item_n = dupload(itn, h->owned, h->stream);
+  dt.nitem_t = (int)itt.size();
+  dt.item_t = dupload(itt, h->owned, h->stream);
+  dt.nred = (int)red.size();
+  dt.red = dupload(red, h->owned, h->stream);
+  dt.part = dalloc<double>((size_t)slot * kTCols, h->owned);
+  // systems of at most 16384 rows also keep the transpose (row products both ways)
+  bool small = true;
+  for (int n : ns) small = small && n <= kDenseTransRows;
+  if (small) {
+    const size_t es = h->f32 ? sizeof(float) : sizeof(double);
+    void* MTr = nullptr;
+    if (hipMalloc(&MTr, es * tot) == hipSuccess) {
+      for (size_t k = 0; k < ns.size(); ++k)
+        launch_transpose(h->stream, ns[k], (const char*)M + es * moff[k], (char*)MTr + es * moff[k], h->f32);
+      HIPCHK(hipStreamSynchronize(h->stream));
+      dt.MT = MTr;
+      L.dense_MT = MTr;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  L.dense_M = M;
+  L.dense_entries = ent;
+}
+
+// Average milliseconds of fn() over reps launches after one warm-up (events on the
+// handle's stream).
+template <typename F>
+static float time_ms(cpc_solver* h, int reps, F fn) {
+  fn();
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, h->stream));
+  for (int r = 0; r < reps; ++r) fn();
+  HIPCHK(hipEventRecord(e1, h->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+// Keep each level's explicit inverse only where it smooths faster than the sweeps
+// (measured on the handle's own matrices), or everywhere it was built when asked to.
+static void tune_dense(cpc_solver* h) {
+  const bool f32 = h->f32;
+  for (size_t d = 0; d < h->lev.size(); ++d) {
+    Level& L = h->lev[d];
+    if (!L.dense_M) continue;
+    bool keep = h->opt.dense_smoother == 2;
+    if (!keep) {
+      void* f = d == 0 ? h->pin : L.f;
+      void* u = d == 0 ? h->u1 : L.u;
+      const float ts = time_ms(h, 3, [&] {
+        run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
+        run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
+      });
+      const float td = time_ms(h, 3, [&] {
+        launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, nullptr);
+        launch_dense_lower_t(h->stream, L.dtri, f32, f32, f, u, nullptr);
+      });
+      keep = td < ts;
+    }
+    if (keep) {
+      h->owned.push_back(L.dense_M);
+      if (L.dense_MT) h->owned.push_back(L.dense_MT);
+      L.dense_smooth = true;
+    } else {
+      (void)hipFree(L.dense_M);
+      if (L.dense_MT) (void)hipFree(L.dense_MT);
+      L.dtri = DenseTriDev{};
+      L.dense_entries = 0.0;
+    }
+    L.dense_M = nullptr;
+    L.dense_MT = nullptr;
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  unsigned herr = 0;
+  HIPCHK(hipMemcpy(&herr, h->sync.err, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (herr) throw HipError{hipErrorUnknown, "a sweep wait exceeded its bound while tuning"};
+}
+
 // Concatenate the systems' hierarchies depth by depth and upload them. At depth d
 // the level vector holds, in this order, the systems that are smoothed at d (still
 // coarsened further) and then the systems whose coarsest level is d; matrices are
@@ -628,6 +805,15 @@ static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_o
       }
       upload_csr(h, strict_lower(sub), L.Ls, false);
       L.t = valloc(h, rows);
+      if (L.nS > 0 && d + 1 < D) {
+        std::vector<int> dn, dv;
+        for (int s : order[d])
+          if (d + 1 < (int)sys[s].A.size()) {
+            dn.push_back(sys[s].A[d].n);
+            dv.push_back(off[d][s]);
+          }
+        build_dense(h, L, dn, dv);
+      }
       L.r = valloc(h, rows);
     }
     if (d > 0) {
@@ -730,7 +916,8 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
     Level& C = h->lev[d + 1];
     const MatDev A = smoothed(L.A, L.nS, f32);
     // (1) pre-smoothing from zero: u = (D+L)^{-1} f
-    run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, done);
+    if (L.dense_smooth) launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, done);
+    else run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, done);
     // (2a) f_c = R (f - A u)
     spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);
     spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
@@ -741,7 +928,8 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
     // (3) post-smoothing, one backward Gauss-Seidel sweep (S_l^T): the new u solves
     //     (D+U) u = f - L u_old, the strict lower part taken at the old values
     spmv_or_throw(h, L.Ls.mat(f32), 1, u, f32, f, f32, L.t, f32, L.Ls.tpr, done);
-    run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, L.t, u, nullptr, nullptr, done);
+    if (L.dense_smooth) launch_dense_lower_t(h->stream, L.dtri, f32, f32, L.t, u, done);  // (D+U)^{-1} = T^{-T}
+    else run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, L.t, u, nullptr, nullptr, done);
   }
   // systems whose coarsest level is this one: e = A_0^{-1} f (FP64 inverse)
   if (L.dense.nblk > 0) launch_bdense(h->stream, L.dense, f, u, f32, done);
@@ -818,8 +1006,14 @@ static void apply_op(cpc_solver* h, int op, const double* r, double* z, const in
     case CPC_OP_BGS: {
       Level& L = h->lev[0];
       // (D+L)^{-1} f and (D+U)^{-1} f: one forward or backward sweep from a zero start
-      if (op == CPC_OP_FGS) run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, rin, h->u1, nullptr, nullptr, done);
-      else run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, rin, h->u1, nullptr, nullptr, done);
+      if (L.dense_smooth) {
+        if (op == CPC_OP_FGS) launch_dense_lower(h->stream, L.dtri, f32, f32, rin, h->u1, done);
+        else launch_dense_lower_t(h->stream, L.dtri, f32, f32, rin, h->u1, done);
+      } else if (op == CPC_OP_FGS) {
+        run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, rin, h->u1, nullptr, nullptr, done);
+      } else {
+        run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, rin, h->u1, nullptr, nullptr, done);
+      }
       launch_vec(h->stream, 2, n, h->u1, f32, nullptr, false, z, false, done);
       break;
     }
@@ -867,12 +1061,15 @@ static double vcycle_bytes(const cpc_solver* h) {
       const double nz = (double)L.nnzS, n = L.nS, nc = h->lev[d + 1].A.n;
       const double p = (double)L.P.nnz;
       const double half = 0.5 * (nz - n);
-      b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + forward GS from zero
+      const double eb = h->f32 ? 4.0 : 8.0;  // explicit inverse entry
+      if (L.dense_smooth) b += eb * L.dense_entries + 2.0 * vb * n;    // T^{-1} f
+      else b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + forward GS from zero
       b += nz * mb + 4.0 * n + 3.0 * vb * n;                   // residual
       b += p * mb + 4.0 * nc + vb * n + vb * nc;               // restriction
       b += p * mb + 4.0 * n + 2.0 * vb * n + vb * nc;          // prolongation + correction
       b += half * mb + 4.0 * n + 3.0 * vb * n;                 // f - L u (old values)
-      b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + (D+U) solve
+      if (L.dense_smooth) b += eb * L.dense_entries + 2.0 * vb * n;    // T^{-T} (f - L u)
+      else b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + (D+U) solve
     }
     for (int n0 : L.dense_n) b += 8.0 * n0 * n0 + 2.0 * vb * n0;  // exact coarsest solves
   }
@@ -891,8 +1088,10 @@ static double kernel_bytes(const cpc_solver* h, int kernel, int d) {
   const double p = (double)L.P.nnz;
   switch (kernel) {
     case CPC_K_SPMV_PQ: return 12.0 * nz + 4.0 * n + 16.0 * n;
-    case CPC_K_FGS: return (half + n) * mb + 4.0 * n + 2.0 * vb * n;
-    case CPC_K_BGS: return (half + n) * mb + 4.0 * n + 2.0 * vb * n;
+    case CPC_K_FGS:
+    case CPC_K_BGS:
+      if (L.dense_smooth) return (h->f32 ? 4.0 : 8.0) * L.dense_entries + 2.0 * vb * n;
+      return (half + n) * mb + 4.0 * n + 2.0 * vb * n;
     case CPC_K_ILU_L: return half * mb + 4.0 * n + 2.0 * vb * n;
     case CPC_K_ILU_U: return (half + n) * mb + 4.0 * n + 4.0 * vb * n;
     case CPC_K_RESIDUAL: return nz * mb + 4.0 * n + 3.0 * vb * n;
@@ -1154,6 +1353,7 @@ void cpc_default_options(cpc_options* o) {
   o->rap_on_gpu = 1;
   o->sweep_block_rows = 0;
   o->sweep_threads = 0;
+  o->dense_smoother = 0;
   o->theta = 0.25;
 }
 
@@ -1171,6 +1371,7 @@ static cpc_status read_options(const cpc_options* opt, cpc_options& o) {
   if (!(o.theta >= 0.0 && o.theta <= 1.0)) return set_err(CPC_E_ARG, "theta must lie in [0, 1]");
   if (o.sweep_threads != 0 && o.sweep_threads != 64 && o.sweep_threads != 256)
     return set_err(CPC_E_ARG, "sweep_threads must be 0, 64 or 256");
+  if (o.dense_smoother < 0 || o.dense_smoother > 2) return set_err(CPC_E_ARG, "dense_smoother must be 0, 1 or 2");
   return CPC_OK;
 }
 
@@ -1215,6 +1416,7 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
     if (st != CPC_OK) return set_err((cpc_status)st, msg);
     sys.clear();
     allocate_work(h.get());
+    tune_dense(h.get());
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError& e) {
@@ -1280,6 +1482,7 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
     sys.clear();
     allocate_work(h.get());
     allocate_batch(h.get());
+    tune_dense(h.get());
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError& e) {
@@ -1353,6 +1556,15 @@ cpc_status cpc_spmv(cpc_handle h, int32_t level, const double* x_dev, double* y_
   } catch (const HipError& e) {
     return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
   }
+  return CPC_OK;
+}
+
+cpc_status cpc_smoother_kind(cpc_handle h, int32_t level, int32_t* kind) {
+  if (!h || !kind) return set_err(CPC_E_ARG, "null argument");
+  if (level < 0 || level >= (int32_t)h->lev.size()) return set_err(CPC_E_ARG, "level out of range");
+  const Level& L = h->lev[level];
+  if (L.nS <= 0 || level + 1 == (int32_t)h->lev.size()) *kind = -1;
+  else *kind = L.dense_smooth ? 1 : 0;
   return CPC_OK;
 }
 
@@ -1459,6 +1671,12 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         break;
       // triangular solves: the sentinel fill before each launch is not timed
       case CPC_K_FGS:
+        if (L.dense_smooth) {
+          ev_begin();
+          launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, nullptr);
+          ev_end();
+          break;
+        }
         launch_fill_sentinel(h->stream, L.lower.d.n, u, f32, nullptr);
         ev_begin();
         launch_sweep_packed(h->stream, SWEEP_LOWER, L.lower.d, L.fgs, f32, f, u, nullptr, nullptr, h->sync,
@@ -1466,6 +1684,12 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         ev_end();
         break;
       case CPC_K_BGS:
+        if (L.dense_smooth) {
+          ev_begin();
+          launch_dense_lower_t(h->stream, L.dtri, f32, f32, f, u, nullptr);
+          ev_end();
+          break;
+        }
         launch_fill_sentinel(h->stream, L.upper.d.n, u, f32, nullptr);
         ev_begin();
         launch_sweep_packed(h->stream, SWEEP_UPPER, L.upper.d, L.bgs, f32, f, u, nullptr, nullptr, h->sync,

@@ -35,7 +35,7 @@ def _dev_vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
 
 def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, theta=0.25, swap_roles=False,
             check_symmetry=True, use_graph=True, check_every=4, sweep_block_rows=0,
-            sweep_threads=0) -> _lib.Options:
+            sweep_threads=0, dense_smoother=0) -> _lib.Options:
     lib = load()
     o = _lib.Options()
     lib.cpc_default_options(ctypes.byref(o))
@@ -50,6 +50,7 @@ def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, th
     o.check_every = int(check_every)
     o.sweep_block_rows = int(sweep_block_rows)
     o.sweep_threads = int(sweep_threads)
+    o.dense_smoother = _lib.DENSE[dense_smoother] if isinstance(dense_smoother, str) else int(dense_smoother)
     return o
 
 
@@ -151,7 +152,13 @@ class Solver:
         depth = np.zeros(cap, np.int32)
         check(self._lib.cpc_hierarchy_info(self._h, ctypes.byref(nlev), _ptr(n_l), _ptr(nnz_l), _ptr(depth)))
         k = nlev.value
-        return {"nlev": k, "n": n_l[:k].tolist(), "nnz": nnz_l[:k].tolist(), "depth": depth[:k].tolist()}
+        kinds = []
+        for d in range(k):
+            kind = ctypes.c_int32(0)
+            check(self._lib.cpc_smoother_kind(self._h, d, ctypes.byref(kind)))
+            kinds.append({-1: "none", 0: "sweep", 1: "dense"}[kind.value])
+        return {"nlev": k, "n": n_l[:k].tolist(), "nnz": nnz_l[:k].tolist(), "depth": depth[:k].tolist(),
+                "smoother": kinds}
 
     def level(self, level: int):
         info = self.hierarchy()

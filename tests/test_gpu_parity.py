@@ -34,26 +34,29 @@ def relerr(a, b):
 
 
 def small_cases():
-    """name -> (problem, forced rows per sweep block or 0 for the automatic choice)."""
+    """name -> (problem, forced rows per sweep block or 0 for the automatic choice,
+    Gauss-Seidel through explicit inverses of D+L: "never", "always" or "auto")."""
     return {
-        "c1": (gen.config1(), 0),
-        "c1-ragged-blocks": (gen.config1(37, 23), 37),
-        "c2s": (gen.scaled_config(2, 0.15), 0),
-        "c2s-tiny-blocks": (gen.scaled_config(2, 0.15), 7),
-        "c3s": (gen.scaled_config(3, 0.15), 0),
-        "c5s": (gen.scaled_config(5, 0.2), 0),
-        "c2m": (gen.scaled_config(2, 0.3), 0),
-        "c5m": (gen.scaled_config(5, 0.35), 0),
+        "c1": (gen.config1(), 0, "never"),
+        "c1-ragged-blocks": (gen.config1(37, 23), 37, "never"),
+        "c1-dense": (gen.config1(), 0, "always"),
+        "c2s": (gen.scaled_config(2, 0.15), 0, "never"),
+        "c2s-tiny-blocks": (gen.scaled_config(2, 0.15), 7, "never"),
+        "c2s-dense": (gen.scaled_config(2, 0.15), 0, "always"),
+        "c3s": (gen.scaled_config(3, 0.15), 0, "auto"),
+        "c5s": (gen.scaled_config(5, 0.2), 0, "auto"),
+        "c2m": (gen.scaled_config(2, 0.3), 0, "auto"),
+        "c5m": (gen.scaled_config(5, 0.35), 0, "always"),
     }
 
 
 @pytest.fixture(scope="module")
 def cases():
     out = {}
-    for k, (p, R) in small_cases().items():
-        print(f"[case] {k} n={p.n} nnz={p.nnz} block_rows={R}", flush=True)
+    for k, (p, R, dense) in small_cases().items():
+        print(f"[case] {k} n={p.n} nnz={p.nnz} block_rows={R} dense={dense}", flush=True)
         h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
-        s = _cpc().Solver(p.n, p.row_ptr, p.col, p.val, sweep_block_rows=R)
+        s = _cpc().Solver(p.n, p.row_ptr, p.col, p.val, sweep_block_rows=R, dense_smoother=dense)
         out[k] = (p, h, s)
     yield out
     for _, _, s in out.values():
@@ -239,3 +242,19 @@ def test_neg_outer_on_pattern(cases):
     g = s.neg_outer(dev(lam), dev(x)).cpu().numpy()
     rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
     assert np.array_equal(g, -lam[rows] * x[p.col])
+
+
+def test_smoother_kinds_follow_the_option(cases):
+    """Levels of at most 65536 rows are smoothed through explicit inverses exactly when
+    asked ("always"); never when told not to; the coarsest level is not smoothed."""
+    for k, (p, R, dense) in small_cases().items():
+        info = cases[k][2].hierarchy()
+        kinds = info["smoother"]
+        assert kinds[-1] == "none", k
+        for d in range(info["nlev"] - 1):
+            if dense == "never":
+                assert kinds[d] == "sweep", (k, d)
+            elif dense == "always":
+                assert kinds[d] == ("dense" if info["n"][d] <= 65536 else "sweep"), (k, d)
+            else:
+                assert kinds[d] in ("sweep", "dense"), (k, d)
