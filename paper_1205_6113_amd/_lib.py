@@ -78,7 +78,7 @@ def load():
     lib.cpc_spmv.restype = I32
     lib.cpc_hierarchy_info.argtypes = [P, ctypes.POINTER(I32), P, P, P]
     lib.cpc_hierarchy_info.restype = I32
-    lib.cpc_smoother_kind.argtypes = [P, I32, ctypes.POINTER(I32)]
+    lib.cpc_smoother_kind.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.cpc_smoother_kind.restype = I32
     lib.cpc_get_level.argtypes = [P, I32, P, P, P]
     lib.cpc_get_level.restype = I32

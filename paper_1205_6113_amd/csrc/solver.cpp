@@ -122,6 +122,10 @@ struct Level {
   void* dense_MT = nullptr;    // its transpose (small systems), same ownership
   bool dense_smooth = false;   // smooth through dtri instead of the level-scheduled sweeps
   double dense_entries = 0.0;  // stored lower-triangle entries (byte model)
+  // device memory of this level's sweep schedules and packs (replaced by the tuner)
+  std::vector<void*> sweep_owned;
+  int sweep_rows = 0;  // rows the sweeps cover (all rows at depth 0 for ILU(0), else the smoothed ones)
+  int sweep_R = 0;     // rows per block requested for them
 };
 
 }  // namespace cpc
@@ -149,6 +153,7 @@ struct cpc_solver {
   long spin_limit = 1L << 22;
   cpc_stats stats{};
   std::vector<void*> owned;
+  std::vector<void*>* cur_owned = &owned;  // where sweep schedules and packs are allocated
   // captured iteration graphs, one per preconditioner
   hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   hipGraph_t graph_src[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -175,6 +180,7 @@ struct cpc_solver {
     for (auto& L : lev) {
       if (L.dense_M) (void)hipFree(L.dense_M);
       if (L.dense_MT) (void)hipFree(L.dense_MT);
+      for (void* ptr : L.sweep_owned) (void)hipFree(ptr);
     }
     for (void* ptr : owned) (void)hipFree(ptr);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -357,10 +363,10 @@ static SweepSchedule make_sweep(cpc_solver* h, const HostCsr& a, bool forward, i
   sd.nblk = s.nblk;
   sd.nlev = (int)s.lvl_ptr.size() - 1;
   sd.maxl = s.max_local_levels;
-  sd.blk_row = dupload(s.blk_row, h->owned, h->stream);
-  sd.blk_beg = dupload(s.blk_beg, h->owned, h->stream);
-  sd.blk_end = dupload(s.blk_end, h->owned, h->stream);
-  sd.lvl_ptr = dupload(s.lvl_ptr, h->owned, h->stream);
+  sd.blk_row = dupload(s.blk_row, *h->cur_owned, h->stream);
+  sd.blk_beg = dupload(s.blk_beg, *h->cur_owned, h->stream);
+  sd.blk_end = dupload(s.blk_end, *h->cur_owned, h->stream);
+  sd.lvl_ptr = dupload(s.lvl_ptr, *h->cur_owned, h->stream);
   sd.grid = std::min(s.nblk, 1024);
   // four waves per block; a one-wave workgroup (no cross-wave barriers) measured
   // slower even where one block covers the matrix, since a level's entries then take
@@ -423,17 +429,17 @@ static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vecto
     pk.ptr = share->ptr;
     pk.col = share->col;
   } else {
-    pk.row = dupload(s.perm, h->owned, h->stream);
-    pk.ptr = dupload(ptr, h->owned, h->stream);
-    pk.col = dupload(col, h->owned, h->stream);
+    pk.row = dupload(s.perm, *h->cur_owned, h->stream);
+    pk.ptr = dupload(ptr, *h->cur_owned, h->stream);
+    pk.col = dupload(col, *h->cur_owned, h->stream);
   }
   if (h->f32) {
     std::vector<float> v32(v.begin(), v.end()), d32(diag.begin(), diag.end());
-    pk.val = dupload(v32, h->owned, h->stream);
-    pk.diag = dupload(d32, h->owned, h->stream);
+    pk.val = dupload(v32, *h->cur_owned, h->stream);
+    pk.diag = dupload(d32, *h->cur_owned, h->stream);
   } else {
-    pk.val = dupload(v, h->owned, h->stream);
-    pk.diag = dupload(diag, h->owned, h->stream);
+    pk.val = dupload(v, *h->cur_owned, h->stream);
+    pk.diag = dupload(diag, *h->cur_owned, h->stream);
   }
   // lanes per row in the summing phase: about eight products per lane
   const double avg = n ? (double)ne / n : 0.0;
@@ -704,6 +710,92 @@ static void tune_dense(cpc_solver* h) {
   if (herr) throw HipError{hipErrorUnknown, "a sweep wait exceeded its bound while tuning"};
 }
 
+// Schedules and packed rows of a level's triangular solves with blocks of R rows
+// (and the ILU(0) packs on the finest level), allocated in the level's own list.
+static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int R, bool ilu) {
+  std::vector<void*>* prev = h->cur_owned;
+  h->cur_owned = &L.sweep_owned;
+  try {
+    SweepSchedule lo = make_sweep(h, sub, true, R, L.lower);
+    SweepSchedule up = make_sweep(h, sub, false, R, L.upper);
+    L.fgs = build_pack(h, sub, sub.v, lo, nullptr);
+    L.bgs = build_pack(h, sub, sub.v, up, nullptr);
+    if (ilu) {
+      h->ilu_l = build_pack(h, sub, h->lu_host, lo, &L.fgs);
+      h->ilu_u = build_pack(h, sub, h->lu_host, up, &L.bgs);
+    }
+  } catch (...) {
+    h->cur_owned = prev;
+    throw;
+  }
+  h->cur_owned = prev;
+  L.sweep_R = R;
+}
+
+// Rows per sweep block, level by level: the candidates' schedules are built and
+// their forward and backward solves (and, on the finest level, the ILU(0) solves)
+// timed on the level's own matrix; the fastest stays. A forced block size skips this.
+static void tune_sweeps(cpc_solver* h) {
+  if (h->opt.sweep_block_rows > 0) return;
+  for (size_t d = 0; d < h->lev.size(); ++d) {
+    Level& L = h->lev[d];
+    if (L.sweep_rows <= 4096 || (L.dense_smooth && d > 0)) continue;
+    const bool ilu = d == 0;
+    const HostCsr sub = L.sweep_rows == L.A_host.n ? L.A_host : leading_rows(L.A_host, L.sweep_rows);
+    void* f = d == 0 ? h->pin : L.f;
+    void* u = d == 0 ? h->u1 : L.u;
+    auto cost = [&] {
+      return time_ms(h, 3, [&] {
+        if (!L.dense_smooth) {
+          run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
+          run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
+        }
+        if (ilu) {
+          run_sweep(h, SWEEP_UNIT_LOWER, L.lower, h->ilu_l, h->res, h->y, nullptr, nullptr, nullptr);
+          run_sweep(h, SWEEP_UPPER_OUT, L.upper, h->ilu_u, h->y, h->w, h->u1, h->u2, nullptr);
+        }
+      });
+    };
+    float best = cost();
+    for (int R : {1024, 2048, 4096, 8192}) {
+      if (R == L.sweep_R || R >= L.sweep_rows) continue;
+      // keep the current build aside, try the candidate in a list of its own
+      DevSweepSched lo = L.lower, up = L.upper;
+      SweepPackDev fg = L.fgs, bg = L.bgs, il = h->ilu_l, iu = h->ilu_u;
+      const int oldR = L.sweep_R;
+      std::vector<void*> old;
+      old.swap(L.sweep_owned);
+      bool built = true;
+      try {
+        build_level_sweeps(h, L, sub, R, ilu);
+      } catch (const HipError&) {
+        built = false;  // the candidate does not fit the sweep kernel's LDS
+        (void)hipGetLastError();
+      }
+      const float t = built ? cost() : 0.f;
+      if (built && t < best) {
+        best = t;
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (void* p : old) (void)hipFree(p);
+      } else {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (void* p : L.sweep_owned) (void)hipFree(p);
+        L.sweep_owned.swap(old);
+        L.lower = lo;
+        L.upper = up;
+        L.fgs = fg;
+        L.bgs = bg;
+        h->ilu_l = il;
+        h->ilu_u = iu;
+        L.sweep_R = oldR;
+      }
+    }
+  }
+  unsigned herr = 0;
+  HIPCHK(hipMemcpy(&herr, h->sync.err, sizeof(unsigned), hipMemcpyDeviceToHost));
+  if (herr) throw HipError{hipErrorUnknown, "a sweep wait exceeded its bound while tuning"};
+}
+
 // Concatenate the systems' hierarchies depth by depth and upload them. At depth d
 // the level vector holds, in this order, the systems that are smoothed at d (still
 // coarsened further) and then the systems whose coarsest level is d; matrices are
@@ -795,14 +887,8 @@ static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_o
       HostCsr sub = (rows == ntot[d]) ? A : leading_rows(A, rows);
       const int Rb = o.sweep_block_rows > 0 ? std::min(o.sweep_block_rows, sweep_max_rows_per_block())
                                             : choose_block_rows(rows);
-      SweepSchedule lo = make_sweep(h, sub, true, Rb, L.lower);
-      SweepSchedule up = make_sweep(h, sub, false, Rb, L.upper);
-      L.fgs = build_pack(h, sub, sub.v, lo, nullptr);
-      L.bgs = build_pack(h, sub, sub.v, up, nullptr);
-      if (d == 0) {
-        h->ilu_l = build_pack(h, sub, h->lu_host, lo, &L.fgs);
-        h->ilu_u = build_pack(h, sub, h->lu_host, up, &L.bgs);
-      }
+      L.sweep_rows = rows;
+      build_level_sweeps(h, L, sub, Rb, d == 0);
       upload_csr(h, strict_lower(sub), L.Ls, false);
       L.t = valloc(h, rows);
       if (L.nS > 0 && d + 1 < D) {
@@ -1417,6 +1503,7 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
     sys.clear();
     allocate_work(h.get());
     tune_dense(h.get());
+    tune_sweeps(h.get());
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError& e) {
@@ -1483,6 +1570,7 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
     allocate_work(h.get());
     allocate_batch(h.get());
     tune_dense(h.get());
+    tune_sweeps(h.get());
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError& e) {
@@ -1559,10 +1647,11 @@ cpc_status cpc_spmv(cpc_handle h, int32_t level, const double* x_dev, double* y_
   return CPC_OK;
 }
 
-cpc_status cpc_smoother_kind(cpc_handle h, int32_t level, int32_t* kind) {
+cpc_status cpc_smoother_kind(cpc_handle h, int32_t level, int32_t* kind, int32_t* block_rows) {
   if (!h || !kind) return set_err(CPC_E_ARG, "null argument");
   if (level < 0 || level >= (int32_t)h->lev.size()) return set_err(CPC_E_ARG, "level out of range");
   const Level& L = h->lev[level];
+  if (block_rows) *block_rows = L.sweep_R;
   if (L.nS <= 0 || level + 1 == (int32_t)h->lev.size()) *kind = -1;
   else *kind = L.dense_smooth ? 1 : 0;
   return CPC_OK;

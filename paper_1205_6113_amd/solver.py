@@ -152,13 +152,15 @@ class Solver:
         depth = np.zeros(cap, np.int32)
         check(self._lib.cpc_hierarchy_info(self._h, ctypes.byref(nlev), _ptr(n_l), _ptr(nnz_l), _ptr(depth)))
         k = nlev.value
-        kinds = []
+        kinds, rows = [], []
         for d in range(k):
             kind = ctypes.c_int32(0)
-            check(self._lib.cpc_smoother_kind(self._h, d, ctypes.byref(kind)))
+            br = ctypes.c_int32(0)
+            check(self._lib.cpc_smoother_kind(self._h, d, ctypes.byref(kind), ctypes.byref(br)))
             kinds.append({-1: "none", 0: "sweep", 1: "dense"}[kind.value])
+            rows.append(br.value)
         return {"nlev": k, "n": n_l[:k].tolist(), "nnz": nnz_l[:k].tolist(), "depth": depth[:k].tolist(),
-                "smoother": kinds}
+                "smoother": kinds, "block_rows": rows}
 
     def level(self, level: int):
         info = self.hierarchy()
