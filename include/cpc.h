@@ -85,9 +85,11 @@ typedef struct {
   int32_t rap_on_gpu;     /* 1: Galerkin products on the GPU (default); 0 is not offered     */
   int32_t sweep_block_rows; /* rows per workgroup block of the triangular sweeps (0 = auto)  */
   int32_t sweep_threads;  /* threads per sweep workgroup: 64 (one wave) or 256; 0 = auto     */
-  int32_t dense_smoother; /* Gauss-Seidel on levels of <= 65536 rows through an explicit
-                             inverse of D+L: 0 = where measured faster at setup, 1 = never,
-                             2 = wherever it fits                                           */
+  int32_t dense_smoother; /* Gauss-Seidel through explicit inverses of D+L (whole level,
+                             <= 65536 rows) or of its diagonal blocks (block substitution):
+                             0 = where measured faster at setup, 1 = never, 2 = whole-level
+                             inverses wherever they fit, 3 = blocks of 2048 rows on every
+                             smoothed level of more than 4096 rows                          */
   double theta;           /* strength threshold of the classical coarsening (0.25)          */
 } cpc_options;
 

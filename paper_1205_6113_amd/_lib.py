@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "CPC_OK", 1: "CPC_E_ARG", 2: "CPC_E_NOT_SPD", 3: "CPC_E_BREAK
 PREC = {"combined": 0, "amg": 1, "ilu": 2, "additive": 3, "none": 4}
 OP = {"combined": 0, "amg": 1, "ilu": 2, "additive": 3, "none": 4, "vcycle": 5, "fgs": 6, "bgs": 7}
 PRECISION = {"fp64": 0, "fp32": 1}
-DENSE = {"auto": 0, "never": 1, "always": 2}
+DENSE = {"auto": 0, "never": 1, "always": 2, "block": 3}
 
 # every entry point declared in include/cpc.h
 EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "cpc_apply_op", "cpc_spmv",

@@ -16,8 +16,8 @@
 // B <- -C^{-1} B A^{-1} from two matrix products (library GEMMs), where A^{-1}, C^{-1}
 // are the inverted diagonal spans. The result is T^{-1}, lower triangular.
 //
-// Products: y = T^{-1} f by one wave per row (coalesced row reads, the vector from
-// L2). y = T^{-T} g: on smaller systems from a stored transpose, row by row like the
+// Products: y = T^{-1} f by one workgroup per row (coalesced row reads, the vector
+// from L2). y = T^{-T} g: on smaller systems from a stored transpose, row by row like the
 // forward product; on larger ones by items (column block of 512, chunk of 1024 rows)
 // whose partial column sums go to a buffer and are added in chunk order
 // (deterministic), which reads each stored entry once without a second copy.
@@ -43,8 +43,8 @@ __device__ __forceinline__ double wsum(double v) {
   return v;
 }
 
-// T (rows [0, n) of a CSR whose columns are offset by voff) into the dense row-major
-// array M (leading dimension n): lower triangle only (upper entries stay zero).
+// The diagonal block of T on rows and columns [voff, voff + n) of a CSR into the dense
+// row-major array M (leading dimension n): lower triangle only (upper entries stay zero).
 __global__ __launch_bounds__(kNT) void scatter_lower_kernel(int n, int voff, const int* __restrict__ rp,
                                                            const int* __restrict__ ci,
                                                            const double* __restrict__ v, double* __restrict__ M) {
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kNT) void scatter_lower_kernel(int n, int voff, con
     const int r = voff + i;
     for (int p = rp[r]; p < rp[r + 1]; ++p) {
       const int j = ci[p] - voff;
-      if (j <= i) M[(long)i * n + j] = v[p];
+      if (j >= 0 && j <= i) M[(long)i * n + j] = v[p];  // the diagonal block only
     }
   }
 }
@@ -113,10 +113,13 @@ __global__ __launch_bounds__(kNT) void to_type_kernel(long n, const double* __re
 }
 
 // y = M f with M lower (y = T^{-1} f) or upper (y = T^{-T} g from the stored
-// transpose) triangular: one wave per row, items (system, first row, end row).
+// transpose) triangular. Items (system, first row, end row); the whole workgroup
+// reads one row at a time (four independent partial sums per thread, so each thread
+// keeps four loads in flight), then adds the 256 partials in a fixed order.
 template <bool UPPER, typename MT, typename XT>
 __global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
                                                             XT* __restrict__ y, const int* __restrict__ done) {
+  __shared__ double red[kNT / 64];
   if (done && *done) return;
   const int4 it = dt.item_n[blockIdx.x];
   const int s = it.x;
@@ -124,21 +127,24 @@ __global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, cons
   const int voff = dt.voff[s];
   const MT* __restrict__ M = reinterpret_cast<const MT*>(UPPER ? dt.MT : dt.M) + dt.moff[s];
   const XT* __restrict__ fs = f + voff;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int i = it.y + w; i < it.z; i += kNT / 64) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i = it.y; i < it.z; ++i) {
     const MT* __restrict__ row = M + (long)i * n;
     const int jb = UPPER ? i : 0, je = UPPER ? n : i + 1;  // stored entries [jb, je)
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int j = jb + lane;
-    for (; j + 192 < je; j += 256) {
+    int j = jb + tid;
+    for (; j + 3 * kNT < je; j += 4 * kNT) {
       a0 += (double)row[j] * (double)fs[j];
-      a1 += (double)row[j + 64] * (double)fs[j + 64];
-      a2 += (double)row[j + 128] * (double)fs[j + 128];
-      a3 += (double)row[j + 192] * (double)fs[j + 192];
+      a1 += (double)row[j + kNT] * (double)fs[j + kNT];
+      a2 += (double)row[j + 2 * kNT] * (double)fs[j + 2 * kNT];
+      a3 += (double)row[j + 3 * kNT] * (double)fs[j + 3 * kNT];
     }
-    for (; j < je; j += 64) a0 += (double)row[j] * (double)fs[j];
-    double acc = wsum<64>((a0 + a1) + (a2 + a3));
-    if (lane == 0) y[voff + i] = (XT)acc;
+    for (; j < je; j += kNT) a0 += (double)row[j] * (double)fs[j];
+    const double v = wsum<64>((a0 + a1) + (a2 + a3));
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (tid == 0) y[voff + i] = (XT)((red[0] + red[1]) + (red[2] + red[3]));
+    __syncthreads();
   }
 }
 

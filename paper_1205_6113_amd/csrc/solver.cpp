@@ -120,12 +120,23 @@ struct Level {
   DenseTriDev dtri{};
   void* dense_M = nullptr;     // held here until the setup tuner keeps or drops it
   void* dense_MT = nullptr;    // its transpose (small systems), same ownership
+  std::vector<void*> dense_owned;  // the kept inverse (and transpose)
   bool dense_smooth = false;   // smooth through dtri instead of the level-scheduled sweeps
   double dense_entries = 0.0;  // stored lower-triangle entries (byte model)
   // device memory of this level's sweep schedules and packs (replaced by the tuner)
   std::vector<void*> sweep_owned;
   int sweep_rows = 0;  // rows the sweeps cover (all rows at depth 0 for ILU(0), else the smoothed ones)
   int sweep_R = 0;     // rows per block requested for them
+  // block-dense form of the smoother: block forward/backward substitution with explicit
+  // inverses of the diagonal blocks of D+L (levels where it beats the sweeps)
+  bool bdense = false;
+  int bd_B = 0;
+  std::vector<int> bd_start;     // K + 1 block starts
+  DenseTriDev bd_dt{};           // the diagonal blocks as systems
+  std::vector<int> bd_item_off;  // K + 1 offsets of each block's row items
+  DevCsr bd_Loff, bd_Uoff;       // lower / upper entries outside the row's block
+  std::vector<void*> bd_owned;
+  double bd_entries = 0.0;       // stored inverse entries (byte model)
 };
 
 }  // namespace cpc
@@ -181,6 +192,8 @@ struct cpc_solver {
       if (L.dense_M) (void)hipFree(L.dense_M);
       if (L.dense_MT) (void)hipFree(L.dense_MT);
       for (void* ptr : L.sweep_owned) (void)hipFree(ptr);
+      for (void* ptr : L.bd_owned) (void)hipFree(ptr);
+      for (void* ptr : L.dense_owned) (void)hipFree(ptr);
     }
     for (void* ptr : owned) (void)hipFree(ptr);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -557,7 +570,7 @@ static long dense_work_need(int n) {
 }
 
 static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, const std::vector<int>& voffs) {
-  if (h->opt.dense_smoother == 1 || ns.empty()) return;
+  if (h->opt.dense_smoother == 1 || h->opt.dense_smoother == 3 || ns.empty()) return;
   double bytes = 0.0;
   for (int n : ns) {
     if (n > kDenseMaxRows) return;
@@ -612,7 +625,7 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
   for (int k = 0; k < (int)ns.size(); ++k) {
     const int n = ns[k];
     ent += 0.5 * (double)n * (n + 1);
-    for (int r = 0; r < n; r += 16) itn.push_back(make_int4(k, r, std::min(r + 16, n), 0));
+    for (int r = 0; r < n; r += 4) itn.push_back(make_int4(k, r, std::min(r + 4, n), 0));
     for (int c0 = 0; c0 < n; c0 += kTCols) {
       const int first = slot;
       for (int r0 = (c0 / kTChunk) * kTChunk; r0 < n; r0 += kTChunk) itt.push_back(make_int4(k, c0, r0, slot++));
@@ -692,8 +705,8 @@ static void tune_dense(cpc_solver* h) {
       keep = td < ts;
     }
     if (keep) {
-      h->owned.push_back(L.dense_M);
-      if (L.dense_MT) h->owned.push_back(L.dense_MT);
+      L.dense_owned.push_back(L.dense_M);
+      if (L.dense_MT) L.dense_owned.push_back(L.dense_MT);
       L.dense_smooth = true;
     } else {
       (void)hipFree(L.dense_M);
@@ -732,14 +745,169 @@ static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int 
   L.sweep_R = R;
 }
 
+// Block-dense form of a level's Gauss-Seidel factor T = D + L with blocks of B rows:
+// the forward solve is, block by block, g_b = f_b - (T entries left of the block) x,
+// x_b = T_bb^{-1} g_b; the backward solve with T^T = D + U runs the blocks in reverse
+// with the entries right of the block and x_b = T_bb^{-T} g_b. Returns false (nothing
+// kept) when it does not fit or a step fails.
+static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B) {
+  const int n = sub.n;
+  std::vector<int> st;
+  for (int r = 0; r < n; r += B) st.push_back(r);
+  st.push_back(n);
+  const int K = (int)st.size() - 1;
+  double bytes = 0.0;
+  for (int b = 0; b < K; ++b) bytes += 16.0 * (st[b + 1] - st[b]) * (double)(st[b + 1] - st[b]);
+  if (bytes > 32e9) return false;
+  HostCsr lo, up;
+  lo.n = up.n = n;
+  lo.ncols = up.ncols = sub.ncols;
+  lo.rp.assign(1, 0);
+  up.rp.assign(1, 0);
+  for (int i = 0; i < n; ++i) {
+    const int b0 = (i / B) * B, b1 = std::min(b0 + B, n);
+    for (int q = sub.rp[i]; q < sub.rp[i + 1]; ++q) {
+      const int j = sub.ci[q];
+      if (j < b0) {
+        lo.ci.push_back(j);
+        lo.v.push_back(sub.v[q]);
+      } else if (j >= b1) {
+        up.ci.push_back(j);
+        up.v.push_back(sub.v[q]);
+      }
+    }
+    lo.rp.push_back((int)lo.ci.size());
+    up.rp.push_back((int)up.ci.size());
+  }
+  std::vector<void*> own;
+  std::vector<long> moff(K);
+  std::vector<int> nbs(K);
+  long tot = 0, wmax = 1;
+  for (int b = 0; b < K; ++b) {
+    nbs[b] = st[b + 1] - st[b];
+    moff[b] = tot;
+    tot += (long)nbs[b] * nbs[b];
+    wmax = std::max(wmax, dense_work_need(nbs[b]));
+  }
+  auto drop = [&] {
+    (void)hipStreamSynchronize(h->stream);
+    for (void* p : own) (void)hipFree(p);
+    (void)hipGetLastError();
+    return false;
+  };
+  double* M64 = nullptr;
+  double* work = nullptr;
+  if (hipMalloc(&M64, sizeof(double) * tot) != hipSuccess) return drop();
+  if (hipMalloc(&work, sizeof(double) * wmax) != hipSuccess) {
+    (void)hipFree(M64);
+    return drop();
+  }
+  bool ok = true;
+  std::string msg;
+  for (int b = 0; ok && b < K; ++b)
+    ok = dense_tri_inverse(h->stream, nbs[b], st[b], L.A.rp, L.A.ci, L.A.v, M64 + moff[b], work, &msg);
+  ok = ok && hipStreamSynchronize(h->stream) == hipSuccess;
+  (void)hipFree(work);
+  if (!ok) {
+    (void)hipFree(M64);
+    return drop();
+  }
+  const size_t es = h->f32 ? sizeof(float) : sizeof(double);
+  void* M = M64;
+  if (h->f32) {
+    float* M32 = nullptr;
+    if (hipMalloc(&M32, sizeof(float) * tot) != hipSuccess) {
+      (void)hipFree(M64);
+      return drop();
+    }
+    launch_to_type(h->stream, tot, M64, M32, true);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(M64);
+    M = M32;
+  }
+  own.push_back(M);
+  void* MT = nullptr;
+  if (hipMalloc(&MT, es * tot) != hipSuccess) return drop();
+  own.push_back(MT);
+  for (int b = 0; b < K; ++b)
+    launch_transpose(h->stream, nbs[b], (const char*)M + es * moff[b], (char*)MT + es * moff[b], h->f32);
+  std::vector<int4> itn;
+  std::vector<int> ioff(1, 0);
+  double ent = 0.0;
+  for (int b = 0; b < K; ++b) {
+    for (int r = 0; r < nbs[b]; r += 4) itn.push_back(make_int4(b, r, std::min(r + 4, nbs[b]), 0));
+    ioff.push_back((int)itn.size());
+    ent += 0.5 * (double)nbs[b] * (nbs[b] + 1);
+  }
+  try {
+    upload_csr(h, lo, L.bd_Loff, false, &own);
+    upload_csr(h, up, L.bd_Uoff, false, &own);
+    DenseTriDev& dt = L.bd_dt;
+    dt = DenseTriDev{};
+    dt.n = dupload(nbs, own, h->stream);
+    dt.moff = dupload(moff, own, h->stream);
+    std::vector<int> voff(st.begin(), st.end() - 1);
+    dt.voff = dupload(voff, own, h->stream);
+    dt.M = M;
+    dt.MT = MT;
+    dt.nitem_n = (int)itn.size();
+    dt.item_n = dupload(itn, own, h->stream);
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError&) {
+    L.bd_dt = DenseTriDev{};
+    return drop();
+  }
+  L.bd_B = B;
+  L.bd_start = st;
+  L.bd_item_off = ioff;
+  L.bd_entries = ent;
+  L.bd_owned.swap(own);
+  return true;
+}
+
+static void free_blockdense(cpc_solver* h, Level& L) {
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (void* p : L.bd_owned) (void)hipFree(p);
+  L.bd_owned.clear();
+  L.bd_dt = DenseTriDev{};
+  L.bd_start.clear();
+  L.bd_item_off.clear();
+  L.bd_B = 0;
+  L.bd_entries = 0.0;
+  L.bdense = false;
+}
+
+// x = T^{-1} f (upper = false) or x = T^{-T} f (upper = true) through the block-dense
+// form; g is a scratch vector of the level.
+static void bdense_solve(cpc_solver* h, Level& L, bool upper, const void* f, void* x, void* g, const int* done) {
+  const bool f32 = h->f32;
+  const size_t es = esz_of(h);
+  const int K = (int)L.bd_start.size() - 1;
+  const DevCsr& off = upper ? L.bd_Uoff : L.bd_Loff;
+  for (int t = 0; t < K; ++t) {
+    const int b = upper ? K - 1 - t : t;
+    const int r0 = L.bd_start[b], nb = L.bd_start[b + 1] - r0;
+    MatDev m = off.mat(f32);
+    m.n = nb;
+    m.rp = off.rp + r0;
+    spmv_or_throw(h, m, 1, x, f32, (const char*)f + es * r0, f32, (char*)g + es * r0, f32, off.tpr, done);
+    DenseTriDev dt = L.bd_dt;
+    dt.item_n += L.bd_item_off[b];
+    dt.nitem_n = L.bd_item_off[b + 1] - L.bd_item_off[b];
+    if (upper) launch_dense_lower_t(h->stream, dt, f32, f32, g, x, done);
+    else launch_dense_lower(h->stream, dt, f32, f32, g, x, done);
+  }
+}
+
 // Rows per sweep block, level by level: the candidates' schedules are built and
 // their forward and backward solves (and, on the finest level, the ILU(0) solves)
 // timed on the level's own matrix; the fastest stays. A forced block size skips this.
 static void tune_sweeps(cpc_solver* h) {
-  if (h->opt.sweep_block_rows > 0) return;
+  if (h->opt.sweep_block_rows > 0 && h->opt.dense_smoother != 3) return;
+  const bool f32 = h->f32;
   for (size_t d = 0; d < h->lev.size(); ++d) {
     Level& L = h->lev[d];
-    if (L.sweep_rows <= 4096 || (L.dense_smooth && d > 0)) continue;
+    if (L.sweep_rows <= 4096) continue;
     const bool ilu = d == 0;
     const HostCsr sub = L.sweep_rows == L.A_host.n ? L.A_host : leading_rows(L.A_host, L.sweep_rows);
     void* f = d == 0 ? h->pin : L.f;
@@ -756,9 +924,9 @@ static void tune_sweeps(cpc_solver* h) {
         }
       });
     };
-    float best = cost();
+    float best = (L.dense_smooth && !ilu) ? 0.f : cost();
     for (int R : {1024, 2048, 4096, 8192}) {
-      if (R == L.sweep_R || R >= L.sweep_rows) continue;
+      if (R == L.sweep_R || R >= L.sweep_rows || (L.dense_smooth && !ilu)) continue;
       // keep the current build aside, try the candidate in a list of its own
       DevSweepSched lo = L.lower, up = L.upper;
       SweepPackDev fg = L.fgs, bg = L.bgs, il = h->ilu_l, iu = h->ilu_u;
@@ -788,6 +956,77 @@ static void tune_sweeps(cpc_solver* h) {
         h->ilu_l = il;
         h->ilu_u = iu;
         L.sweep_R = oldR;
+      }
+    }
+    // block-dense form of the Gauss-Seidel factor, blocks of 2048 / 4096 / 8192 rows
+    if (h->opt.dense_smoother == 3 && d + 1 < h->lev.size()) {
+      if (build_blockdense(h, L, sub, 2048)) L.bdense = true;  // forced form (tests)
+      continue;
+    }
+    if (L.sweep_rows > 8192 && d + 1 < h->lev.size() && h->opt.dense_smoother != 1 &&
+        h->opt.dense_smoother != 2) {
+      auto gs_cost = [&] {
+        return time_ms(h, 3, [&] {
+          if (L.bdense) {
+            bdense_solve(h, L, false, f, u, L.r, nullptr);
+            bdense_solve(h, L, true, f, u, L.r, nullptr);
+          } else if (L.dense_smooth) {
+            launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, nullptr);
+            launch_dense_lower_t(h->stream, L.dtri, f32, f32, f, u, nullptr);
+          } else {
+            run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
+            run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
+          }
+        });
+      };
+      float gbest = gs_cost();
+      const bool was_dense = L.dense_smooth;
+      for (int B : {1024, 2048, 4096, 8192}) {
+        if (B >= L.sweep_rows) continue;
+        // the current best block-dense form (if any) is set aside while B is tried
+        Level keep;
+        keep.bdense = L.bdense;
+        keep.bd_B = L.bd_B;
+        keep.bd_start.swap(L.bd_start);
+        keep.bd_dt = L.bd_dt;
+        keep.bd_item_off.swap(L.bd_item_off);
+        keep.bd_Loff = L.bd_Loff;
+        keep.bd_Uoff = L.bd_Uoff;
+        keep.bd_owned.swap(L.bd_owned);
+        keep.bd_entries = L.bd_entries;
+        L.bdense = false;
+        bool better = false;
+        if (build_blockdense(h, L, sub, B)) {
+          L.bdense = true;
+          L.dense_smooth = false;
+          const float t = gs_cost();
+          L.dense_smooth = was_dense && !(t < gbest);
+          better = t < gbest;
+          if (better) gbest = t;
+        }
+        if (better) {
+          HIPCHK(hipStreamSynchronize(h->stream));
+          for (void* p : keep.bd_owned) (void)hipFree(p);
+        } else {
+          free_blockdense(h, L);
+          L.bdense = keep.bdense;
+          L.bd_B = keep.bd_B;
+          L.bd_start.swap(keep.bd_start);
+          L.bd_dt = keep.bd_dt;
+          L.bd_item_off.swap(keep.bd_item_off);
+          L.bd_Loff = keep.bd_Loff;
+          L.bd_Uoff = keep.bd_Uoff;
+          L.bd_owned.swap(keep.bd_owned);
+          L.bd_entries = keep.bd_entries;
+        }
+      }
+      if (L.bdense && was_dense) {  // the block form replaces the whole-level inverse
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (void* p : L.dense_owned) (void)hipFree(p);
+        L.dense_owned.clear();
+        L.dtri = DenseTriDev{};
+        L.dense_entries = 0.0;
+        L.dense_smooth = false;
       }
     }
   }
@@ -1003,6 +1242,7 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
     const MatDev A = smoothed(L.A, L.nS, f32);
     // (1) pre-smoothing from zero: u = (D+L)^{-1} f
     if (L.dense_smooth) launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, done);
+    else if (L.bdense) bdense_solve(h, L, false, f, u, L.r, done);
     else run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, done);
     // (2a) f_c = R (f - A u)
     spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);
@@ -1015,6 +1255,7 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
     //     (D+U) u = f - L u_old, the strict lower part taken at the old values
     spmv_or_throw(h, L.Ls.mat(f32), 1, u, f32, f, f32, L.t, f32, L.Ls.tpr, done);
     if (L.dense_smooth) launch_dense_lower_t(h->stream, L.dtri, f32, f32, L.t, u, done);  // (D+U)^{-1} = T^{-T}
+    else if (L.bdense) bdense_solve(h, L, true, L.t, u, L.r, done);
     else run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, L.t, u, nullptr, nullptr, done);
   }
   // systems whose coarsest level is this one: e = A_0^{-1} f (FP64 inverse)
@@ -1095,6 +1336,8 @@ static void apply_op(cpc_solver* h, int op, const double* r, double* z, const in
       if (L.dense_smooth) {
         if (op == CPC_OP_FGS) launch_dense_lower(h->stream, L.dtri, f32, f32, rin, h->u1, done);
         else launch_dense_lower_t(h->stream, L.dtri, f32, f32, rin, h->u1, done);
+      } else if (L.bdense) {
+        bdense_solve(h, L, op == CPC_OP_BGS, rin, h->u1, L.r, done);
       } else if (op == CPC_OP_FGS) {
         run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, rin, h->u1, nullptr, nullptr, done);
       } else {
@@ -1148,13 +1391,16 @@ static double vcycle_bytes(const cpc_solver* h) {
       const double p = (double)L.P.nnz;
       const double half = 0.5 * (nz - n);
       const double eb = h->f32 ? 4.0 : 8.0;  // explicit inverse entry
-      if (L.dense_smooth) b += eb * L.dense_entries + 2.0 * vb * n;    // T^{-1} f
+      const double bdb = eb * L.bd_entries + (double)L.bd_Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
+      if (L.bdense) b += bdb;                                     // block-dense T^{-1} f
+      else if (L.dense_smooth) b += eb * L.dense_entries + 2.0 * vb * n;    // T^{-1} f
       else b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + forward GS from zero
       b += nz * mb + 4.0 * n + 3.0 * vb * n;                   // residual
       b += p * mb + 4.0 * nc + vb * n + vb * nc;               // restriction
       b += p * mb + 4.0 * n + 2.0 * vb * n + vb * nc;          // prolongation + correction
       b += half * mb + 4.0 * n + 3.0 * vb * n;                 // f - L u (old values)
-      if (L.dense_smooth) b += eb * L.dense_entries + 2.0 * vb * n;    // T^{-T} (f - L u)
+      if (L.bdense) b += bdb;                                     // block-dense T^{-T} (f - L u)
+      else if (L.dense_smooth) b += eb * L.dense_entries + 2.0 * vb * n;    // T^{-T} (f - L u)
       else b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + (D+U) solve
     }
     for (int n0 : L.dense_n) b += 8.0 * n0 * n0 + 2.0 * vb * n0;  // exact coarsest solves
@@ -1176,6 +1422,8 @@ static double kernel_bytes(const cpc_solver* h, int kernel, int d) {
     case CPC_K_SPMV_PQ: return 12.0 * nz + 4.0 * n + 16.0 * n;
     case CPC_K_FGS:
     case CPC_K_BGS:
+      if (L.bdense)
+        return (h->f32 ? 4.0 : 8.0) * L.bd_entries + (double)L.bd_Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
       if (L.dense_smooth) return (h->f32 ? 4.0 : 8.0) * L.dense_entries + 2.0 * vb * n;
       return (half + n) * mb + 4.0 * n + 2.0 * vb * n;
     case CPC_K_ILU_L: return half * mb + 4.0 * n + 2.0 * vb * n;
@@ -1457,7 +1705,7 @@ static cpc_status read_options(const cpc_options* opt, cpc_options& o) {
   if (!(o.theta >= 0.0 && o.theta <= 1.0)) return set_err(CPC_E_ARG, "theta must lie in [0, 1]");
   if (o.sweep_threads != 0 && o.sweep_threads != 64 && o.sweep_threads != 256)
     return set_err(CPC_E_ARG, "sweep_threads must be 0, 64 or 256");
-  if (o.dense_smoother < 0 || o.dense_smoother > 2) return set_err(CPC_E_ARG, "dense_smoother must be 0, 1 or 2");
+  if (o.dense_smoother < 0 || o.dense_smoother > 3) return set_err(CPC_E_ARG, "dense_smoother must be 0, 1, 2 or 3");
   return CPC_OK;
 }
 
@@ -1653,7 +1901,8 @@ cpc_status cpc_smoother_kind(cpc_handle h, int32_t level, int32_t* kind, int32_t
   const Level& L = h->lev[level];
   if (block_rows) *block_rows = L.sweep_R;
   if (L.nS <= 0 || level + 1 == (int32_t)h->lev.size()) *kind = -1;
-  else *kind = L.dense_smooth ? 1 : 0;
+  else *kind = L.dense_smooth ? 1 : (L.bdense ? 2 : 0);
+  if (block_rows && L.bdense) *block_rows = L.bd_B;
   return CPC_OK;
 }
 
@@ -1760,6 +2009,12 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         break;
       // triangular solves: the sentinel fill before each launch is not timed
       case CPC_K_FGS:
+        if (L.bdense) {
+          ev_begin();
+          bdense_solve(h, L, false, f, u, L.r, nullptr);
+          ev_end();
+          break;
+        }
         if (L.dense_smooth) {
           ev_begin();
           launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, nullptr);
@@ -1773,6 +2028,12 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         ev_end();
         break;
       case CPC_K_BGS:
+        if (L.bdense) {
+          ev_begin();
+          bdense_solve(h, L, true, f, u, L.r, nullptr);
+          ev_end();
+          break;
+        }
         if (L.dense_smooth) {
           ev_begin();
           launch_dense_lower_t(h->stream, L.dtri, f32, f32, f, u, nullptr);

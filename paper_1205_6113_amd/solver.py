@@ -157,7 +157,7 @@ class Solver:
             kind = ctypes.c_int32(0)
             br = ctypes.c_int32(0)
             check(self._lib.cpc_smoother_kind(self._h, d, ctypes.byref(kind), ctypes.byref(br)))
-            kinds.append({-1: "none", 0: "sweep", 1: "dense"}[kind.value])
+            kinds.append({-1: "none", 0: "sweep", 1: "dense", 2: "block"}[kind.value])
             rows.append(br.value)
         return {"nlev": k, "n": n_l[:k].tolist(), "nnz": nnz_l[:k].tolist(), "depth": depth[:k].tolist(),
                 "smoother": kinds, "block_rows": rows}

@@ -47,6 +47,7 @@ def small_cases():
         "c5s": (gen.scaled_config(5, 0.2), 0, "auto"),
         "c2m": (gen.scaled_config(2, 0.3), 0, "auto"),
         "c5m": (gen.scaled_config(5, 0.35), 0, "always"),
+        "c2m-block": (gen.scaled_config(2, 0.3), 0, "block"),
     }
 
 
@@ -256,5 +257,9 @@ def test_smoother_kinds_follow_the_option(cases):
                 assert kinds[d] == "sweep", (k, d)
             elif dense == "always":
                 assert kinds[d] == ("dense" if info["n"][d] <= 65536 else "sweep"), (k, d)
+            elif dense == "block":
+                assert kinds[d] == ("block" if info["n"][d] > 4096 else "sweep"), (k, d)
+                if kinds[d] == "block":
+                    assert info["block_rows"][d] == 2048, (k, d)
             else:
-                assert kinds[d] in ("sweep", "dense"), (k, d)
+                assert kinds[d] in ("sweep", "dense", "block"), (k, d)
