@@ -22,10 +22,12 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
-# kernel reported in the roofline object (the family that dominates the solve time in
+# kernel reported in the roofline object (the kernel that dominates the solve time in
 # the committed kernel-trace summary) and the committed traffic counters for it
-ROOFLINE_KERNEL = "bgs"
-TRAFFIC_FILE = ROOT / "profiles" / "traffic_bgs_sweep_c2.json"
+ROOFLINE_KERNEL = "dense_gemv"
+ROOFLINE_NAME = "gemv_tri_rows_kernel"
+TRAFFIC_FILE = ROOT / "profiles" / "traffic_gemv_tri_rows_c2.txt"
+KERNEL_SOURCE = ROOT / "paper_1205_6113_amd" / "csrc" / "dense_tri.hip"
 
 
 def log(msg):
@@ -106,17 +108,23 @@ def main():
     # roofline of the dominant kernel family (HIP events on the solver's stream)
     tk = solver.time_kernel(ROOFLINE_KERNEL, level=-1, reps=args.roofline_reps)
     achieved = tk["bytes"] / (tk["avg_ms"] / 1000.0) / 1e9
+    # counted HBM bytes per launch from the committed rocprofv3 counter passes, only if
+    # they were taken on this workload, precision and kernel source
     traffic = None
     if TRAFFIC_FILE.exists():
         try:
+            import hashlib
             tr = json.loads(TRAFFIC_FILE.read_text())
-            if tr.get("workload") == args.workload and tr.get("precision") == args.precision:
+            src = hashlib.sha256(KERNEL_SOURCE.read_bytes()).hexdigest()
+            if (tr.get("workload") == args.workload and tr.get("precision") == args.precision
+                    and tr.get("kernel_source_sha256") == src):
                 traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "tri_sweep_kernel (backward (D+U) solve of the Gauss-Seidel smoother, every smoothed level)",
+                "kernel": f"{ROOFLINE_NAME} (products with the explicit inverses of D+L or of its diagonal "
+                          "blocks, both directions, every level smoothed that way)",
                 "avg_launch_us": round(1000.0 * tk["avg_ms"], 3), "bytes_per_launch": tk["bytes"],
                 "launches_timed": tk["launches"]}
     log(f"roofline {ROOFLINE_KERNEL}: {1000 * tk['avg_ms']:.2f} us/launch, {tk['bytes'] / 1e6:.2f} MB/launch "

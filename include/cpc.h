@@ -86,7 +86,7 @@ typedef struct {
   int32_t sweep_block_rows; /* rows per workgroup block of the triangular sweeps (0 = auto)  */
   int32_t sweep_threads;  /* threads per sweep workgroup: 64 (one wave) or 256; 0 = auto     */
   int32_t dense_smoother; /* Gauss-Seidel through explicit inverses of D+L (whole level,
-                             <= 65536 rows) or of its diagonal blocks (block substitution):
+                             <= 16384 rows) or of its diagonal blocks (block substitution):
                              0 = where measured faster at setup, 1 = never, 2 = whole-level
                              inverses wherever they fit, 3 = blocks of 2048 rows on every
                              smoothed level of more than 4096 rows                          */
@@ -217,13 +217,17 @@ typedef enum {
   CPC_K_PROLONG = 7,   /* u += P e                                                          */
   CPC_K_VCYCLE = 8,    /* one whole V-cycle                                                 */
   CPC_K_PRECOND = 9,   /* one application of the handle's preconditioner                    */
-  CPC_K_ITERATION = 10 /* one whole PCG iteration                                           */
+  CPC_K_ITERATION = 10, /* one whole PCG iteration                                          */
+  CPC_K_DENSE_GEMV = 11 /* products with explicit inverses of D+L or of its diagonal blocks
+                           (both directions), one launch per block and direction            */
 } cpc_kernel;
 
 /* Measurement helper (not needed to solve): runs `reps` repetitions of the kernel
  * family `kernel` (cpc_kernel) on the handle's current work vectors and reports the
  * mean duration of one launch (HIP events recorded on the handle's stream around all
- * repetitions, ms), the algorithmic HBM bytes of one launch (the byte model: matrix
+ * repetitions, around each launch for the triangular solves, or around a captured
+ * graph of all of them replayed reps times for the dense products,
+ * ms), the algorithmic HBM bytes of one launch (the byte model: matrix
  * streams read once, vectors read or written once per launch) and the number of
  * launches timed. level >= 0 selects one level; level = -1 takes every level the
  * family runs on in one V-cycle, one launch per level per repetition (the averages

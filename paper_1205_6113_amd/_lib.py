@@ -26,7 +26,7 @@ EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "c
            "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values", "cpc_setup_batch",
            "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind")
 KERNEL = {"spmv_pq": 0, "fgs": 1, "bgs": 2, "ilu_l": 3, "ilu_u": 4, "residual": 5, "restrict": 6, "prolong": 7,
-          "vcycle": 8, "precond": 9, "iteration": 10}
+          "vcycle": 8, "precond": 9, "iteration": 10, "dense_gemv": 11}
 
 
 class Options(ctypes.Structure):

@@ -557,8 +557,8 @@ static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::
 }
 
 // Explicit inverses of T = D + L for the smoothed systems of a level (all of them or
-// none): at most 65536 rows each and 64 GB for the level.
-static constexpr int kDenseMaxRows = 65536;
+// none): at most 16384 rows each (larger levels take the block form) and 64 GB.
+static constexpr int kDenseMaxRows = 16384;
 static constexpr double kDenseMaxBytes = 64e9;
 static constexpr int kDenseTransRows = 16384;
 
@@ -1967,7 +1967,7 @@ cpc_status cpc_neg_outer_on_pattern(cpc_handle h, const double* lam_dev, const d
 cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t reps, double* avg_ms,
                            double* bytes_per_launch, int32_t* launches) {
   if (!h) return set_err(CPC_E_ARG, "null handle");
-  if (reps < 1 || kernel < CPC_K_SPMV_PQ || kernel > CPC_K_ITERATION) return set_err(CPC_E_ARG, "bad kernel or reps");
+  if (reps < 1 || kernel < CPC_K_SPMV_PQ || kernel > CPC_K_DENSE_GEMV) return set_err(CPC_E_ARG, "bad kernel or reps");
   const int nlev = (int)h->lev.size();
   const bool per_level = kernel >= CPC_K_FGS && kernel <= CPC_K_PROLONG && kernel != CPC_K_ILU_L &&
                          kernel != CPC_K_ILU_U;
@@ -1982,6 +1982,10 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
       for (int d = 0; d + 1 < nlev; ++d) levels.push_back(d);
     }
     if (levels.empty()) return set_err(CPC_E_ARG, "hierarchy has one level");
+  } else if (kernel == CPC_K_DENSE_GEMV) {
+    for (int d = 0; d + 1 < nlev; ++d)
+      if ((h->lev[d].bdense || h->lev[d].dense_smooth) && (level < 0 || level == d)) levels.push_back(d);
+    if (levels.empty()) return set_err(CPC_E_ARG, "no level is smoothed through explicit inverses");
   } else {
     levels.push_back(0);
   }
@@ -2080,6 +2084,57 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         break;
     }
   };
+  if (kernel == CPC_K_DENSE_GEMV) {
+    // the dense products of every selected level, both directions, captured once as a
+    // graph and replayed reps times between one pair of events (launch gaps kept
+    // small, no per-launch event overhead); one launch per block and direction
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    try {
+      int count = 0;
+      double bytes = 0.0;
+      const double eb = f32 ? 4.0 : 8.0, vb = f32 ? 4.0 : 8.0;
+      HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      for (int d : levels) {
+        Level& L = h->lev[d];
+        void* f = d == 0 ? h->pin : L.f;
+        void* u = d == 0 ? h->u1 : L.u;
+        auto both = [&](const DenseTriDev& dt, double entries, double rows) {
+          launch_dense_lower(h->stream, dt, f32, f32, f, u, nullptr);
+          launch_dense_lower_t(h->stream, dt, f32, f32, f, u, nullptr);
+          count += 2;
+          bytes += 2.0 * (eb * entries + 2.0 * vb * rows);
+        };
+        if (L.bdense) {
+          const int K = (int)L.bd_start.size() - 1;
+          for (int b = 0; b < K; ++b) {
+            DenseTriDev dt = L.bd_dt;
+            dt.item_n += L.bd_item_off[b];
+            dt.nitem_n = L.bd_item_off[b + 1] - L.bd_item_off[b];
+            const double nb = L.bd_start[b + 1] - L.bd_start[b];
+            both(dt, 0.5 * nb * (nb + 1), nb);
+          }
+        } else {
+          both(L.dtri, L.dense_entries, (double)L.nS);
+        }
+      }
+      HIPCHK(hipStreamEndCapture(h->stream, &g));
+      HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      const float ms = time_ms(h, reps, [&] { HIPCHK(hipGraphLaunch(ge, h->stream)); });
+      (void)hipGraphExecDestroy(ge);
+      (void)hipGraphDestroy(g);
+      if (avg_ms) *avg_ms = ms / count;
+      if (bytes_per_launch) *bytes_per_launch = bytes / count;
+      if (launches) *launches = reps * count;
+      HIPCHK(hipGetLastError());
+    } catch (const HipError& e) {
+      if (ge) (void)hipGraphExecDestroy(ge);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamEndCapture(h->stream, &g);
+      return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+    }
+    return CPC_OK;
+  }
   try {
     if (kernel == CPC_K_SPMV_PQ || kernel == CPC_K_ITERATION) {
       // a running state with positive scalars so that nothing returns early
@@ -2115,8 +2170,9 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
       else b += iteration_bytes(h, h->opt.prec);
     }
     const int nl = reps * (int)levels.size();
+    const double bpl = b / levels.size();
     if (avg_ms) *avg_ms = ms / nl;
-    if (bytes_per_launch) *bytes_per_launch = b / levels.size();
+    if (bytes_per_launch) *bytes_per_launch = bpl;
     if (launches) *launches = nl;
     unsigned herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, h->sync.err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));

@@ -246,7 +246,7 @@ def test_neg_outer_on_pattern(cases):
 
 
 def test_smoother_kinds_follow_the_option(cases):
-    """Levels of at most 65536 rows are smoothed through explicit inverses exactly when
+    """Levels of at most 16384 rows are smoothed through explicit inverses exactly when
     asked ("always"); never when told not to; the coarsest level is not smoothed."""
     for k, (p, R, dense) in small_cases().items():
         info = cases[k][2].hierarchy()
@@ -256,7 +256,7 @@ def test_smoother_kinds_follow_the_option(cases):
             if dense == "never":
                 assert kinds[d] == "sweep", (k, d)
             elif dense == "always":
-                assert kinds[d] == ("dense" if info["n"][d] <= 65536 else "sweep"), (k, d)
+                assert kinds[d] == ("dense" if info["n"][d] <= 16384 else "sweep"), (k, d)
             elif dense == "block":
                 assert kinds[d] == ("block" if info["n"][d] > 4096 else "sweep"), (k, d)
                 if kinds[d] == "block":
