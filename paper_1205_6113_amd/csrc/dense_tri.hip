@@ -16,8 +16,8 @@
 // B <- -C^{-1} B A^{-1} from two matrix products (library GEMMs), where A^{-1}, C^{-1}
 // are the inverted diagonal spans. The result is T^{-1}, lower triangular.
 //
-// Products: y = T^{-1} f by one workgroup per row (coalesced row reads, the vector
-// from L2). y = T^{-T} g: on smaller systems from a stored transpose, row by row like the
+// Products: y = T^{-1} f by one workgroup per four rows (coalesced row reads, the
+// vector from L2). y = T^{-T} g: on smaller systems from a stored transpose, row by row like the
 // forward product; on larger ones by items (column block of 512, chunk of 1024 rows)
 // whose partial column sums go to a buffer and are added in chunk order
 // (deterministic), which reads each stored entry once without a second copy.
@@ -113,13 +113,14 @@ __global__ __launch_bounds__(kNT) void to_type_kernel(long n, const double* __re
 }
 
 // y = M f with M lower (y = T^{-1} f) or upper (y = T^{-T} g from the stored
-// transpose) triangular. Items (system, first row, end row); the whole workgroup
-// reads one row at a time (four independent partial sums per thread, so each thread
-// keeps four loads in flight), then adds the 256 partials in a fixed order.
+// transpose) triangular. Items (system, first row, end row) of at most four rows: the
+// workgroup walks the columns of the four rows together, so each vector entry is
+// loaded once for four rows and each thread keeps up to ten loads in flight (two
+// columns a step), then adds the 256 partials of each row in a fixed order.
 template <bool UPPER, typename MT, typename XT>
 __global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
                                                             XT* __restrict__ y, const int* __restrict__ done) {
-  __shared__ double red[kNT / 64];
+  __shared__ double red[kNT / 64][4];
   if (done && *done) return;
   const int4 it = dt.item_n[blockIdx.x];
   const int s = it.x;
@@ -128,24 +129,43 @@ __global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, cons
   const MT* __restrict__ M = reinterpret_cast<const MT*>(UPPER ? dt.MT : dt.M) + dt.moff[s];
   const XT* __restrict__ fs = f + voff;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int i = it.y; i < it.z; ++i) {
-    const MT* __restrict__ row = M + (long)i * n;
-    const int jb = UPPER ? i : 0, je = UPPER ? n : i + 1;  // stored entries [jb, je)
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int j = jb + tid;
-    for (; j + 3 * kNT < je; j += 4 * kNT) {
-      a0 += (double)row[j] * (double)fs[j];
-      a1 += (double)row[j + kNT] * (double)fs[j + kNT];
-      a2 += (double)row[j + 2 * kNT] * (double)fs[j + 2 * kNT];
-      a3 += (double)row[j + 3 * kNT] * (double)fs[j + 3 * kNT];
-    }
-    for (; j < je; j += kNT) a0 += (double)row[j] * (double)fs[j];
-    const double v = wsum<64>((a0 + a1) + (a2 + a3));
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    if (tid == 0) y[voff + i] = (XT)((red[0] + red[1]) + (red[2] + red[3]));
-    __syncthreads();
+  const int r0 = it.y, nr = it.z - it.y;  // 1 <= nr <= 4
+  // union of the rows' stored entries: lower rows i use [0, i], upper rows [i, n)
+  const int jb = UPPER ? r0 : 0, je = UPPER ? n : it.z;
+  const MT* __restrict__ row0 = M + (long)r0 * n;
+  const long rs1 = nr > 1 ? n : 0, rs2 = nr > 2 ? 2L * n : 0, rs3 = nr > 3 ? 3L * n : 0;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  auto add = [&](int j) {
+    const double fv = (double)fs[j];
+    // row r + r0 holds column j when j <= r0 + r (lower) or j >= r0 + r (upper)
+    const bool ok0 = UPPER ? j >= r0 : j <= r0;
+    const bool ok1 = nr > 1 && (UPPER ? j >= r0 + 1 : j <= r0 + 1);
+    const bool ok2 = nr > 2 && (UPPER ? j >= r0 + 2 : j <= r0 + 2);
+    const bool ok3 = nr > 3 && (UPPER ? j >= r0 + 3 : j <= r0 + 3);
+    const double m0 = ok0 ? (double)row0[j] : 0.0;
+    const double m1 = ok1 ? (double)row0[rs1 + j] : 0.0;
+    const double m2 = ok2 ? (double)row0[rs2 + j] : 0.0;
+    const double m3 = ok3 ? (double)row0[rs3 + j] : 0.0;
+    a0 += m0 * fv;
+    a1 += m1 * fv;
+    a2 += m2 * fv;
+    a3 += m3 * fv;
+  };
+  int j = jb + tid;
+  for (; j + kNT < je; j += 2 * kNT) {
+    add(j);
+    add(j + kNT);
   }
+  if (j < je) add(j);
+  const double v0 = wsum<64>(a0), v1 = wsum<64>(a1), v2 = wsum<64>(a2), v3 = wsum<64>(a3);
+  if (lane == 0) {
+    red[w][0] = v0;
+    red[w][1] = v1;
+    red[w][2] = v2;
+    red[w][3] = v3;
+  }
+  __syncthreads();
+  if (tid < nr) y[voff + r0 + tid] = (XT)((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
 }
 
 // Partial column sums of T^{-T} g: item (system, first column c0, first row r0, slot);
