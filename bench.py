@@ -59,6 +59,145 @@ def cpu_baseline(p, iters_gpu):
     return h, r, setup_s, solve_s, np
 
 
+def bench_batch(args):
+    """Batch of 64 independent TPFA systems (edges 32..96) in one batched solve, against
+    the same 64 systems solved one after the other with single-system handles."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1205_6113_amd as cpc
+    probs = gen.config4()
+    n_tot = sum(p.n for p in probs)
+    log(f"workload c4: {len(probs)} systems, {n_tot} unknowns in all")
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    bs = cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs], device=dev, verbose=True)
+    setup_s = time.perf_counter() - t0
+    log(f"batch setup {setup_s:.1f}s")
+    b = torch.as_tensor(np.concatenate([p.b for p in probs]), device=dev)
+    tol = probs[0].tol
+    for w in range(args.warmup):
+        x, its, rels, st = bs.solve(b, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        x, its, rels, st = bs.solve(b, tol=tol)
+    torch.cuda.synchronize()
+    ms_batch = 1000.0 * (time.perf_counter() - t0) / args.steps
+    stats = bs.stats()
+    log(f"batch: {ms_batch:.1f} ms per batch solve, iterations {int(its.min())}..{int(its.max())}")
+    # the same systems one by one (setups untimed): every 4th system, times 4
+    seq_ms, errs = 0.0, []
+    offs = bs.offsets
+    sample = list(range(0, len(probs), 4))
+    for k in sample:
+        p = probs[k]
+        log(f"single system {k}: n={p.n}")
+        s1 = cpc.Solver(p.n, p.row_ptr, p.col, p.val, device=dev)
+        b1 = torch.as_tensor(p.b, device=dev)
+        x1, it1, rel1, st1 = s1.solve(b1, tol=tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x1, it1, rel1, st1 = s1.solve(b1, tol=tol)
+        torch.cuda.synchronize()
+        seq_ms += 1000.0 * (time.perf_counter() - t0)
+        xb = x[offs[k]:offs[k] + p.n]
+        errs.append(float(torch.linalg.norm(xb - x1) / torch.linalg.norm(x1)))
+        s1.close()
+    seq_ms *= len(probs) / len(sample)
+    log(f"sequential: {seq_ms:.1f} ms for the {len(probs)} single-system solves (from {len(sample)} of them)")
+    # the batched preconditioner runs over every system until the last one stops
+    bytes_batch = stats["bytes_per_iter"] * int(its.max()) + stats["bytes_initial"]
+    out = {
+        "metric": "combined-PCG solve s + HBM GB/s to 1e-8 rel res; FP32-precond vs FP64",
+        "value": round(bytes_batch / (ms_batch / 1000.0) / 1e9, 3) if bytes_batch else None,
+        "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_batch, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"batch of {len(probs)} 3-d TPFA systems, edges 32..96 ({n_tot} unknowns), "
+                               "B_co PCG to 1e-8",
+                   "systems": len(probs), "unknowns": n_tot, "setup_s": round(setup_s, 3),
+                   "solves_per_s": round(len(probs) / (ms_batch / 1000.0), 2),
+                   "iters_min": int(its.min()), "iters_max": int(its.max()), "iters_mean": float(its.mean()),
+                   "relres_max": float(rels.max()), "sequential_ms": round(seq_ms, 3),
+                   "sequential_sample": f"every 4th system ({len(sample)}), scaled by {len(probs) / len(sample):g}",
+                   "speedup_vs_sequential": round(seq_ms / ms_batch, 3),
+                   "x_relerr_batch_vs_single_max": max(errs)},
+    }
+    print(json.dumps(out), flush=True)
+    bs.close()
+
+
+def bench_adjoint(args):
+    """Differentiable solve on C5: forward (assembly, setup, PCG) and backward (adjoint
+    PCG, gradient assembly) times; gradient against the oracle and central differences."""
+    import numpy as np
+    import torch
+    import gen
+    from paper_1205_6113_amd import adjoint as adj
+    p = gen.config5()
+    nx, ny, nz = p.dims
+    dev = torch.device("cuda:0")
+    grid = adj.TpfaGrid(nx, ny, nz, p.kz_ratio, p.dirichlet_x)
+    obs = torch.as_tensor(p.meta["obs"], device=dev)
+    d = torch.as_tensor(p.meta["d"], device=dev)
+    tol = 1e-10
+    times = []
+    for k in range(args.warmup + args.steps):
+        logk = torch.as_tensor(p.logk.ravel(), device=dev).requires_grad_(True)
+        b = torch.as_tensor(p.b, device=dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x = adj.tpfa_solve(logk, b, grid, tol=tol, tune=False)  # rule-based setup (no timing)
+        L = 0.5 * ((x[obs] - d) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if k >= args.warmup:
+            times.append((t1 - t0, t2 - t1))
+    fwd = float(np.mean([t[0] for t in times]))
+    bwd = float(np.mean([t[1] for t in times]))
+    g_logk = logk.grad.cpu().numpy()
+    g_b = b.grad.cpu().numpy()
+    log(f"forward {fwd:.3f}s backward {bwd:.3f}s")
+    res = {"forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "loss": float(L.item())}
+    # central differences with the preconditioner frozen at log k, 20 cells
+    fz = adj.FrozenPreconditionerSolve(logk.detach(), grid)
+    h = 1e-6
+    fd_err = []
+    for c in p.meta["fd_cells"]:
+        vals = []
+        for sgn in (1.0, -1.0):
+            lk = logk.detach().clone()
+            lk[int(c)] += sgn * h
+            xs, it, rel, st = fz.solve(lk, b.detach(), tol=1e-13)
+            vals.append(0.5 * float(((xs[obs] - d) ** 2).sum()))
+        g_fd = (vals[0] - vals[1]) / (2 * h)
+        fd_err.append(abs(g_fd - g_logk[c]) / max(abs(g_logk[c]), 1e-3 * np.abs(g_logk).max()))
+    fz.close()
+    res["fd_cells"] = len(fd_err)
+    res["fd_relerr_max"] = float(max(fd_err))
+    if not args.no_cpu_baseline:
+        import oracle
+        hh = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
+        ref = oracle.misfit_gradient(p, hh, tol=tol)
+        res["grad_logk_relerr_vs_oracle"] = float(np.linalg.norm(g_logk - ref["grad_logk"]) /
+                                                  np.linalg.norm(ref["grad_logk"]))
+        res["grad_b_relerr_vs_oracle"] = float(np.linalg.norm(g_b - ref["grad_b"]) / np.linalg.norm(ref["grad_b"]))
+    log(f"gradient check: {res}")
+    out = {
+        "metric": "combined-PCG solve s + HBM GB/s to 1e-8 rel res; FP32-precond vs FP64",
+        "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * (fwd + bwd), 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "differentiable 3-d 96x96x48 TPFA solve (442,368 unknowns), forward + adjoint, "
+                               "PCG to 1e-10", **res},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +207,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-reps", type=int, default=5)
+    ap.add_argument("--compare-precision", action="store_true",
+                    help="also solve in the other precision and report speedup and solution difference")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is "
@@ -78,6 +219,10 @@ def main():
     import torch
     import paper_1205_6113_amd as cpc
 
+    if args.workload == "c4":
+        return bench_batch(args)
+    if args.workload == "c5":
+        return bench_adjoint(args)
     p, desc = workload(args.workload)
     log(f"workload {desc}: n={p.n} nnz={p.nnz}")
     torch.cuda.init()
@@ -130,6 +275,27 @@ def main():
     log(f"roofline {ROOFLINE_KERNEL}: {1000 * tk['avg_ms']:.2f} us/launch, {tk['bytes'] / 1e6:.2f} MB/launch "
         f"-> {achieved:.1f} GB/s")
 
+    compare = None
+    if args.compare_precision:
+        other = "fp64" if args.precision == "fp32" else "fp32"
+        s2 = cpc.Solver(p.n, p.row_ptr, p.col, p.val, device=dev, precision=other)
+        x2 = torch.zeros_like(b)
+        for w in range(args.warmup):
+            x2, it2, rel2, st2 = s2.solve(b, x=x2, tol=p.tol, maxit=10000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            x2, it2, rel2, st2 = s2.solve(b, x=x2, tol=p.tol, maxit=10000)
+        torch.cuda.synchronize()
+        ms2 = 1000.0 * (time.perf_counter() - t0) / args.steps
+        x64, x32 = (x2, x) if other == "fp64" else (x, x2)
+        diff = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+        compare = {"precision": other, "ms_per_solve": round(ms2, 4), "iters": it2, "relres": rel2,
+                   "speedup_fp32_vs_fp64": round((ms2 / ms_per_step) if other == "fp64" else (ms_per_step / ms2), 4),
+                   "x_relerr_fp32_vs_fp64": diff}
+        log(f"{other}: {ms2:.3f} ms/solve iters={it2}; fp32 vs fp64 solution {diff:.2e}")
+        s2.close()
+
     out = {
         "metric": "combined-PCG solve s + HBM GB/s to 1e-8 rel res; FP32-precond vs FP64",
         "value": round(value, 3),
@@ -149,6 +315,8 @@ def main():
                    "bytes_per_solve": bytes_solve, "precision": args.precision},
         "roofline": roofline,
     }
+    if compare:
+        out["config"]["compare"] = compare
     if not args.no_cpu_baseline:
         h, r, osetup, osolve, _ = cpu_baseline(p, it)
         ob = stats["bytes_per_iter"] * r["iters"] + stats["bytes_initial"]

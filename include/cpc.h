@@ -90,6 +90,9 @@ typedef struct {
                              0 = where measured faster at setup, 1 = never, 2 = whole-level
                              inverses wherever they fit, 3 = blocks of 2048 rows on every
                              smoothed level of more than 4096 rows                          */
+  int32_t tune;           /* 1: pick each level's smoother form and sweep block size by timing
+                             candidates at setup (default); 0: fixed rules (faster setup)   */
+  int32_t verbose;        /* 1: one progress line per setup phase on stderr                 */
   double theta;           /* strength threshold of the classical coarsening (0.25)          */
 } cpc_options;
 

@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
                 ("check_symmetry", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("rap_on_gpu", ctypes.c_int32), ("sweep_block_rows", ctypes.c_int32),
                 ("sweep_threads", ctypes.c_int32), ("dense_smoother", ctypes.c_int32),
-                ("theta", ctypes.c_double)]
+                ("tune", ctypes.c_int32), ("verbose", ctypes.c_int32), ("theta", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

@@ -323,6 +323,13 @@ static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncol
   return ok;
 }
 
+static void progress(const cpc_solver* h, const std::string& what) {
+  if (h->opt.verbose) {
+    std::fprintf(stderr, "[cpc setup] %s\n", what.c_str());
+    std::fflush(stderr);
+  }
+}
+
 static size_t esz_of(const cpc_solver* h) { return h->f32 ? sizeof(float) : sizeof(double); }
 
 static void* valloc(cpc_solver* h, int n) {
@@ -690,8 +697,8 @@ static void tune_dense(cpc_solver* h) {
   for (size_t d = 0; d < h->lev.size(); ++d) {
     Level& L = h->lev[d];
     if (!L.dense_M) continue;
-    bool keep = h->opt.dense_smoother == 2;
-    if (!keep) {
+    bool keep = h->opt.dense_smoother == 2 || (!h->opt.tune && L.A.n <= 8192);
+    if (!keep && h->opt.tune) {
       void* f = d == 0 ? h->pin : L.f;
       void* u = d == 0 ? h->u1 : L.u;
       const float ts = time_ms(h, 3, [&] {
@@ -905,6 +912,20 @@ static void bdense_solve(cpc_solver* h, Level& L, bool upper, const void* f, voi
 static void tune_sweeps(cpc_solver* h) {
   if (h->opt.sweep_block_rows > 0 && h->opt.dense_smoother != 3) return;
   const bool f32 = h->f32;
+  if (!h->opt.tune && h->opt.dense_smoother != 3) {
+    // fixed rules (measured on the 1M-unknown pressure systems): the block-dense form
+    // with 4096-row blocks between 8192 and 300000 smoothed rows
+    for (size_t d = 0; d + 1 < h->lev.size(); ++d) {
+      Level& L = h->lev[d];
+      if (h->opt.dense_smoother == 1 || h->opt.dense_smoother == 2 || L.dense_smooth || L.sweep_rows <= 8192 ||
+          L.sweep_rows > 300000)
+        continue;
+      const HostCsr sub = L.sweep_rows == L.A_host.n ? L.A_host : leading_rows(L.A_host, L.sweep_rows);
+      if (build_blockdense(h, L, sub, 4096)) L.bdense = true;
+      progress(h, "level " + std::to_string(d) + ": block-dense smoother, 4096-row blocks");
+    }
+    return;
+  }
   for (size_t d = 0; d < h->lev.size(); ++d) {
     Level& L = h->lev[d];
     if (L.sweep_rows <= 4096) continue;
@@ -924,9 +945,10 @@ static void tune_sweeps(cpc_solver* h) {
         }
       });
     };
-    float best = (L.dense_smooth && !ilu) ? 0.f : cost();
+    const bool try_r = L.sweep_rows <= 2000000 && !(L.dense_smooth && !ilu);
+    float best = try_r ? cost() : 0.f;
     for (int R : {1024, 2048, 4096, 8192}) {
-      if (R == L.sweep_R || R >= L.sweep_rows || (L.dense_smooth && !ilu)) continue;
+      if (!try_r || R == L.sweep_R || R >= L.sweep_rows) continue;
       // keep the current build aside, try the candidate in a list of its own
       DevSweepSched lo = L.lower, up = L.upper;
       SweepPackDev fg = L.fgs, bg = L.bgs, il = h->ilu_l, iu = h->ilu_u;
@@ -1020,6 +1042,10 @@ static void tune_sweeps(cpc_solver* h) {
           L.bd_entries = keep.bd_entries;
         }
       }
+      progress(h, "level " + std::to_string(d) + ": " +
+                      (L.bdense ? "block-dense, " + std::to_string(L.bd_B) + "-row blocks"
+                                : (L.dense_smooth ? std::string("explicit inverse") : "sweeps, " +
+                                   std::to_string(L.sweep_R) + "-row blocks")));
       if (L.bdense && was_dense) {  // the block form replaces the whole-level inverse
         HIPCHK(hipStreamSynchronize(h->stream));
         for (void* p : L.dense_owned) (void)hipFree(p);
@@ -1688,6 +1714,8 @@ void cpc_default_options(cpc_options* o) {
   o->sweep_block_rows = 0;
   o->sweep_threads = 0;
   o->dense_smoother = 0;
+  o->tune = 1;
+  o->verbose = 0;
   o->theta = 0.25;
 }
 
@@ -1744,12 +1772,15 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
       HIPCHK(hipStreamCreate(&h->stream));
       h->own_stream = true;
     }
+    progress(h.get(), "ILU(0) factored; building the hierarchy");
     st = build_sys_hier(h.get(), sys[0], o, &msg);
     if (st != CPC_OK) return set_err((cpc_status)st, msg);
+    progress(h.get(), "hierarchy of " + std::to_string(sys[0].A.size()) + " levels; assembling");
     st = assemble_levels(h.get(), sys, o, &msg);
     if (st != CPC_OK) return set_err((cpc_status)st, msg);
     sys.clear();
     allocate_work(h.get());
+    progress(h.get(), "levels assembled; choosing smoother forms");
     tune_dense(h.get());
     tune_sweeps(h.get());
     HIPCHK(hipGetLastError());
@@ -1795,6 +1826,7 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
       A0.ci.assign(col_idx[s], col_idx[s] + row_ptr[s][n[s]]);
       A0.v.assign(val[s], val[s] + row_ptr[s][n[s]]);
       sys[s].A.push_back(std::move(A0));
+      if (s % 8 == 0) progress(h.get(), "ILU(0) of system " + std::to_string(s));
       int st = ilu0_factor(sys[s].A[0], sys[s].lu, &msg);
       if (st != CPC_OK) return set_err((cpc_status)st, "system " + std::to_string(s) + ": " + msg);
       h->sys_n.push_back(n[s]);
@@ -1808,9 +1840,12 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
       h->own_stream = true;
     }
     for (int s = 0; s < nsys; ++s) {
+      progress(h.get(), "system " + std::to_string(s) + " of " + std::to_string(nsys) + ": hierarchy (" +
+                            std::to_string(sys[s].A[0].n) + " rows)");
       int st = build_sys_hier(h.get(), sys[s], o, &msg);
       if (st != CPC_OK) return set_err((cpc_status)st, "system " + std::to_string(s) + ": " + msg);
     }
+    progress(h.get(), "assembling the batch levels");
     int st = assemble_levels(h.get(), sys, o, &msg);
     if (st != CPC_OK) return set_err((cpc_status)st, msg);
     h->nnz = h->lev[0].A.nnz;

@@ -35,7 +35,7 @@ def _dev_vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
 
 def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, theta=0.25, swap_roles=False,
             check_symmetry=True, use_graph=True, check_every=4, sweep_block_rows=0,
-            sweep_threads=0, dense_smoother=0) -> _lib.Options:
+            sweep_threads=0, dense_smoother=0, tune=True, verbose=False) -> _lib.Options:
     lib = load()
     o = _lib.Options()
     lib.cpc_default_options(ctypes.byref(o))
@@ -50,6 +50,8 @@ def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, th
     o.check_every = int(check_every)
     o.sweep_block_rows = int(sweep_block_rows)
     o.sweep_threads = int(sweep_threads)
+    o.tune = int(bool(tune))
+    o.verbose = int(bool(verbose))
     o.dense_smoother = _lib.DENSE[dense_smoother] if isinstance(dense_smoother, str) else int(dense_smoother)
     return o
 
