@@ -48,11 +48,12 @@ __device__ __forceinline__ double wsum(double v) {
 __global__ __launch_bounds__(kNT) void scatter_lower_kernel(int n, int voff, const int* __restrict__ rp,
                                                            const int* __restrict__ ci,
                                                            const double* __restrict__ v, double* __restrict__ M) {
+  const long ld = dense_ld(n);
   for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
     const int r = voff + i;
     for (int p = rp[r]; p < rp[r + 1]; ++p) {
       const int j = ci[p] - voff;
-      if (j >= 0 && j <= i) M[(long)i * n + j] = v[p];  // the diagonal block only
+      if (j >= 0 && j <= i) M[i * ld + j] = v[p];  // the diagonal block only
     }
   }
 }
@@ -65,9 +66,10 @@ __global__ __launch_bounds__(kLeaf) void leaf_inverse_kernel(int n, double* __re
   __shared__ double trow[kLeaf];
   const int b0 = blockIdx.x * kLeaf;
   const int nb = min(kLeaf, n - b0);
+  const long ld = dense_ld(n);
   const int j = threadIdx.x;
   for (int i = 0; i < nb; ++i) {
-    if (j < nb) trow[j] = M[(long)(b0 + i) * n + b0 + j];
+    if (j < nb) trow[j] = M[(b0 + i) * ld + b0 + j];
     __syncthreads();
     const double dinv = 1.0 / trow[i];
     double x = 0.0;
@@ -87,23 +89,24 @@ __global__ __launch_bounds__(kLeaf) void leaf_inverse_kernel(int n, double* __re
     __syncthreads();
   }
   for (int i = 0; i < nb; ++i)
-    if (j < nb) M[(long)(b0 + i) * n + b0 + j] = X[i][j];
+    if (j < nb) M[(b0 + i) * ld + b0 + j] = X[i][j];
 }
 
-// Y = X^T for an n x n row-major X, 32 x 32 tiles through LDS.
+// Y = X^T for an n x n row-major X (row stride dense_ld(n)), 32 x 32 tiles through LDS.
 template <typename MT>
 __global__ __launch_bounds__(kNT) void transpose_kernel(int n, const MT* __restrict__ X, MT* __restrict__ Y) {
   __shared__ MT tile[32][33];
+  const long ld = dense_ld(n);
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
   for (int r = ty; r < 32; r += 8) {
     const int i = by + r, j = bx + tx;
-    if (i < n && j < n) tile[r][tx] = X[(long)i * n + j];
+    if (i < n && j < n) tile[r][tx] = X[i * ld + j];
   }
   __syncthreads();
   for (int r = ty; r < 32; r += 8) {
     const int i = bx + r, j = by + tx;
-    if (i < n && j < n) Y[(long)i * n + j] = tile[tx][r];
+    if (i < n && j < n) Y[i * ld + j] = tile[tx][r];
   }
 }
 
@@ -112,51 +115,99 @@ __global__ __launch_bounds__(kNT) void to_type_kernel(long n, const double* __re
   for (long i = (long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long)gridDim.x * kNT) y[i] = (MT)a[i];
 }
 
+template <typename MT>
+struct Vec16;  // 16-byte vector of MT
+template <>
+struct Vec16<double> {
+  using T = double2;
+  static constexpr int N = 2;
+  __device__ static double at(const T& v, int k) { return k == 0 ? v.x : v.y; }
+};
+template <>
+struct Vec16<float> {
+  using T = float4;
+  static constexpr int N = 4;
+  __device__ static double at(const T& v, int k) {
+    return (double)(k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w)));
+  }
+};
+
 // y = M f with M lower (y = T^{-1} f) or upper (y = T^{-T} g from the stored
 // transpose) triangular. Items (system, first row, end row) of at most four rows: the
-// workgroup walks the columns of the four rows together, so each vector entry is
-// loaded once for four rows and each thread keeps up to ten loads in flight (two
-// columns a step), then adds the 256 partials of each row in a fixed order.
+// workgroup walks the columns of the four rows together, each thread taking 16 bytes
+// of each row per step (rows are 16-byte aligned; entries outside a row's triangle
+// are zero and masked), so each vector entry is loaded once for four rows; the 256
+// partials of each row are then added in a fixed order.
 template <bool UPPER, typename MT, typename XT>
 __global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
                                                             XT* __restrict__ y, const int* __restrict__ done) {
+  using V = Vec16<MT>;
+  constexpr int W = V::N;
   __shared__ double red[kNT / 64][4];
   if (done && *done) return;
   const int4 it = dt.item_n[blockIdx.x];
   const int s = it.x;
   const int n = dt.n[s];
+  const long ld = dense_ld(n);
   const int voff = dt.voff[s];
   const MT* __restrict__ M = reinterpret_cast<const MT*>(UPPER ? dt.MT : dt.M) + dt.moff[s];
   const XT* __restrict__ fs = f + voff;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r0 = it.y, nr = it.z - it.y;  // 1 <= nr <= 4
-  // union of the rows' stored entries: lower rows i use [0, i], upper rows [i, n)
-  const int jb = UPPER ? r0 : 0, je = UPPER ? n : it.z;
-  const MT* __restrict__ row0 = M + (long)r0 * n;
-  const long rs1 = nr > 1 ? n : 0, rs2 = nr > 2 ? 2L * n : 0, rs3 = nr > 3 ? 3L * n : 0;
+  // union of the rows' entries: lower rows i hold [0, i], upper rows [i, n); start at a
+  // multiple of W so that loads stay aligned
+  const int jb = UPPER ? (r0 / W) * W : 0, je = UPPER ? n : it.z;
+  const typename V::T* __restrict__ row0 = reinterpret_cast<const typename V::T*>(M + r0 * ld);
+  const long vs = ld / W;  // row stride in vectors
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  auto add = [&](int j) {
-    const double fv = (double)fs[j];
-    // row r + r0 holds column j when j <= r0 + r (lower) or j >= r0 + r (upper)
-    const bool ok0 = UPPER ? j >= r0 : j <= r0;
-    const bool ok1 = nr > 1 && (UPPER ? j >= r0 + 1 : j <= r0 + 1);
-    const bool ok2 = nr > 2 && (UPPER ? j >= r0 + 2 : j <= r0 + 2);
-    const bool ok3 = nr > 3 && (UPPER ? j >= r0 + 3 : j <= r0 + 3);
-    const double m0 = ok0 ? (double)row0[j] : 0.0;
-    const double m1 = ok1 ? (double)row0[rs1 + j] : 0.0;
-    const double m2 = ok2 ? (double)row0[rs2 + j] : 0.0;
-    const double m3 = ok3 ? (double)row0[rs3 + j] : 0.0;
-    a0 += m0 * fv;
-    a1 += m1 * fv;
-    a2 += m2 * fv;
-    a3 += m3 * fv;
+  const typename V::T zero{};
+  // columns j .. j + W - 1 where every row of the item holds all of them
+  auto add_full = [&](int j) {
+    const long c = j / W;
+    const typename V::T m0 = row0[c];
+    const typename V::T m1 = nr > 1 ? row0[vs + c] : zero;
+    const typename V::T m2 = nr > 2 ? row0[2 * vs + c] : zero;
+    const typename V::T m3 = nr > 3 ? row0[3 * vs + c] : zero;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const double fv = (double)fs[j + k];
+      a0 += V::at(m0, k) * fv;
+      a1 += V::at(m1, k) * fv;
+      a2 += V::at(m2, k) * fv;
+      a3 += V::at(m3, k) * fv;
+    }
   };
-  int j = jb + tid;
-  for (; j + kNT < je; j += 2 * kNT) {
-    add(j);
-    add(j + kNT);
+  // the same with each row's triangle and the end of the range masked
+  auto add_masked = [&](int j) {
+    const long c = j / W;
+    const typename V::T m0 = row0[c];
+    const typename V::T m1 = nr > 1 ? row0[vs + c] : zero;
+    const typename V::T m2 = nr > 2 ? row0[2 * vs + c] : zero;
+    const typename V::T m3 = nr > 3 ? row0[3 * vs + c] : zero;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int jj = j + k;
+      if (jj >= je) break;
+      const double fv = (double)fs[jj];
+      // row r0 + r holds column jj when jj <= r0 + r (lower) or jj >= r0 + r (upper)
+      if (UPPER ? jj >= r0 : jj <= r0) a0 += V::at(m0, k) * fv;
+      if (UPPER ? jj >= r0 + 1 : jj <= r0 + 1) a1 += V::at(m1, k) * fv;
+      if (UPPER ? jj >= r0 + 2 : jj <= r0 + 2) a2 += V::at(m2, k) * fv;
+      if (UPPER ? jj >= r0 + 3 : jj <= r0 + 3) a3 += V::at(m3, k) * fv;
+    }
+  };
+  // unmasked bulk [fa, fe): lower rows all hold [0, r0]; upper rows all hold [r0 + 3, n)
+  const int fa = UPPER ? min(((r0 + 3 + W - 1) / W) * W, (n / W) * W) : 0;
+  const int fe = UPPER ? (n / W) * W : ((r0 + 1) / W) * W;
+  int j = fa + W * tid;
+  for (; j + W * kNT < fe; j += 2 * W * kNT) {
+    add_full(j);
+    add_full(j + W * kNT);
   }
-  if (j < je) add(j);
+  if (j < fe) add_full(j);
+  // masked edges: [jb, fa) and [fe, je), at most a few vectors each
+  for (int jm = jb + W * tid; jm < fa; jm += W * kNT) add_masked(jm);
+  for (int jm = fe + W * tid; jm < je; jm += W * kNT) add_masked(jm);
   const double v0 = wsum<64>(a0), v1 = wsum<64>(a1), v2 = wsum<64>(a2), v3 = wsum<64>(a3);
   if (lane == 0) {
     red[w][0] = v0;
@@ -188,8 +239,8 @@ __global__ __launch_bounds__(kNT) void gemv_lower_t_part_kernel(DenseTriDev dt, 
     int i = rbeg;
     for (; i + 1 < rend; i += 2) {
       const double g0 = (double)gs[i], g1 = (double)gs[i + 1];
-      const MT* r0p = M + (long)i * n + c;
-      const MT* r1p = r0p + n;
+      const MT* r0p = M + (long)i * dense_ld(n) + c;
+      const MT* r1p = r0p + dense_ld(n);
       a0 += (double)r0p[0] * g0;
       b0 += (double)r1p[0] * g1;
       if (two) {
@@ -199,7 +250,7 @@ __global__ __launch_bounds__(kNT) void gemv_lower_t_part_kernel(DenseTriDev dt, 
     }
     if (i < rend) {
       const double g0 = (double)gs[i];
-      const MT* r0p = M + (long)i * n + c;
+      const MT* r0p = M + (long)i * dense_ld(n) + c;
       a0 += (double)r0p[0] * g0;
       if (two) a1 += (double)r0p[1] * g0;
     }
@@ -271,7 +322,8 @@ bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int*
     return false;
   }
   bool ok = rocblas_set_stream(hb, s) == rocblas_status_success;
-  if (ok && hipMemsetAsync(M, 0, sizeof(double) * (size_t)n * n, s) != hipSuccess) ok = false;
+  const long ld = dense_ld(n);
+  if (ok && hipMemsetAsync(M, 0, sizeof(double) * (size_t)n * ld, s) != hipSuccess) ok = false;
   if (ok) {
     scatter_lower_kernel<<<std::min((n + kNT - 1) / kNT, 1024), kNT, 0, s>>>(n, voff, rp, ci, v, M);
     leaf_inverse_kernel<<<(n + kLeaf - 1) / kLeaf, kLeaf, 0, s>>>(n, M);
@@ -285,16 +337,16 @@ bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int*
     for (int a = 0; ok && a + sp < n; a += 2 * sp) {
       const int e = std::min(a + 2 * sp, n);
       const int m1 = sp, m2 = e - a - sp;
-      double* Ai = M + (long)a * n + a;
-      double* B = M + (long)(a + sp) * n + a;
-      double* Ci = M + (long)(a + sp) * n + a + sp;
+      double* Ai = M + a * ld + a;
+      double* B = M + (a + sp) * ld + a;
+      double* Ci = M + (a + sp) * ld + a + sp;
       // W (m2 x m1, row-major, ld m1) = B A^{-1}
-      ok = rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m1, m2, m1, &one, Ai, n, B, n, &zero,
+      ok = rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m1, m2, m1, &one, Ai, (int)ld, B, (int)ld, &zero,
                          work, m1) == rocblas_status_success;
       // B = -C^{-1} W
       if (ok)
-        ok = rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m1, m2, m2, &mone, work, m1, Ci, n,
-                           &zero, B, n) == rocblas_status_success;
+        ok = rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m1, m2, m2, &mone, work, m1, Ci, (int)ld,
+                           &zero, B, (int)ld) == rocblas_status_success;
     }
   }
   if (!ok && msg && msg->empty()) *msg = "dense triangular inverse failed";

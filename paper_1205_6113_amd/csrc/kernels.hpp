@@ -142,7 +142,7 @@ constexpr int kTCols = 512;    // columns of one item of the transposed product
 constexpr int kTChunk = 1024;  // rows of one item of the transposed product
 struct DenseTriDev {
   const int* n;        // [nsys] rows of each system
-  const long* moff;    // [nsys] element offset of each system's n x n row-major inverse
+  const long* moff;    // [nsys] element offset of each system's row-major inverse (row stride dense_ld(n))
   const int* voff;     // [nsys] first row of each system in the level vector
   const void* M;       // the inverses (lower triangular; FP64 or FP32)
   const void* MT;      // their transposes (upper triangular), or null: transposed product by items
@@ -154,8 +154,11 @@ struct DenseTriDev {
   const int4* red;
   double* part;        // [slots][kTCols]
 };
+// Row stride of a stored n x n inverse: n rounded up to a multiple of 4 elements, so
+// that every row starts 16-byte aligned (the padding columns hold zeros).
+__host__ __device__ inline int dense_ld(int n) { return (n + 3) & ~3; }
 // T^{-1} of rows [voff, voff + n) of the level CSR (columns offset by voff) into the
-// dense n x n array M (FP64), using work (>= the largest off-diagonal product).
+// dense n x dense_ld(n) array M (FP64), using work (>= the largest off-diagonal product).
 bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int* ci, const double* v, double* M,
                        double* work, std::string* msg);
 void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,

@@ -588,7 +588,7 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
   long tot = 0, wmax = 1;
   for (size_t k = 0; k < ns.size(); ++k) {
     moff[k] = tot;
-    tot += (long)ns[k] * ns[k];
+    tot += (long)ns[k] * dense_ld(ns[k]);
     wmax = std::max(wmax, dense_work_need(ns[k]));
   }
   double* M64 = nullptr;
@@ -658,6 +658,7 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
     const size_t es = h->f32 ? sizeof(float) : sizeof(double);
     void* MTr = nullptr;
     if (hipMalloc(&MTr, es * tot) == hipSuccess) {
+      HIPCHK(hipMemsetAsync(MTr, 0, es * tot, h->stream));  // zero padding columns
       for (size_t k = 0; k < ns.size(); ++k)
         launch_transpose(h->stream, ns[k], (const char*)M + es * moff[k], (char*)MTr + es * moff[k], h->f32);
       HIPCHK(hipStreamSynchronize(h->stream));
@@ -793,7 +794,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   for (int b = 0; b < K; ++b) {
     nbs[b] = st[b + 1] - st[b];
     moff[b] = tot;
-    tot += (long)nbs[b] * nbs[b];
+    tot += (long)nbs[b] * dense_ld(nbs[b]);
     wmax = std::max(wmax, dense_work_need(nbs[b]));
   }
   auto drop = [&] {
@@ -836,6 +837,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   void* MT = nullptr;
   if (hipMalloc(&MT, es * tot) != hipSuccess) return drop();
   own.push_back(MT);
+  if (hipMemsetAsync(MT, 0, es * tot, h->stream) != hipSuccess) return drop();  // zero padding columns
   for (int b = 0; b < K; ++b)
     launch_transpose(h->stream, nbs[b], (const char*)M + es * moff[b], (char*)MT + es * moff[b], h->f32);
   std::vector<int4> itn;
