@@ -209,6 +209,11 @@ def main():
     ap.add_argument("--roofline-reps", type=int, default=5)
     ap.add_argument("--compare-precision", action="store_true",
                     help="also solve in the other precision and report speedup and solution difference")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="copy MB megabytes device to device once (a plain copy of known size for "
+                         "calibrating memory counters)")
+    ap.add_argument("--rules", action="store_true", help="rule-based setup instead of the timing tuner")
+    ap.add_argument("--verbose", action="store_true", help="print setup progress")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is "
@@ -228,7 +233,8 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    solver = cpc.Solver(p.n, p.row_ptr, p.col, p.val, device=dev, precision=args.precision)
+    solver = cpc.Solver(p.n, p.row_ptr, p.col, p.val, device=dev, precision=args.precision,
+                        tune=not args.rules, verbose=args.verbose)
     setup_s = time.perf_counter() - t0
     info = solver.hierarchy()
     log(f"setup {setup_s:.2f}s levels={info['nlev']} n={info['n']}")
@@ -274,6 +280,16 @@ def main():
                 "launches_timed": tk["launches"]}
     log(f"roofline {ROOFLINE_KERNEL}: {1000 * tk['avg_ms']:.2f} us/launch, {tk['bytes'] / 1e6:.2f} MB/launch "
         f"-> {achieved:.1f} GB/s")
+    # after the roofline launches, so that the copy's write-backs do not land on them
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration * (1 << 20)
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {nbytes} bytes")
+        del src, dst
 
     compare = None
     if args.compare_precision:
