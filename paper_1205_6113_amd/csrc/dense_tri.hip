@@ -16,8 +16,8 @@
 // B <- -C^{-1} B A^{-1} from two matrix products (library GEMMs), where A^{-1}, C^{-1}
 // are the inverted diagonal spans. The result is T^{-1}, lower triangular.
 //
-// Products: y = T^{-1} f by one workgroup per four rows (coalesced row reads, the
-// vector from L2). y = T^{-T} g: on smaller systems from a stored transpose, row by row like the
+// Products: y = T^{-1} f by one workgroup per eight rows, four from each end of the
+// system (coalesced row reads, the vector from L2). y = T^{-T} g: on smaller systems from a stored transpose, row by row like the
 // forward product; on larger ones by items (column block of 512, chunk of 1024 rows)
 // whose partial column sums go to a buffer and are added in chunk order
 // (deterministic), which reads each stored entry once without a second copy.
@@ -132,91 +132,154 @@ struct Vec16<float> {
   }
 };
 
+// Column modes of one group of rows over a run of aligned vectors: no row of the group
+// holds an entry there, every row holds every entry, or some entries are masked.
+enum { kNone = 0, kFull = 1, kMask = 2 };
+
+// Per-item context of the row products: the two row groups of the item and the rows'
+// triangles (lower rows i hold [0, i], upper rows [i, n)).
+template <bool UPPER, typename MT, typename XT>
+struct RowItem {
+  using V = Vec16<MT>;
+  using VT = typename V::T;
+  static constexpr int W = V::N;
+  const VT* ra;  // first row of group A, as vectors
+  const VT* rb;  // first row of group B
+  long vs;       // row stride in vectors
+  const XT* fs;  // the system's part of the input vector
+  int n, a0, b0, na, nb;
+  __device__ bool holds(int row, int j) const { return UPPER ? (j >= row && j < n) : j <= row; }
+};
+
+// Adds the products of the vectors at j, j + W*kNT, ... < q for the rows of groups A and B
+// in the given modes. Every loaded vector entry of the input is shared by all 8 rows.
+template <int MA, int MB, bool UPPER, typename MT, typename XT>
+__device__ __forceinline__ void add_run(const RowItem<UPPER, MT, XT>& it, int j, int q, double (&acc)[2 * kHalfRows]) {
+  using V = Vec16<MT>;
+  using VT = typename V::T;
+  constexpr int W = V::N, H = kHalfRows;
+#pragma unroll 2
+  for (; j < q; j += W * kNT) {
+    const long c = j / W;
+    VT m[2 * H];
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      m[r] = (MA != kNone && r < it.na) ? it.ra[r * it.vs + c] : VT{};
+      m[H + r] = (MB != kNone && r < it.nb) ? it.rb[r * it.vs + c] : VT{};
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int jj = j + k;
+      if (MA == kMask || MB == kMask) {
+        if (jj >= it.n) break;
+      }
+      const double fv = (double)it.fs[jj];
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        if (MA == kFull || (MA == kMask && it.holds(it.a0 + r, jj))) acc[r] += V::at(m[r], k) * fv;
+        if (MB == kFull || (MB == kMask && it.holds(it.b0 + r, jj))) acc[H + r] += V::at(m[H + r], k) * fv;
+      }
+    }
+  }
+}
+
+// Vector-aligned bounds of one group's columns: [s, e) holds every entry of the group,
+// [fl, fh) is where every row of the group holds whole vectors.
+struct GroupSpan {
+  int s, fl, fh, e;
+};
+template <bool UPPER, int W>
+__device__ __forceinline__ GroupSpan group_span(int r0, int nr, int n) {
+  if (nr == 0) return {0, 0, 0, 0};
+  const int last = r0 + nr - 1;
+  const int nv = ((n + W - 1) / W) * W;  // end of the vectors that cover [0, n)
+  if (UPPER)  // rows hold [r, n): all rows full from the last row's start to the last whole vector
+    return {(r0 / W) * W, min(((last + W - 1) / W) * W, (n / W) * W), (n / W) * W, nv};
+  // rows hold [0, r]: all rows full up to the first row's end
+  return {0, 0, ((r0 + 1) / W) * W, min((last / W + 1) * W, nv)};
+}
+__device__ __forceinline__ int group_mode(const GroupSpan& g, int j) {
+  if (j < g.s || j >= g.e) return kNone;
+  return (j >= g.fl && j < g.fh) ? kFull : kMask;
+}
+
 // y = M f with M lower (y = T^{-1} f) or upper (y = T^{-T} g from the stored
-// transpose) triangular. Items (system, first row, end row) of at most four rows: the
-// workgroup walks the columns of the four rows together, each thread taking 16 bytes
-// of each row per step (rows are 16-byte aligned; entries outside a row's triangle
-// are zero and masked), so each vector entry is loaded once for four rows; the 256
-// partials of each row are then added in a fixed order.
+// transpose) triangular. An item holds two groups of at most four rows, one from each end
+// of the system (rows 4k.. and the mirrored rows from the bottom), so that every item
+// carries about the same number of entries and no workgroup of a launch lags far behind
+// the others. The workgroup walks the columns of the item's rows together, each thread
+// taking 16 bytes of each row per step (rows are 16-byte aligned), so each vector entry
+// is loaded once for all the rows. The column range is cut at the groups' triangle edges
+// into runs where each group is absent, whole, or masked per entry; the 256 partials of
+// each row are then added in a fixed order.
 template <bool UPPER, typename MT, typename XT>
 __global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
                                                             XT* __restrict__ y, const int* __restrict__ done) {
   using V = Vec16<MT>;
-  constexpr int W = V::N;
-  __shared__ double red[kNT / 64][4];
+  using VT = typename V::T;
+  constexpr int W = V::N, H = kHalfRows;
+  __shared__ double red[kNT / 64][2 * H];
   if (done && *done) return;
-  const int4 it = dt.item_n[blockIdx.x];
-  const int s = it.x;
-  const int n = dt.n[s];
-  const long ld = dense_ld(n);
+  const int4 iv = dt.item_n[blockIdx.x];
+  const int s = iv.x;
+  RowItem<UPPER, MT, XT> it;
+  it.n = dt.n[s];
+  it.a0 = iv.y;
+  it.b0 = iv.z;
+  it.na = iv.w & 15;
+  it.nb = (iv.w >> 4) & 15;
+  const long ld = dense_ld(it.n);
   const int voff = dt.voff[s];
   const MT* __restrict__ M = reinterpret_cast<const MT*>(UPPER ? dt.MT : dt.M) + dt.moff[s];
-  const XT* __restrict__ fs = f + voff;
+  it.ra = reinterpret_cast<const VT*>(M + it.a0 * ld);
+  it.rb = reinterpret_cast<const VT*>(M + it.b0 * ld);
+  it.vs = ld / W;
+  it.fs = f + voff;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r0 = it.y, nr = it.z - it.y;  // 1 <= nr <= 4
-  // union of the rows' entries: lower rows i hold [0, i], upper rows [i, n); start at a
-  // multiple of W so that loads stay aligned
-  const int jb = UPPER ? (r0 / W) * W : 0, je = UPPER ? n : it.z;
-  const typename V::T* __restrict__ row0 = reinterpret_cast<const typename V::T*>(M + r0 * ld);
-  const long vs = ld / W;  // row stride in vectors
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  const typename V::T zero{};
-  // columns j .. j + W - 1 where every row of the item holds all of them
-  auto add_full = [&](int j) {
-    const long c = j / W;
-    const typename V::T m0 = row0[c];
-    const typename V::T m1 = nr > 1 ? row0[vs + c] : zero;
-    const typename V::T m2 = nr > 2 ? row0[2 * vs + c] : zero;
-    const typename V::T m3 = nr > 3 ? row0[3 * vs + c] : zero;
+  double acc[2 * H];
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-      const double fv = (double)fs[j + k];
-      a0 += V::at(m0, k) * fv;
-      a1 += V::at(m1, k) * fv;
-      a2 += V::at(m2, k) * fv;
-      a3 += V::at(m3, k) * fv;
-    }
-  };
-  // the same with each row's triangle and the end of the range masked
-  auto add_masked = [&](int j) {
-    const long c = j / W;
-    const typename V::T m0 = row0[c];
-    const typename V::T m1 = nr > 1 ? row0[vs + c] : zero;
-    const typename V::T m2 = nr > 2 ? row0[2 * vs + c] : zero;
-    const typename V::T m3 = nr > 3 ? row0[3 * vs + c] : zero;
+  for (int r = 0; r < 2 * H; ++r) acc[r] = 0.0;
+  const GroupSpan ga = group_span<UPPER, W>(it.a0, it.na, it.n);
+  const GroupSpan gb = group_span<UPPER, W>(it.b0, it.nb, it.n);
+  // run boundaries: the groups' span bounds, sorted (all multiples of W)
+  int cut[8] = {ga.s, ga.fl, ga.fh, ga.e, gb.s, gb.fl, gb.fh, gb.e};
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-      const int jj = j + k;
-      if (jj >= je) break;
-      const double fv = (double)fs[jj];
-      // row r0 + r holds column jj when jj <= r0 + r (lower) or jj >= r0 + r (upper)
-      if (UPPER ? jj >= r0 : jj <= r0) a0 += V::at(m0, k) * fv;
-      if (UPPER ? jj >= r0 + 1 : jj <= r0 + 1) a1 += V::at(m1, k) * fv;
-      if (UPPER ? jj >= r0 + 2 : jj <= r0 + 2) a2 += V::at(m2, k) * fv;
-      if (UPPER ? jj >= r0 + 3 : jj <= r0 + 3) a3 += V::at(m3, k) * fv;
+  for (int i = 1; i < 8; ++i)
+#pragma unroll
+    for (int k = 7; k >= i; --k)
+      if (cut[k] < cut[k - 1]) {
+        const int t = cut[k];
+        cut[k] = cut[k - 1];
+        cut[k - 1] = t;
+      }
+  for (int i = 0; i < 7; ++i) {
+    const int p = cut[i], q = cut[i + 1];
+    if (p >= q) continue;
+    const int ma = group_mode(ga, p), mb = group_mode(gb, p);
+    const int j = p + W * tid;
+    switch (ma * 3 + mb) {
+      case kNone * 3 + kFull: add_run<kNone, kFull>(it, j, q, acc); break;
+      case kNone * 3 + kMask: add_run<kNone, kMask>(it, j, q, acc); break;
+      case kFull * 3 + kNone: add_run<kFull, kNone>(it, j, q, acc); break;
+      case kFull * 3 + kFull: add_run<kFull, kFull>(it, j, q, acc); break;
+      case kFull * 3 + kMask: add_run<kFull, kMask>(it, j, q, acc); break;
+      case kMask * 3 + kNone: add_run<kMask, kNone>(it, j, q, acc); break;
+      case kMask * 3 + kFull: add_run<kMask, kFull>(it, j, q, acc); break;
+      case kMask * 3 + kMask: add_run<kMask, kMask>(it, j, q, acc); break;
+      default: break;
     }
-  };
-  // unmasked bulk [fa, fe): lower rows all hold [0, r0]; upper rows all hold [r0 + 3, n)
-  const int fa = UPPER ? min(((r0 + 3 + W - 1) / W) * W, (n / W) * W) : 0;
-  const int fe = UPPER ? (n / W) * W : ((r0 + 1) / W) * W;
-  int j = fa + W * tid;
-  for (; j + W * kNT < fe; j += 2 * W * kNT) {
-    add_full(j);
-    add_full(j + W * kNT);
   }
-  if (j < fe) add_full(j);
-  // masked edges: [jb, fa) and [fe, je), at most a few vectors each
-  for (int jm = jb + W * tid; jm < fa; jm += W * kNT) add_masked(jm);
-  for (int jm = fe + W * tid; jm < je; jm += W * kNT) add_masked(jm);
-  const double v0 = wsum<64>(a0), v1 = wsum<64>(a1), v2 = wsum<64>(a2), v3 = wsum<64>(a3);
-  if (lane == 0) {
-    red[w][0] = v0;
-    red[w][1] = v1;
-    red[w][2] = v2;
-    red[w][3] = v3;
+#pragma unroll
+  for (int r = 0; r < 2 * H; ++r) {
+    const double v = wsum<64>(acc[r]);
+    if (lane == 0) red[w][r] = v;
   }
   __syncthreads();
-  if (tid < nr) y[voff + r0 + tid] = (XT)((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
+  if (tid < 2 * H) {
+    const bool ok = tid < H ? tid < it.na : tid - H < it.nb;
+    const int row = tid < H ? it.a0 + tid : it.b0 + tid - H;
+    if (ok) y[voff + row] = (XT)((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
+  }
 }
 
 // Partial column sums of T^{-T} g: item (system, first column c0, first row r0, slot);
@@ -278,6 +341,20 @@ __global__ __launch_bounds__(kNT) void gemv_lower_t_sum_kernel(DenseTriDev dt, X
 }
 
 }  // namespace
+
+void dense_row_items(int sys, int n, std::vector<int4>& items) {
+  const int m = (n + kHalfRows - 1) / kHalfRows;  // groups of four rows, the last one ragged
+  for (int k = 0; k < (m + 1) / 2; ++k) {
+    const int a0 = k * kHalfRows, na = std::min(kHalfRows, n - a0);
+    const int kb = m - 1 - k;
+    int b0 = 0, nb = 0;
+    if (kb > k) {
+      b0 = kb * kHalfRows;
+      nb = std::min(kHalfRows, n - b0);
+    }
+    items.push_back(make_int4(sys, a0, b0, na | (nb << 4)));
+  }
+}
 
 void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,
                         const int* done) {

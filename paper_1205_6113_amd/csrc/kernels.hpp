@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 namespace cpc {
 
@@ -140,13 +141,14 @@ struct SweepPackDev {
 // Dense explicit inverses T^{-1} = (D+L)^{-1} of the systems of one level (dense_tri.hip).
 constexpr int kTCols = 512;    // columns of one item of the transposed product
 constexpr int kTChunk = 1024;  // rows of one item of the transposed product
+constexpr int kHalfRows = 4;  // rows of one group of a row-product item (two groups per item)
 struct DenseTriDev {
   const int* n;        // [nsys] rows of each system
   const long* moff;    // [nsys] element offset of each system's row-major inverse (row stride dense_ld(n))
   const int* voff;     // [nsys] first row of each system in the level vector
   const void* M;       // the inverses (lower triangular; FP64 or FP32)
   const void* MT;      // their transposes (upper triangular), or null: transposed product by items
-  int nitem_n;         // y = T^{-1} f items: {system, first row, end row, 0}
+  int nitem_n;         // row-product items: {system, first row of group A, of group B, rows of A | rows of B << 4}
   const int4* item_n;
   int nitem_t;         // partial sums of y = T^{-T} g: {system, first column, first row, slot}
   const int4* item_t;
@@ -161,6 +163,9 @@ __host__ __device__ inline int dense_ld(int n) { return (n + 3) & ~3; }
 // dense n x dense_ld(n) array M (FP64), using work (>= the largest off-diagonal product).
 bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int* ci, const double* v, double* M,
                        double* work, std::string* msg);
+// Row-product items of one system of n rows (system index sys), appended to items:
+// groups of four rows from the top paired with the mirrored groups from the bottom.
+void dense_row_items(int sys, int n, std::vector<int4>& items);
 void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,
                         const int* done);
 void launch_dense_lower_t(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* g, void* y,

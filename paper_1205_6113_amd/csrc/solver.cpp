@@ -632,7 +632,7 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
   for (int k = 0; k < (int)ns.size(); ++k) {
     const int n = ns[k];
     ent += 0.5 * (double)n * (n + 1);
-    for (int r = 0; r < n; r += 4) itn.push_back(make_int4(k, r, std::min(r + 4, n), 0));
+    dense_row_items(k, n, itn);
     for (int c0 = 0; c0 < n; c0 += kTCols) {
       const int first = slot;
       for (int r0 = (c0 / kTChunk) * kTChunk; r0 < n; r0 += kTChunk) itt.push_back(make_int4(k, c0, r0, slot++));
@@ -844,7 +844,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   std::vector<int> ioff(1, 0);
   double ent = 0.0;
   for (int b = 0; b < K; ++b) {
-    for (int r = 0; r < nbs[b]; r += 4) itn.push_back(make_int4(b, r, std::min(r + 4, nbs[b]), 0));
+    dense_row_items(b, nbs[b], itn);
     ioff.push_back((int)itn.size());
     ent += 0.5 * (double)nbs[b] * (nbs[b] + 1);
   }
