@@ -21,8 +21,11 @@
  *     adjoint, one backward sweep, as S_l^T (Section 3.3).
  *   - Combined preconditioner (Algorithm 2.1): S = one V-cycle, B = ILU(0)
  *     (the assignment of Section 3 and of the experiments in Section 5).
- *   - Comparators of Table 5.2: ILU(0) alone, AMG(GS) with two cycles, and the
+ *   - Comparators of Table 5.2: ILU(0) alone, AMG(GS) with two cycles, AMG(ILU(0))
+ *     (ILU(0) as the finest-level smoother, GS below, two cycles), and the
  *     additive form S~ + B of eq. (2.7) with W_1 = V, A_1^{-1} = B.
+ *   - The wrong-order composition B-bar of the remark after Theorem 2.1, which is
+ *     not SPD in general (the negative case the remark warns about).
  *   - PCG stopped on the relative residual of the recursively updated residual.
  *
  * Readings where the paper is silent (strength threshold, tie-breaks, second
@@ -46,7 +49,11 @@ enum {
   OR_OP_FGS = 6,        /* forward GS from zero on the finest level, (D+L)^{-1}   */
   OR_OP_BGS = 7,        /* backward GS from zero on the finest level, (D+U)^{-1}  */
   OR_OP_COMBINED_GS = 8,/* Algorithm 2.1 with S = (D+L)^{-1}, S^T = (D+U)^{-1}, B = ILU(0) */
-  OR_OP_COMBINED_SWAP = 9 /* Algorithm 2.1 with S = ILU(0), B = V-cycle           */
+  OR_OP_COMBINED_SWAP = 9, /* Algorithm 2.1 with S = ILU(0), B = V-cycle          */
+  OR_PREC_AMG_ILU = 10, /* AMG(ILU(0)) of Table 5.2: two V-cycles whose finest-level
+                           smoother is ILU(0) (GS below)                          */
+  OR_PREC_BBAR = 11     /* the wrong-order B-bar of Remark 2.1:
+                           I - B-bar A = (I - BA)(I - S~A)(I - BA)               */
 };
 
 #define OR_MAXLEV 64
@@ -780,6 +787,35 @@ static void vcycle(const or_hier* h, int d, const double* f, double* u) {
   free(e);
 }
 
+/* The V-cycle of the AMG(ILU(0)) comparator (Section 5): as Algorithm 3.2 on the
+ * finest level but with ILU(0) as the smoother, pre: u1 = (LU)^{-1} f, post:
+ * u3 = u2 + (LU)^{-1} (f - A u2) (for symmetric A the ILU(0) product LU is
+ * symmetric up to rounding, so the same factor serves as its own adjoint); the
+ * coarser levels use the Gauss-Seidel V-cycle. A one-level hierarchy is the exact
+ * solve. */
+static void vcycle_ilu_top(const or_hier* h, const double* f, double* u) {
+  if (h->nlev == 1) { coarse_solve(h, f, u); return; }
+  const or_csr* A = &h->A[0];
+  int n = A->n, nc = h->A[1].n;
+  double* r = (double*)malloc(sizeof(double) * (size_t)n);
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  double* fc = (double*)malloc(sizeof(double) * (size_t)nc);
+  double* e = (double*)malloc(sizeof(double) * (size_t)nc);
+  ilu_apply(h, f, u);
+  residual(A, f, u, r);
+  spmv(&h->R[0], r, fc);
+  vcycle(h, 1, fc, e);
+  spmv(&h->P[0], e, w);
+  for (int i = 0; i < n; ++i) u[i] = u[i] + w[i];
+  residual(A, f, u, r);
+  ilu_apply(h, r, w);
+  for (int i = 0; i < n; ++i) u[i] = u[i] + w[i];
+  free(r);
+  free(w);
+  free(fc);
+  free(e);
+}
+
 typedef void (*op_fn)(const or_hier* h, const double* r, double* z);
 
 static void op_vcycle(const or_hier* h, const double* r, double* z) { vcycle(h, 0, r, z); }
@@ -825,6 +861,41 @@ static void sym_smoother(const or_hier* h, const double* f, double* u) {
   free(w);
 }
 
+/* AMG(ILU(0)) with two cycles: z = V'(f), z = z + V'(f - A z), V' = vcycle_ilu_top */
+static void amg_ilu(const or_hier* h, const double* f, double* u) {
+  const or_csr* A = &h->A[0];
+  int n = A->n;
+  double* r = (double*)malloc(sizeof(double) * (size_t)n);
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  vcycle_ilu_top(h, f, u);
+  residual(A, f, u, r);
+  vcycle_ilu_top(h, r, w);
+  for (int i = 0; i < n; ++i) u[i] = u[i] + w[i];
+  free(r);
+  free(w);
+}
+
+/* B-bar of the remark after Theorem 2.1, I - B-bar A = (I - BA)(I - S~A)(I - BA),
+ * applied to f from a zero start: the error propagators act right to left, so
+ *   u1 = B f,  u2 = u1 + S~ (f - A u1),  u3 = u2 + B (f - A u2),
+ * with B = b_scale * ILU(0) and S~ the two-cycle AMG(GS) operator. */
+static void bbar(const or_hier* h, const double* f, double* u) {
+  const or_csr* A = &h->A[0];
+  int n = A->n;
+  double* r = (double*)malloc(sizeof(double) * (size_t)n);
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  ilu_apply(h, f, u);
+  for (int i = 0; i < n; ++i) u[i] = h->b_scale * u[i];
+  residual(A, f, u, r);
+  sym_smoother(h, r, w);
+  for (int i = 0; i < n; ++i) u[i] = u[i] + w[i];
+  residual(A, f, u, r);
+  ilu_apply(h, r, w);
+  for (int i = 0; i < n; ++i) u[i] = u[i] + h->b_scale * w[i];
+  free(r);
+  free(w);
+}
+
 int or_apply(const or_hier* h, int which, const double* r, double* z) {
   int n = h->A[0].n;
   switch (which) {
@@ -845,6 +916,8 @@ int or_apply(const or_hier* h, int which, const double* r, double* z) {
     case OR_OP_BGS: backward_gs(&h->A[0], r, z); return OR_OK;
     case OR_OP_COMBINED_GS: combined(h, op_fgs, op_ilu, op_bgs, r, z); return OR_OK;
     case OR_OP_COMBINED_SWAP: combined(h, op_ilu, op_vcycle, op_ilu, r, z); return OR_OK;
+    case OR_PREC_AMG_ILU: amg_ilu(h, r, z); return OR_OK;
+    case OR_PREC_BBAR: bbar(h, r, z); return OR_OK;
     default: return OR_E_ARG;
   }
 }

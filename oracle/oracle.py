@@ -21,6 +21,7 @@ import numpy as np
 OR_OK, OR_E_ARG, OR_E_NOT_SPD, OR_E_BREAKDOWN, OR_E_MAXIT, OR_E_NOMEM = 0, 1, 2, 3, 4, 6
 PREC_COMBINED, PREC_AMG, PREC_ILU, PREC_ADDITIVE, PREC_NONE = 0, 1, 2, 3, 4
 OP_VCYCLE, OP_FGS, OP_BGS, OP_COMBINED_GS, OP_COMBINED_SWAP = 5, 6, 7, 8, 9
+PREC_AMG_ILU, PREC_BBAR = 10, 11
 
 _HERE = Path(__file__).resolve().parent
 _SRC = _HERE / "cpc_oracle.c"

@@ -429,6 +429,92 @@ def test_swapped_roles_variant_is_spd_here():
     assert np.max(np.abs(Bs - Bs.T)) <= 1e-11 * np.max(np.abs(Bs))
 
 
+def test_amg_ilu_is_exact_where_ilu0_is():
+    """AMG(ILU(0)) of Table 5.2 (ILU(0) as the finest-level smoother, two cycles):
+    on a tridiagonal matrix ILU(0) is the exact LU, so the pre-smoothing already
+    solves the system, the coarse correction and the post-smoothing add nothing and
+    the operator is A^{-1} (compared with LAPACK's solve), on a hierarchy with
+    several levels."""
+    rng = np.random.default_rng(21)
+    n = 300
+    off = -rng.uniform(0.5, 2.0, n - 1)
+    d = np.zeros(n)
+    d[:-1] -= off
+    d[1:] -= off
+    d += rng.uniform(0.0, 0.2, n)
+    A = np.diag(d) + np.diag(off, 1) + np.diag(off, -1)
+    n_, rp, ci, v = dense_to_csr(A)
+    h = oracle.Hierarchy(n, rp, ci, v, max_coarse=16)
+    assert h.nlev >= 3
+    f = rng.standard_normal(n)
+    z = h.apply(oracle.PREC_AMG_ILU, f)
+    x = sla.solve(A, f, assume_a="pos")
+    assert np.linalg.norm(z - x) <= 1e-11 * np.linalg.norm(x)
+    # the AMG(GS) comparator is not exact here: the pin separates the two smoothers
+    zg = h.apply(oracle.PREC_AMG, f)
+    assert np.linalg.norm(zg - x) > 1e-8 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("dims,seed", [((6, 6, 1), 71), ((4, 4, 4), 72)])
+def test_amg_ilu_symmetric_positive_here(dims, seed):
+    """With A symmetric, ILU(0) = L D L^T up to rounding, so AMG(ILU(0)) is
+    symmetric; on these M-matrices ILU(0) converges and the operator is SPD."""
+    n, rp, ci, v, A = tiny_problem(*dims, seed, sigma=2.0)
+    h = oracle.Hierarchy(n, rp, ci, v, max_coarse=6)
+    assert h.nlev >= 2
+    V = h.dense_operator(oracle.PREC_AMG_ILU)
+    assert np.max(np.abs(V - V.T)) <= 1e-12 * np.max(np.abs(V))
+    assert np.linalg.eigvalsh(0.5 * (V + V.T)).min() > 0
+
+
+@pytest.mark.parametrize("omega", [1.0, 8.0])
+def test_bbar_error_propagator(omega):
+    """Remark after Theorem 2.1: I - B-bar A = (I - BA)(I - S~A)(I - BA), here with
+    B = omega * ILU(0) and S~ the two-cycle AMG(GS) operator, both as dense matrices
+    taken from their own operators."""
+    n, rp, ci, v, A = tiny_problem(6, 5, 2, 61, sigma=1.5)
+    h1 = oracle.Hierarchy(n, rp, ci, v, max_coarse=8)
+    B = omega * h1.dense_operator(oracle.PREC_ILU)
+    St = h1.dense_operator(oracle.PREC_AMG)
+    h = oracle.Hierarchy(n, rp, ci, v, max_coarse=8, b_scale=omega)
+    Bb = h.dense_operator(oracle.PREC_BBAR)
+    I = np.eye(n)
+    lhs = I - Bb @ A
+    rhs = (I - B @ A) @ (I - St @ A) @ (I - B @ A)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-11 * max(1.0, np.max(np.abs(lhs)))
+
+
+def test_bbar_without_b_is_the_two_cycle_smoother():
+    """B = 0 leaves I - B-bar A = I - S~A: B-bar is the AMG(GS) comparator, bitwise."""
+    n, rp, ci, v, A = tiny_problem(8, 7, 2, 91, sigma=1.5)
+    h0 = oracle.Hierarchy(n, rp, ci, v, max_coarse=8, b_scale=0.0)
+    h = oracle.Hierarchy(n, rp, ci, v, max_coarse=8)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        r = rng.standard_normal(n)
+        assert np.array_equal(h0.apply(oracle.PREC_BBAR, r), h.apply(oracle.PREC_AMG, r))
+
+
+@pytest.mark.parametrize("dims,seed", [((6, 6, 1), 71), ((8, 7, 2), 91), ((12, 12, 2), 5)])
+def test_bbar_loses_definiteness_where_bco_keeps_it(dims, seed):
+    """The remark's warning: with B scaled so that I - BA is far from a contraction
+    (omega = 8, largest eigenvalue of BA well above 2) the wrong-order B-bar is
+    indefinite and PCG with it breaks down, while B_co built from the same S and B
+    stays SPD (Theorem 2.1 needs only B SPD) and PCG with it converges."""
+    n, rp, ci, v, A = tiny_problem(*dims, seed, sigma=2.0)
+    h = oracle.Hierarchy(n, rp, ci, v, max_coarse=6, b_scale=8.0)
+    Bb = h.dense_operator(oracle.PREC_BBAR)
+    Bc = h.dense_operator(oracle.PREC_COMBINED)
+    B = h.dense_operator(oracle.PREC_ILU)
+    assert np.max(np.linalg.eigvals(8.0 * B @ A).real) > 2.0
+    assert np.linalg.eigvalsh(0.5 * (Bb + Bb.T)).min() < 0
+    assert np.max(np.abs(Bc - Bc.T)) <= 1e-12 * np.max(np.abs(Bc))
+    assert np.linalg.eigvalsh(0.5 * (Bc + Bc.T)).min() > 0
+    b = np.random.default_rng(3).standard_normal(n)
+    assert h.pcg(oracle.PREC_BBAR, b, 1e-10, 300)["status"] == oracle.OR_E_BREAKDOWN
+    assert h.pcg(oracle.PREC_COMBINED, b, 1e-10, 300)["status"] == oracle.OR_OK
+
+
 def test_table_5_2_ordering_qualitative():
     """Qualitative ordering of Table 5.2 on a scaled synthetic case:
     B_co needs the fewest iterations; ILU(0) the most. (parity unpinned: the
