@@ -51,7 +51,12 @@ typedef enum {
   CPC_PREC_AMG = 1,      /* AMG(GS): two V-cycles, i.e. S~ of Section 2 with S = V-cycle    */
   CPC_PREC_ILU = 2,      /* ILU(0) alone                                                    */
   CPC_PREC_ADDITIVE = 3, /* B^ = S~ + B, eq. (2.7) with W_1 = V, Pi_1 = I, A_1^{-1} = B      */
-  CPC_PREC_NONE = 4      /* identity (plain CG)                                             */
+  CPC_PREC_NONE = 4,     /* identity (plain CG)                                             */
+  CPC_PREC_AMG_ILU = 5,  /* AMG(ILU(0)) of Table 5.2: two V-cycles with ILU(0) as the
+                            finest-level smoother (pre and post) and GS below            */
+  CPC_PREC_BBAR = 6      /* B-bar of the remark after Theorem 2.1, the wrong order:
+                            I - B-bar A = (I - BA)(I - S~A)(I - BA); not SPD in general
+                            (kept to show why Algorithm 2.1's order matters)              */
 } cpc_prec;
 
 /* Operators applied by cpc_apply_op (each z = M r from a zero initial guess). */
@@ -63,7 +68,9 @@ typedef enum {
   CPC_OP_NONE = 4,     /* identity                                                          */
   CPC_OP_VCYCLE = 5,   /* one V-cycle (Algorithm 3.2)                                       */
   CPC_OP_FGS = 6,      /* (D+L)^{-1} on the finest level (one forward Gauss-Seidel sweep)   */
-  CPC_OP_BGS = 7       /* (D+U)^{-1} on the finest level (one backward Gauss-Seidel sweep)  */
+  CPC_OP_BGS = 7,      /* (D+U)^{-1} on the finest level (one backward Gauss-Seidel sweep)  */
+  CPC_OP_AMG_ILU = 8,  /* AMG(ILU(0)), as CPC_PREC_AMG_ILU                                  */
+  CPC_OP_BBAR = 9      /* B-bar, as CPC_PREC_BBAR                                           */
 } cpc_op;
 
 typedef enum {

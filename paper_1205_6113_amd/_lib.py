@@ -14,8 +14,9 @@ CPC_OK, CPC_E_ARG, CPC_E_NOT_SPD, CPC_E_BREAKDOWN, CPC_E_MAXIT, CPC_E_DEVICE, CP
 STATUS_NAMES = {0: "CPC_OK", 1: "CPC_E_ARG", 2: "CPC_E_NOT_SPD", 3: "CPC_E_BREAKDOWN", 4: "CPC_E_MAXIT",
                 5: "CPC_E_DEVICE", 6: "CPC_E_NOMEM"}
 
-PREC = {"combined": 0, "amg": 1, "ilu": 2, "additive": 3, "none": 4}
-OP = {"combined": 0, "amg": 1, "ilu": 2, "additive": 3, "none": 4, "vcycle": 5, "fgs": 6, "bgs": 7}
+PREC = {"combined": 0, "amg": 1, "ilu": 2, "additive": 3, "none": 4, "amg_ilu": 5, "bbar": 6}
+OP = {"combined": 0, "amg": 1, "ilu": 2, "additive": 3, "none": 4, "vcycle": 5, "fgs": 6, "bgs": 7,
+      "amg_ilu": 8, "bbar": 9}
 PRECISION = {"fp64": 0, "fp32": 1}
 DENSE = {"auto": 0, "never": 1, "always": 2, "block": 3}
 

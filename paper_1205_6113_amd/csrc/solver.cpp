@@ -141,6 +141,8 @@ struct Level {
 
 }  // namespace cpc
 
+constexpr int kNumPrec = CPC_PREC_BBAR + 1;  // preconditioners cpc_solve can run
+
 struct cpc_solver {
   cpc_options opt{};
   hipStream_t stream = nullptr;
@@ -166,9 +168,9 @@ struct cpc_solver {
   std::vector<void*> owned;
   std::vector<void*>* cur_owned = &owned;  // where sweep schedules and packs are allocated
   // captured iteration graphs, one per preconditioner
-  hipGraphExec_t graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipGraph_t graph_src[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  double* graph_x[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // x bound into each graph
+  hipGraphExec_t graph[kNumPrec] = {};
+  hipGraph_t graph_src[kNumPrec] = {};
+  double* graph_x[kNumPrec] = {};  // x bound into each graph
   const double* op_vals = nullptr;  // values PCG multiplies by (null: the setup matrix)
   // batch of independent systems (cpc_setup_batch)
   bool batch = false;
@@ -177,12 +179,12 @@ struct cpc_solver {
   cpc::BatchDev bd{};
   double* btol = nullptr;
   int* bmaxit = nullptr;
-  hipGraphExec_t bgraph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipGraph_t bgraph_src[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  double* bgraph_x[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t bgraph[kNumPrec] = {};
+  hipGraph_t bgraph_src[kNumPrec] = {};
+  double* bgraph_x[kNumPrec] = {};
 
   ~cpc_solver() {
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < kNumPrec; ++i) {
       if (graph[i]) (void)hipGraphExecDestroy(graph[i]);
       if (graph_src[i]) (void)hipGraphDestroy(graph_src[i]);
       if (bgraph[i]) (void)hipGraphExecDestroy(bgraph[i]);
@@ -1297,6 +1299,31 @@ static void ilu_apply(cpc_solver* h, const void* f, void* w, const void* base, v
   run_sweep(h, out ? SWEEP_UPPER_OUT : SWEEP_UPPER, L.upper, h->ilu_u, h->y, w, base, out, done);
 }
 
+// The V-cycle of the AMG(ILU(0)) comparator (Section 5): Algorithm 3.2 with ILU(0) as
+// the smoother on the finest level, pre u = (LU)^{-1} f and post u += (LU)^{-1}(f - A u)
+// (for symmetric A the ILU(0) product is symmetric up to rounding, so the factor is its
+// own adjoint), and the Gauss-Seidel V-cycle below. Rows of systems solved exactly on
+// the finest level (batches) are overwritten by that solve at the end.
+static void vcycle_ilu_top(cpc_solver* h, const void* f, void* u, const int* done) {
+  Level& L = h->lev[0];
+  const bool f32 = h->f32;
+  if (!(L.nS > 0 && h->lev.size() > 1)) {
+    vcycle(h, 0, f, u, done);
+    return;
+  }
+  Level& C = h->lev[1];
+  const MatDev A = smoothed(L.A, L.nS, f32);
+  ilu_apply(h, f, u, nullptr, nullptr, done);                                           // (1)
+  spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);                       // (2a)
+  spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
+  vcycle(h, 1, C.f, C.u, done);                                                         // (2b)
+  spmv_or_throw(h, L.P.mat(f32), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);     // (2c)
+  spmv_or_throw(h, A, 1, u, f32, f, f32, L.t, f32, L.A.tpr, done);                       // (3)
+  ilu_apply(h, L.t, L.r, nullptr, nullptr, done);
+  launch_vec(h->stream, 1, L.nS, L.r, f32, nullptr, false, u, f32, done);
+  if (L.dense.nblk > 0) launch_bdense(h->stream, L.dense, f, u, f32, done);
+}
+
 // res = r - A u with FP64 A and FP64 r (outer residual of Algorithm 2.1)
 static void outer_residual(cpc_solver* h, const double* r, const void* u, void* res, const int* done) {
   Level& L = h->lev[0];
@@ -1336,6 +1363,29 @@ static void apply_op(cpc_solver* h, int op, const double* r, double* z, const in
       outer_residual(h, r, h->u1, h->res, done);
       vcycle(h, 0, h->res, h->t, done);
       launch_vec(h->stream, 0, n, h->u1, f32, h->t, f32, z, false, done);
+      break;
+    }
+    case CPC_OP_AMG_ILU: {  // two ILU(0)-smoothed cycles: z = V'(r) + V'(r - A V'(r))
+      vcycle_ilu_top(h, rin, h->u1, done);
+      outer_residual(h, r, h->u1, h->res, done);
+      vcycle_ilu_top(h, h->res, h->t, done);
+      launch_vec(h->stream, 0, n, h->u1, f32, h->t, f32, z, false, done);
+      break;
+    }
+    case CPC_OP_BBAR: {
+      // I - B-bar A = (I - BA)(I - S~A)(I - BA) from a zero start, the propagators
+      // acting right to left: u1 = B r, u2 = u1 + S~(r - A u1), z = u2 + B(r - A u2),
+      // with S~(g) = a + V(g - A a), a = V(g), i.e. u2 = (u1 + a) + V(r - A(u1 + a))
+      ilu_apply(h, rin, h->u1, nullptr, nullptr, done);
+      outer_residual(h, r, h->u1, h->res, done);
+      vcycle(h, 0, h->res, h->t, done);
+      launch_vec(h->stream, 0, n, h->u1, f32, h->t, f32, h->u2, f32, done);
+      outer_residual(h, r, h->u2, h->res, done);
+      vcycle(h, 0, h->res, h->t, done);
+      launch_vec(h->stream, 1, n, h->t, f32, nullptr, false, h->u2, f32, done);
+      outer_residual(h, r, h->u2, h->res, done);
+      ilu_apply(h, h->res, h->t, nullptr, nullptr, done);
+      launch_vec(h->stream, 0, n, h->u2, f32, h->t, f32, z, false, done);
       break;
     }
     case CPC_OP_ILU: {
@@ -1386,6 +1436,8 @@ static int prec_to_op(int prec) {
     case CPC_PREC_AMG: return CPC_OP_AMG;
     case CPC_PREC_ILU: return CPC_OP_ILU;
     case CPC_PREC_ADDITIVE: return CPC_OP_ADDITIVE;
+    case CPC_PREC_AMG_ILU: return CPC_OP_AMG_ILU;
+    case CPC_PREC_BBAR: return CPC_OP_BBAR;
     default: return CPC_OP_NONE;
   }
 }
@@ -1408,6 +1460,22 @@ static void enqueue_iteration(cpc_solver* h, int prec, double* x) {
 
 // Algorithmic HBM bytes of one application of each piece (byte model of the
 // measurement plan: matrix streams read once per pass, vectors once per kernel).
+// Bytes of the smoothing on level d of one V-cycle: pre-smoothing, the strict-lower
+// pass of the post-smoothing and the post-smoothing (same model as vcycle_bytes).
+static double level_smooth_bytes(const cpc_solver* h, size_t d) {
+  const double vb = h->f32 ? 4.0 : 8.0;
+  const double mb = h->f32 ? 8.0 : 12.0;
+  const Level& L = h->lev[d];
+  if (!(L.nS > 0 && d + 1 < h->lev.size())) return 0.0;
+  const double nz = (double)L.nnzS, n = L.nS, half = 0.5 * (nz - n);
+  const double eb = h->f32 ? 4.0 : 8.0;
+  double one;
+  if (L.bdense) one = eb * L.bd_entries + (double)L.bd_Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
+  else if (L.dense_smooth) one = eb * L.dense_entries + 2.0 * vb * n;
+  else one = vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;
+  return 2.0 * one + half * mb + 4.0 * n + 3.0 * vb * n;
+}
+
 static double vcycle_bytes(const cpc_solver* h) {
   const double vb = h->f32 ? 4.0 : 8.0;           // vector element
   const double mb = h->f32 ? 8.0 : 12.0;          // matrix entry (value + column)
@@ -1478,6 +1546,14 @@ static double prec_bytes(const cpc_solver* h, int prec) {
     case CPC_PREC_AMG: return conv + 2.0 * V + outer + (2.0 * vb + 8.0) * n;
     case CPC_PREC_ILU: return conv + ilu + (vb + 8.0) * n;
     case CPC_PREC_ADDITIVE: return conv + 2.0 * V + outer + ilu + 2.0 * (2.0 * vb + 8.0) * n;
+    case CPC_PREC_AMG_ILU: {
+      // each cycle trades the finest level's two sweeps (and the strict-lower pass)
+      // for two ILU(0) applications, a residual and an axpy
+      const double Vi = V - level_smooth_bytes(h, 0) + 2.0 * ilu + (nz * mb + 4.0 * n + 3.0 * vb * n) +
+                        3.0 * vb * n;
+      return conv + 2.0 * Vi + outer + (2.0 * vb + 8.0) * n;
+    }
+    case CPC_PREC_BBAR: return conv + 2.0 * V + 2.0 * ilu + 3.0 * outer + 3.0 * (2.0 * vb + 8.0) * n;
     default: return 16.0 * n;
   }
 }
@@ -1494,7 +1570,7 @@ static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x,
   if (h->batch) return set_err(CPC_E_ARG, "batch handle: use cpc_solve_batch");
   if (!b || !x) return set_err(CPC_E_ARG, "null vector");
   if (maxit < 0 || !(tol >= 0.0)) return set_err(CPC_E_ARG, "maxit must be >= 0 and tol >= 0");
-  if (prec < 0 || prec > CPC_PREC_NONE) return set_err(CPC_E_ARG, "unknown preconditioner");
+  if (prec < 0 || prec >= kNumPrec) return set_err(CPC_E_ARG, "unknown preconditioner");
   const double t0 = now_s();
   try {
     PcgState init{};
@@ -1729,7 +1805,7 @@ static cpc_status read_options(const cpc_options* opt, cpc_options& o) {
     if (opt->struct_size != (int32_t)sizeof(cpc_options)) return set_err(CPC_E_ARG, "cpc_options.struct_size mismatch");
     o = *opt;
   }
-  if (o.prec < 0 || o.prec > CPC_PREC_NONE) return set_err(CPC_E_ARG, "unknown preconditioner");
+  if (o.prec < 0 || o.prec >= kNumPrec) return set_err(CPC_E_ARG, "unknown preconditioner");
   if (o.precision != CPC_FP64 && o.precision != CPC_FP32_PRECOND) return set_err(CPC_E_ARG, "unknown precision");
   if (o.max_levels < 1 || o.max_levels > 64 || o.max_coarse < 1) return set_err(CPC_E_ARG, "bad level limits");
   if (!(o.theta >= 0.0 && o.theta <= 1.0)) return set_err(CPC_E_ARG, "theta must lie in [0, 1]");
@@ -1899,7 +1975,7 @@ cpc_status cpc_solve_with(cpc_handle h, int32_t prec, const double* b_dev, doubl
 cpc_status cpc_apply_op(cpc_handle h, int32_t op, const double* r_dev, double* z_dev) {
   if (!h) return set_err(CPC_E_ARG, "null handle");
   if (!r_dev || !z_dev) return set_err(CPC_E_ARG, "null vector");
-  if (op < CPC_OP_COMBINED || op > CPC_OP_BGS) return set_err(CPC_E_ARG, "unknown operator");
+  if (op < CPC_OP_COMBINED || op > CPC_OP_BBAR) return set_err(CPC_E_ARG, "unknown operator");
   try {
     apply_op(h, op, r_dev, z_dev, nullptr);
     HIPCHK(hipGetLastError());
@@ -2229,7 +2305,7 @@ cpc_status cpc_set_operator_values(cpc_handle h, const double* val_dev) {
   if (!h) return set_err(CPC_E_ARG, "null handle");
   if (h->op_vals != val_dev) {
     h->op_vals = val_dev;
-    for (int i = 0; i < 5; ++i) {  // captured graphs bind the operator's values
+    for (int i = 0; i < kNumPrec; ++i) {  // captured graphs bind the operator's values
       if (h->graph[i]) (void)hipGraphExecDestroy(h->graph[i]);
       if (h->graph_src[i]) (void)hipGraphDestroy(h->graph_src[i]);
       h->graph[i] = nullptr;

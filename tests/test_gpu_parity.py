@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 OPS = {"combined": oracle.PREC_COMBINED, "amg": oracle.PREC_AMG, "ilu": oracle.PREC_ILU,
        "additive": oracle.PREC_ADDITIVE, "none": oracle.PREC_NONE, "vcycle": oracle.OP_VCYCLE,
-       "fgs": oracle.OP_FGS, "bgs": oracle.OP_BGS}
+       "fgs": oracle.OP_FGS, "bgs": oracle.OP_BGS, "amg_ilu": oracle.PREC_AMG_ILU, "bbar": oracle.PREC_BBAR}
 
 
 def _cpc():
@@ -116,7 +116,7 @@ def true_relres(p, x):
     return float(np.linalg.norm(p.b - ax) / np.linalg.norm(p.b))
 
 
-@pytest.mark.parametrize("prec", ["combined", "amg", "additive"])
+@pytest.mark.parametrize("prec", ["combined", "amg", "additive", "amg_ilu", "bbar"])
 def test_pcg_parity(cases, prec):
     """Iteration counts equal and x within 1e-10 of the oracle at the oracle's
     iteration count (the AMG-based preconditioners converge in a few iterations,
