@@ -71,6 +71,7 @@ typedef struct {
   int check_symmetry;
   double s_scale; /* S := s_scale * S inside Algorithm 2.1 (1 = the method; 0 = degenerate S = 0) */
   double b_scale; /* B := b_scale * B inside Algorithm 2.1 and eq. (2.7) (Theorem 2.2 scales B) */
+  int ilu_k;      /* level of fill of the ILU factorisation B (Algorithm 3.1); 0 = ILU(0) */
 } or_opts;
 
 typedef struct {
@@ -83,6 +84,9 @@ typedef struct {
   int n0;              /* coarsest size                                                  */
   double *chol;        /* lower Cholesky factor of the coarsest matrix, row-major n0 x n0 */
   double *lu;          /* ILU(0) values on the pattern of the finest A                   */
+  or_csr F;            /* the ILU(k) factor applied as B: L strictly lower (unit diagonal
+                          implied), U on and above the diagonal; for k = 0 the pattern of A */
+  int *flev;           /* level of fill of every entry of F                              */
   double *work;        /* scratch vectors                                                 */
   double s_scale, b_scale;
 } or_hier;
@@ -182,6 +186,108 @@ int or_ilu0(int n, const int* rp, const int* ci, const double* v, double* lu) {
   free(diag);
   return status;
 }
+
+/* ------------------------------------------------------------------ */
+/* ILU(k), Algorithm 3.1 with the level of fill of its definition. Row i starts as
+ * row i of A with level 0 on its entries (the diagonal included). For m < i in
+ * increasing order, if the current level of (i, m) is at most k:
+ *   a_im := a_im / u_mm, then for every stored entry (m, j), j > m, of the factor:
+ *   a_ij := a_ij - a_im u_mj (an entry not yet in row i enters as 0 first) and
+ *   lev_ij := min(lev_ij, lev_im + lev_mj + 1).
+ * Entries created in row i join the sweep over m in column order. At the end of
+ * the row every entry with level above k is dropped. Output (malloc'ed, freed with
+ * or_free_buf): frp[n+1], fci/fv/flev[nnz] sorted by column. For k = 0 the
+ * pattern is that of A and the values are those of or_ilu0. */
+#define OR_LEV_INF (1 << 28)
+int or_iluk(int n, const int* rp, const int* ci, const double* v, int k, int** frp_out, int** fci_out,
+            double** fv_out, int** flev_out) {
+  int* frp = (int*)malloc(sizeof(int) * ((size_t)n + 1));
+  int* fdiag = (int*)malloc(sizeof(int) * (size_t)n);
+  double* w = (double*)malloc(sizeof(double) * (size_t)n);
+  int* lv = (int*)malloc(sizeof(int) * (size_t)n);
+  int* nxt = (int*)malloc(sizeof(int) * ((size_t)n + 1));
+  long cap = (long)rp[n] + n + 16, nnz = 0;
+  int* fci = (int*)malloc(sizeof(int) * (size_t)cap);
+  double* fv = (double*)malloc(sizeof(double) * (size_t)cap);
+  int* flev = (int*)malloc(sizeof(int) * (size_t)cap);
+  int status = OR_OK;
+  if (!frp || !fdiag || !w || !lv || !nxt || !fci || !fv || !flev) { status = OR_E_NOMEM; goto out; }
+  for (int j = 0; j < n; ++j) lv[j] = -1; /* -1: column not in the working row */
+  frp[0] = 0;
+  for (int i = 0; i < n && status == OR_OK; ++i) {
+    /* working row: a sorted linked list of columns, head at index n */
+    int last = n;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      int j = ci[p];
+      w[j] = v[p];
+      lv[j] = 0;
+      nxt[last] = j;
+      last = j;
+    }
+    nxt[last] = -1;
+    for (int m = nxt[n]; m >= 0 && m < i; m = nxt[m]) {
+      if (lv[m] > k) continue;
+      w[m] = w[m] / fv[fdiag[m]];
+      int at = m; /* insertion point: the list is sorted and every j below is > m */
+      for (int q = fdiag[m] + 1; q < frp[m + 1]; ++q) {
+        int j = fci[q];
+        if (lv[j] < 0) {
+          while (nxt[at] >= 0 && nxt[at] < j) at = nxt[at];
+          nxt[j] = nxt[at];
+          nxt[at] = j;
+          w[j] = 0.0;
+          lv[j] = OR_LEV_INF;
+        }
+        w[j] = w[j] - w[m] * fv[q];
+        int l = lv[m] + flev[q] + 1;
+        if (l < lv[j]) lv[j] = l;
+        at = j;
+      }
+    }
+    /* keep the entries of level <= k */
+    for (int j = nxt[n]; j >= 0; j = nxt[j]) {
+      if (lv[j] <= k) {
+        if (nnz == cap) {
+          cap = 2 * cap;
+          int* a = (int*)realloc(fci, sizeof(int) * (size_t)cap);
+          if (a) fci = a;
+          double* b = (double*)realloc(fv, sizeof(double) * (size_t)cap);
+          if (b) fv = b;
+          int* c = (int*)realloc(flev, sizeof(int) * (size_t)cap);
+          if (c) flev = c;
+          if (!a || !b || !c) { status = OR_E_NOMEM; break; }
+        }
+        if (j == i) fdiag[i] = (int)nnz;
+        fci[nnz] = j;
+        fv[nnz] = w[j];
+        flev[nnz] = lv[j];
+        nnz++;
+      }
+    }
+    for (int j = nxt[n]; j >= 0; j = nxt[j]) lv[j] = -1;
+    frp[i + 1] = (int)nnz;
+    if (status == OR_OK && !(fv[fdiag[i]] > 0.0)) status = OR_E_NOT_SPD;
+  }
+out:
+  free(fdiag);
+  free(w);
+  free(lv);
+  free(nxt);
+  if (status != OR_OK) {
+    free(frp);
+    free(fci);
+    free(fv);
+    free(flev);
+    return status;
+  }
+  *frp_out = frp;
+  *fci_out = fci;
+  *fv_out = fv;
+  *flev_out = flev;
+  return OR_OK;
+}
+
+void or_free_buf(void* p) { free(p); }
 
 /* ------------------------------------------------------------------ */
 /* Classical Ruge-Stueben coarsening of one level.
@@ -594,6 +700,7 @@ void or_default_opts(or_opts* o) {
   o->check_symmetry = 1;
   o->s_scale = 1.0;
   o->b_scale = 1.0;
+  o->ilu_k = 0;
 }
 
 void or_free(or_hier* h) {
@@ -606,6 +713,8 @@ void or_free(or_hier* h) {
   }
   free(h->chol);
   free(h->lu);
+  csr_free(&h->F);
+  free(h->flev);
   free(h->work);
   free(h);
 }
@@ -631,6 +740,18 @@ or_hier* or_setup(int n, const int* rp, const int* ci, const double* v, const or
   if (!h->lu) goto nomem;
   *status = or_ilu0(n, rp, ci, v, h->lu);
   if (*status) { or_free(h); return NULL; }
+  if (o.ilu_k < 0) o.ilu_k = 0;
+  {
+    int *frp, *fci, *flev;
+    double* fv;
+    *status = or_iluk(n, rp, ci, v, o.ilu_k, &frp, &fci, &fv, &flev);
+    if (*status) { or_free(h); return NULL; }
+    h->F.n = n;
+    h->F.rp = frp;
+    h->F.ci = fci;
+    h->F.v = fv;
+    h->flev = flev;
+  }
   int d = 0;
   for (;;) {
     or_csr* A = &h->A[d];
@@ -711,10 +832,10 @@ static void backward_gs(const or_csr* a, const double* f, double* y) {
   }
 }
 
-/* z = (LU)^{-1} r with the ILU(0) factors stored on the pattern of A */
+/* z = (LU)^{-1} r with the ILU(k) factors (for k = 0 on the pattern of A) */
 static void ilu_apply(const or_hier* h, const double* r, double* z) {
-  const or_csr* a = &h->A[0];
-  const double* lu = h->lu;
+  const or_csr* a = &h->F;
+  const double* lu = h->F.v;
   int n = a->n;
   /* L y = r (unit lower) */
   for (int i = 0; i < n; ++i) {
@@ -1016,6 +1137,14 @@ void or_get_p(const or_hier* h, int d, int* rp, int* ci, double* v) {
 }
 void or_get_cf(const or_hier* h, int d, int* cf) { memcpy(cf, h->cf[d], sizeof(int) * (size_t)h->A[d].n); }
 void or_get_ilu(const or_hier* h, double* lu) { memcpy(lu, h->lu, sizeof(double) * (size_t)h->A[0].rp[h->A[0].n]); }
+long or_ilu_nnz(const or_hier* h) { return h->F.rp[h->F.n]; }
+void or_get_ilu_factor(const or_hier* h, int* rp, int* ci, double* v, int* lev) {
+  long nnz = h->F.rp[h->F.n];
+  memcpy(rp, h->F.rp, sizeof(int) * ((size_t)h->F.n + 1));
+  memcpy(ci, h->F.ci, sizeof(int) * (size_t)nnz);
+  memcpy(v, h->F.v, sizeof(double) * (size_t)nnz);
+  memcpy(lev, h->flev, sizeof(int) * (size_t)nnz);
+}
 void or_get_chol(const or_hier* h, double* g) { memcpy(g, h->chol, sizeof(double) * (size_t)h->n0 * (size_t)h->n0); }
 
 /* standalone pieces for pins */

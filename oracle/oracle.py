@@ -32,7 +32,7 @@ _lib = None
 class _Opts(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("max_coarse", ctypes.c_int),
                 ("max_levels", ctypes.c_int), ("check_symmetry", ctypes.c_int),
-                ("s_scale", ctypes.c_double), ("b_scale", ctypes.c_double)]
+                ("s_scale", ctypes.c_double), ("b_scale", ctypes.c_double), ("ilu_k", ctypes.c_int)]
 
 
 def build_oracle(force: bool = False) -> Path:
@@ -72,6 +72,9 @@ def _load():
     lib.or_get_p.argtypes = [P, I, P, P, P]
     lib.or_get_cf.argtypes = [P, I, P]
     lib.or_get_ilu.argtypes = [P, P]
+    lib.or_ilu_nnz.argtypes = [P]
+    lib.or_ilu_nnz.restype = ctypes.c_long
+    lib.or_get_ilu_factor.argtypes = [P, P, P, P, P]
     lib.or_get_chol.argtypes = [P, P]
     _lib = lib
     return lib
@@ -116,13 +119,13 @@ class Hierarchy:
     """SETUP of the oracle: ILU(0) factors + classical AMG hierarchy."""
 
     def __init__(self, n, row_ptr, col, val, theta=0.25, max_coarse=256, max_levels=25,
-                 check_symmetry=True, s_scale=1.0, b_scale=1.0):
+                 check_symmetry=True, s_scale=1.0, b_scale=1.0, ilu_k=0):
         lib = _load()
         self._lib = lib
         self.n = int(n)
         rp, ci, v = _csr_args(row_ptr, col, val)
         o = _Opts(float(theta), int(max_coarse), int(max_levels), int(bool(check_symmetry)),
-                  float(s_scale), float(b_scale))
+                  float(s_scale), float(b_scale), int(ilu_k))
         st = ctypes.c_int(0)
         self._h = lib.or_setup(self.n, _ptr(rp), _ptr(ci), _ptr(v), ctypes.byref(o), ctypes.byref(st))
         self.status = st.value
@@ -168,6 +171,17 @@ class Hierarchy:
         out = np.empty(nnz, np.float64)
         self._lib.or_get_ilu(self._h, _ptr(out))
         return out
+
+    def ilu_factor(self):
+        """The ILU(k) factor B applies: (row_ptr, col, values, level of fill); L strictly
+        lower with unit diagonal implied, U on and above the diagonal."""
+        nnz = self._lib.or_ilu_nnz(self._h)
+        rp = np.empty(self.n + 1, np.int32)
+        ci = np.empty(nnz, np.int32)
+        v = np.empty(nnz, np.float64)
+        lev = np.empty(nnz, np.int32)
+        self._lib.or_get_ilu_factor(self._h, _ptr(rp), _ptr(ci), _ptr(v), _ptr(lev))
+        return rp, ci, v, lev
 
     def coarse_cholesky(self):
         n0 = self._lib.or_level_n(self._h, self.nlev - 1)

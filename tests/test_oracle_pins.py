@@ -151,6 +151,91 @@ def test_ilu0_defining_property(dims, seed):
     assert np.max(np.abs(U - np.diag(np.diag(U)) @ L.T)) <= 1e-12 * np.max(np.abs(U))
 
 
+def _ilu1_fill_closed_form(nx, ny, nz):
+    """Level-1 fill of ILU on the natural-order 5/7-point grid pattern, from grid
+    coordinates: the pivot m = i - e_a (an earlier neighbour of i) carries its later
+    neighbour j = m + e_b (b != a) into row i, so (i, i - e_a + e_b) has level 1
+    (and (j, i) by symmetry of the argument)."""
+    dims = [nx, ny, nz]
+    strides = [1, nx, nx * ny]
+    fill = set()
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                c = [x, y, z]
+                i = x + nx * (y + ny * z)
+                for a in range(3):
+                    if c[a] < 1:
+                        continue
+                    for b in range(3):
+                        if b == a or c[b] + 1 >= dims[b]:
+                            continue
+                        j = i - strides[a] + strides[b]
+                        fill.add((i, j))
+                        fill.add((j, i))
+    return fill
+
+
+@pytest.mark.parametrize("dims", [(7, 6, 1), (5, 4, 3)])
+def test_iluk_level1_pattern_closed_form(dims):
+    """ILU(1) (Algorithm 3.1, k = 1) keeps the pattern of A plus exactly the level-1
+    fill of the grid stencil, derived above from coordinates; every entry's level is
+    0 on the pattern of A and 1 on the fill."""
+    n, rp, ci, v, A = tiny_problem(*dims, 31, sigma=1.0)
+    h = oracle.Hierarchy(n, rp, ci, v, ilu_k=1)
+    frp, fci, fv, lev = h.ilu_factor()
+    got = {(i, int(j)): int(l) for i in range(n) for j, l in zip(fci[frp[i]:frp[i + 1]], lev[frp[i]:frp[i + 1]])}
+    base = {(i, int(j)) for i in range(n) for j in ci[rp[i]:rp[i + 1]]}
+    fill = _ilu1_fill_closed_form(*dims)
+    assert set(got) == base | fill
+    assert all(got[e] == 0 for e in base) and all(got[e] == 1 for e in fill - base)
+
+
+def test_iluk_k0_is_ilu0_bitwise():
+    """k = 0 keeps the pattern of A and reproduces ILU(0) bit for bit."""
+    n, rp, ci, v, A = tiny_problem(6, 5, 3, 33, sigma=1.5)
+    h = oracle.Hierarchy(n, rp, ci, v, ilu_k=0)
+    frp, fci, fv, lev = h.ilu_factor()
+    lu, st = oracle.ilu0(n, rp, ci, v)
+    assert np.array_equal(frp, rp) and np.array_equal(fci, ci) and np.array_equal(fv, lu)
+    assert not lev.any()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_iluk_defining_property(k):
+    """R = A - LU vanishes on the kept pattern (the ILU(k) condition of Section 3.1)."""
+    n, rp, ci, v, A = tiny_problem(6, 5, 3, 34 + k, sigma=1.5)
+    h = oracle.Hierarchy(n, rp, ci, v, ilu_k=k)
+    frp, fci, fv, lev = h.ilu_factor()
+    F = gen.csr_to_dense(n, frp, fci, fv)
+    LU = (np.tril(F, -1) + np.eye(n)) @ np.triu(F)
+    rows = np.repeat(np.arange(n), np.diff(frp))
+    assert np.max(np.abs((LU - A)[rows, fci])) <= 1e-14 * np.max(np.abs(A))
+    assert lev.max() <= k
+
+
+def test_iluk_with_all_fill_is_exact_lu():
+    """With k at least the largest level that occurs nothing is dropped: the factor
+    is the exact LU (LAPACK, no row exchanges for this SPD M-matrix)."""
+    n, rp, ci, v, A = tiny_problem(7, 6, 1, 36, sigma=1.0)
+    h = oracle.Hierarchy(n, rp, ci, v, ilu_k=n)
+    frp, fci, fv, lev = h.ilu_factor()
+    F = gen.csr_to_dense(n, frp, fci, fv)
+    P, L, U = sla.lu(A)
+    assert np.array_equal(P, np.eye(n))
+    assert np.max(np.abs(np.tril(F, -1) + np.eye(n) - L)) <= 1e-14
+    assert np.max(np.abs(np.triu(F) - U)) <= 1e-14 * np.max(np.abs(U))
+
+
+def test_iluk_combined_is_spd():
+    """Theorem 2.1 with B = ILU(1): B_co stays symmetric positive definite."""
+    n, rp, ci, v, A = tiny_problem(6, 6, 2, 37, sigma=2.0)
+    h = oracle.Hierarchy(n, rp, ci, v, max_coarse=8, ilu_k=1)
+    Bco = h.dense_operator(oracle.PREC_COMBINED)
+    assert np.max(np.abs(Bco - Bco.T)) <= 1e-12 * np.max(np.abs(Bco))
+    assert np.linalg.eigvalsh(0.5 * (Bco + Bco.T)).min() > 0
+
+
 def test_ilu0_reports_nonpositive_pivot():
     A = np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 0.5], [0.0, 0.5, 1.0]])  # indefinite
     n, rp, ci, v = dense_to_csr(A)
