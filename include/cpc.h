@@ -100,6 +100,9 @@ typedef struct {
   int32_t tune;           /* 1: pick each level's smoother form and sweep block size by timing
                              candidates at setup (default); 0: fixed rules (faster setup)   */
   int32_t verbose;        /* 1: one progress line per setup phase on stderr                 */
+  int32_t ilu_fill;       /* level of fill k of the ILU factorisation used as B (Algorithm
+                             3.1; 0 = ILU(0), the paper's choice; at most 16; single
+                             systems only, cpc_setup_batch rejects k > 0)                  */
   double theta;           /* strength threshold of the classical coarsening (0.25)          */
 } cpc_options;
 
@@ -173,8 +176,16 @@ cpc_status cpc_get_prolongation(cpc_handle h, int32_t level, int64_t* p_nnz, int
                                 double* val, int32_t* cf);
 
 /* Copy the ILU(0) values (on the pattern of the finest A; strictly lower = L with a
- * unit diagonal implied, diagonal and upper = U) to a host array of nnz entries. */
+ * unit diagonal implied, diagonal and upper = U) to a host array of nnz entries.
+ * CPC_E_ARG for a handle set up with ilu_fill > 0 (use cpc_get_ilu_factor). */
 cpc_status cpc_get_ilu(cpc_handle h, double* lu);
+
+/* The ILU(k) factor the handle applies as B (k = options.ilu_fill; Algorithm 3.1):
+ * *nnz = its number of entries; then, for non-null arrays, its row pointers
+ * (n + 1), columns (sorted within rows) and values (strictly lower = L with a unit
+ * diagonal implied, diagonal and upper = U), host arrays the caller owns. For k = 0
+ * the pattern is that of the finest A. */
+cpc_status cpc_get_ilu_factor(cpc_handle h, int64_t* nnz, int32_t* row_ptr, int32_t* col_idx, double* val);
 
 /* Statistics of the handle (setup time, last solve). */
 cpc_status cpc_get_stats(cpc_handle h, cpc_stats* st);

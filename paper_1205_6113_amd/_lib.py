@@ -25,7 +25,7 @@ EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "c
            "cpc_hierarchy_info", "cpc_get_level", "cpc_get_prolongation", "cpc_get_ilu", "cpc_get_stats",
            "cpc_neg_outer_on_pattern", "cpc_time_kernel", "cpc_destroy", "cpc_last_error", "cpc_tpfa_pattern",
            "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values", "cpc_setup_batch",
-           "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind")
+           "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind", "cpc_get_ilu_factor")
 KERNEL = {"spmv_pq": 0, "fgs": 1, "bgs": 2, "ilu_l": 3, "ilu_u": 4, "residual": 5, "restrict": 6, "prolong": 7,
           "vcycle": 8, "precond": 9, "iteration": 10, "dense_gemv": 11}
 
@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
                 ("check_symmetry", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("rap_on_gpu", ctypes.c_int32), ("sweep_block_rows", ctypes.c_int32),
                 ("sweep_threads", ctypes.c_int32), ("dense_smoother", ctypes.c_int32),
-                ("tune", ctypes.c_int32), ("verbose", ctypes.c_int32), ("theta", ctypes.c_double)]
+                ("tune", ctypes.c_int32), ("verbose", ctypes.c_int32), ("ilu_fill", ctypes.c_int32),
+                ("theta", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -87,6 +88,8 @@ def load():
     lib.cpc_get_prolongation.restype = I32
     lib.cpc_get_ilu.argtypes = [P, P]
     lib.cpc_get_ilu.restype = I32
+    lib.cpc_get_ilu_factor.argtypes = [P, ctypes.POINTER(ctypes.c_int64), P, P, P]
+    lib.cpc_get_ilu_factor.restype = I32
     lib.cpc_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
     lib.cpc_get_stats.restype = I32
     lib.cpc_neg_outer_on_pattern.argtypes = [P, P, P, P]

@@ -28,6 +28,21 @@ int cpch_ilu0(int n, const int* rp, const int* ci, const double* v, double* lu) 
   return st;
 }
 
+// ILU(k): call with f_rp only to get nnz (returned, or -status), then with all arrays.
+long cpch_iluk(int n, const int* rp, const int* ci, const double* v, int k, int* f_rp, int* f_ci, double* f_v,
+               int* f_lev) {
+  HostCsr a = make_csr(n, rp, ci, v);
+  HostCsr f;
+  std::vector<int> lev;
+  int st = cpc::iluk_factor(a, k, f, lev, nullptr);
+  if (st) return -st;
+  if (f_rp) std::memcpy(f_rp, f.rp.data(), sizeof(int) * (n + 1));
+  if (f_ci) std::memcpy(f_ci, f.ci.data(), sizeof(int) * f.ci.size());
+  if (f_v) std::memcpy(f_v, f.v.data(), sizeof(double) * f.v.size());
+  if (f_lev) std::memcpy(f_lev, lev.data(), sizeof(int) * lev.size());
+  return (long)f.ci.size();
+}
+
 int cpch_rs_coarsen(int n, const int* rp, const int* ci, const double* v, double theta, int* cf) {
   HostCsr a = make_csr(n, rp, ci, v);
   std::vector<int> c;

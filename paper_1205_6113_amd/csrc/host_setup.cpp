@@ -6,6 +6,7 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -80,6 +81,79 @@ int ilu0_factor(const HostCsr& a, std::vector<double>& lu, std::string* msg) {
     for (int p = b; p < e; ++p) where[a.ci[p]] = -1;
     if (!(lu[dpos[i]] > 0.0)) {
       if (msg) *msg = "ILU(0) pivot not positive at row " + std::to_string(i);
+      return CPC_E_NOT_SPD;
+    }
+  }
+  return CPC_OK;
+}
+
+int iluk_factor(const HostCsr& a, int k, HostCsr& f, std::vector<int>& lev, std::string* msg) {
+  // Row i: values and levels in dense arrays over the columns touched so far; the
+  // pivots still to visit (columns below i) in a min-heap, so that they are taken in
+  // increasing order even as eliminations add new ones. A pivot m whose level exceeds
+  // k is passed over; entry (i, j) of row m of the factor updates (i, j) as
+  // w_j - w_m u_mj (a new entry enters as 0), with level min(lev_j, lev_m + lev_mj + 1).
+  // Entries above level k are dropped when the row is done.
+  constexpr int kInf = 1 << 28;
+  const int n = a.n;
+  f = HostCsr{};
+  f.n = n;
+  f.ncols = n;
+  f.rp.assign(n + 1, 0);
+  f.ci.reserve(a.ci.size() + n);
+  f.v.reserve(a.ci.size() + n);
+  lev.clear();
+  lev.reserve(a.ci.size() + n);
+  std::vector<double> w(n, 0.0);
+  std::vector<int> lv(n, -1), dpos(n, -1), touched;
+  std::vector<int> heap;
+  auto later = std::greater<int>();
+  for (int i = 0; i < n; ++i) {
+    touched.clear();
+    heap.clear();
+    for (int p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+      const int j = a.ci[p];
+      w[j] = a.v[p];
+      lv[j] = 0;
+      touched.push_back(j);
+      if (j < i) heap.push_back(j);
+    }
+    std::make_heap(heap.begin(), heap.end(), later);
+    while (!heap.empty()) {
+      std::pop_heap(heap.begin(), heap.end(), later);
+      const int m = heap.back();
+      heap.pop_back();
+      if (lv[m] > k) continue;
+      w[m] = w[m] / f.v[dpos[m]];
+      for (int q = dpos[m] + 1; q < f.rp[m + 1]; ++q) {
+        const int j = f.ci[q];
+        if (lv[j] < 0) {
+          w[j] = 0.0;
+          lv[j] = kInf;
+          touched.push_back(j);
+          if (j < i) {
+            heap.push_back(j);
+            std::push_heap(heap.begin(), heap.end(), later);
+          }
+        }
+        w[j] = w[j] - w[m] * f.v[q];
+        const int l = lv[m] + lev[q] + 1;
+        if (l < lv[j]) lv[j] = l;
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int j : touched) {
+      if (lv[j] <= k) {
+        if (j == i) dpos[i] = (int)f.ci.size();
+        f.ci.push_back(j);
+        f.v.push_back(w[j]);
+        lev.push_back(lv[j]);
+      }
+      lv[j] = -1;
+    }
+    f.rp[i + 1] = (int)f.ci.size();
+    if (dpos[i] < 0 || !(f.v[dpos[i]] > 0.0)) {
+      if (msg) *msg = "ILU(" + std::to_string(k) + ") pivot not positive at row " + std::to_string(i);
       return CPC_E_NOT_SPD;
     }
   }

@@ -26,6 +26,12 @@ int validate_csr(int n, const int32_t* rp, const int32_t* ci, const double* v, b
 // strictly lower part = L (unit diagonal implied), rest = U. Returns cpc_status.
 int ilu0_factor(const HostCsr& a, std::vector<double>& lu, std::string* msg);
 
+// ILU(k) by levels of fill (Algorithm 3.1): f holds the kept pattern (sorted rows) with
+// L strictly lower (unit diagonal implied) and U on and above the diagonal; lev the
+// level of fill of each kept entry. k = 0 gives the pattern of a and ilu0_factor's
+// values. CPC_E_NOT_SPD on a pivot <= 0.
+int iluk_factor(const HostCsr& a, int k, HostCsr& f, std::vector<int>& lev, std::string* msg);
+
 // Classical C/F splitting (1 = C, 0 = F). Returns the number of C points.
 int rs_coarsen(const HostCsr& a, double theta, std::vector<int>& cf);
 

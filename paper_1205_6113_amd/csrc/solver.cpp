@@ -152,6 +152,12 @@ struct cpc_solver {
   bool f32 = false;  // preconditioner precision
   std::vector<cpc::Level> lev;
   std::vector<double> lu_host;
+  // ILU(k) with k > 0 (options.ilu_fill): its own factor, sweep schedules and packs
+  bool iluk = false;
+  cpc::HostCsr iluF;
+  std::vector<int> iluF_lev;
+  cpc::DevSweepSched ilu_lower, ilu_upper;
+  double ilu_lnnz = 0.0, ilu_unnz = 0.0;  // entries of the applied factor below / on and above the diagonal
   double* lu = nullptr;
   float* lu32 = nullptr;
   cpc::SweepPackDev ilu_l{}, ilu_u{};  // ILU(0) L (lower entries of LU) and U (upper entries, diagonal)
@@ -743,7 +749,7 @@ static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int 
     SweepSchedule up = make_sweep(h, sub, false, R, L.upper);
     L.fgs = build_pack(h, sub, sub.v, lo, nullptr);
     L.bgs = build_pack(h, sub, sub.v, up, nullptr);
-    if (ilu) {
+    if (ilu && !h->iluk) {
       h->ilu_l = build_pack(h, sub, h->lu_host, lo, &L.fgs);
       h->ilu_u = build_pack(h, sub, h->lu_host, up, &L.bgs);
     }
@@ -754,6 +760,28 @@ static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int 
   h->cur_owned = prev;
   L.sweep_R = R;
 }
+
+// Schedules and packs of an ILU(k) factor with k > 0 (its pattern is not that of A, so
+// the triangular solves of B get their own), rows per block R; built once after the
+// level-0 sweeps are settled.
+static void build_iluk_sweeps(cpc_solver* h, int R) {
+  std::vector<void*>* prev = h->cur_owned;
+  h->cur_owned = &h->owned;
+  try {
+    SweepSchedule lo = make_sweep(h, h->iluF, true, R, h->ilu_lower);
+    SweepSchedule up = make_sweep(h, h->iluF, false, R, h->ilu_upper);
+    h->ilu_l = build_pack(h, h->iluF, h->iluF.v, lo, nullptr);
+    h->ilu_u = build_pack(h, h->iluF, h->iluF.v, up, nullptr);
+  } catch (...) {
+    h->cur_owned = prev;
+    throw;
+  }
+  h->cur_owned = prev;
+}
+
+// The schedules the ILU triangular solves run on.
+static const DevSweepSched& ilu_lower_sched(const cpc_solver* h) { return h->iluk ? h->ilu_lower : h->lev[0].lower; }
+static const DevSweepSched& ilu_upper_sched(const cpc_solver* h) { return h->iluk ? h->ilu_upper : h->lev[0].upper; }
 
 // Block-dense form of a level's Gauss-Seidel factor T = D + L with blocks of B rows:
 // the forward solve is, block by block, g_b = f_b - (T entries left of the block) x,
@@ -943,7 +971,7 @@ static void tune_sweeps(cpc_solver* h) {
           run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
           run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
         }
-        if (ilu) {
+        if (ilu && !h->iluk) {
           run_sweep(h, SWEEP_UNIT_LOWER, L.lower, h->ilu_l, h->res, h->y, nullptr, nullptr, nullptr);
           run_sweep(h, SWEEP_UPPER_OUT, L.upper, h->ilu_u, h->y, h->w, h->u1, h->u2, nullptr);
         }
@@ -1294,9 +1322,8 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
 
 // z = (LU)^{-1} f (out = nullptr) or out = base + (LU)^{-1} f
 static void ilu_apply(cpc_solver* h, const void* f, void* w, const void* base, void* out, const int* done) {
-  Level& L = h->lev[0];
-  run_sweep(h, SWEEP_UNIT_LOWER, L.lower, h->ilu_l, f, h->y, nullptr, nullptr, done);
-  run_sweep(h, out ? SWEEP_UPPER_OUT : SWEEP_UPPER, L.upper, h->ilu_u, h->y, w, base, out, done);
+  run_sweep(h, SWEEP_UNIT_LOWER, ilu_lower_sched(h), h->ilu_l, f, h->y, nullptr, nullptr, done);
+  run_sweep(h, out ? SWEEP_UPPER_OUT : SWEEP_UPPER, ilu_upper_sched(h), h->ilu_u, h->y, w, base, out, done);
 }
 
 // The V-cycle of the AMG(ILU(0)) comparator (Section 5): Algorithm 3.2 with ILU(0) as
@@ -1536,7 +1563,8 @@ static double prec_bytes(const cpc_solver* h, int prec) {
   const double mb = h->f32 ? 8.0 : 12.0;
   const double nz = (double)h->lev[0].A.nnz, n = h->n;
   const double half = 0.5 * (nz - n);
-  const double ilu = (half * mb + 4.0 * n + 2.0 * vb * n) + ((half + n) * mb + 4.0 * n + 4.0 * vb * n) +
+  const double ilo = h->iluk ? h->ilu_lnnz : half, iup = h->iluk ? h->ilu_unnz : half + n;
+  const double ilu = (ilo * mb + 4.0 * n + 2.0 * vb * n) + (iup * mb + 4.0 * n + 4.0 * vb * n) +
                      2.0 * vb * n;  // L and U solves, marker fills
   const double outer = nz * 12.0 + 4.0 * n + 8.0 * n + 2.0 * vb * n;
   const double V = vcycle_bytes(h);
@@ -1794,6 +1822,7 @@ void cpc_default_options(cpc_options* o) {
   o->dense_smoother = 0;
   o->tune = 1;
   o->verbose = 0;
+  o->ilu_fill = 0;
   o->theta = 0.25;
 }
 
@@ -1812,6 +1841,7 @@ static cpc_status read_options(const cpc_options* opt, cpc_options& o) {
   if (o.sweep_threads != 0 && o.sweep_threads != 64 && o.sweep_threads != 256)
     return set_err(CPC_E_ARG, "sweep_threads must be 0, 64 or 256");
   if (o.dense_smoother < 0 || o.dense_smoother > 3) return set_err(CPC_E_ARG, "dense_smoother must be 0, 1, 2 or 3");
+  if (o.ilu_fill < 0 || o.ilu_fill > 16) return set_err(CPC_E_ARG, "ilu_fill must lie in [0, 16]");
   return CPC_OK;
 }
 
@@ -1844,6 +1874,13 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
     }
     int st = ilu0_factor(sys[0].A[0], sys[0].lu, &msg);
     if (st != CPC_OK) return set_err((cpc_status)st, msg);
+    if (o.ilu_fill > 0) {
+      st = iluk_factor(sys[0].A[0], o.ilu_fill, h->iluF, h->iluF_lev, &msg);
+      if (st != CPC_OK) return set_err((cpc_status)st, msg);
+      h->iluk = true;
+      for (int i = 0; i < n; ++i)
+        for (int q = h->iluF.rp[i]; q < h->iluF.rp[i + 1]; ++q) (h->iluF.ci[q] < i ? h->ilu_lnnz : h->ilu_unnz) += 1.0;
+    }
     if (hip_stream) {
       h->stream = (hipStream_t)hip_stream;
     } else {
@@ -1861,6 +1898,10 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
     progress(h.get(), "levels assembled; choosing smoother forms");
     tune_dense(h.get());
     tune_sweeps(h.get());
+    if (h->iluk) {
+      progress(h.get(), "ILU(" + std::to_string(o.ilu_fill) + ") sweeps");
+      build_iluk_sweeps(h.get(), h->lev[0].sweep_R > 0 ? h->lev[0].sweep_R : choose_block_rows(n));
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError& e) {
@@ -1890,6 +1931,7 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
     total += n[s];
   }
   if (total > 2147483647LL) return set_err(CPC_E_ARG, "batch exceeds 2^31 rows");
+  if (o.ilu_fill > 0) return set_err(CPC_E_ARG, "ilu_fill > 0 is offered for single systems only");
   auto h = std::make_unique<cpc_solver>();
   h->opt = o;
   h->batch = true;
@@ -2055,7 +2097,22 @@ cpc_status cpc_get_prolongation(cpc_handle h, int32_t level, int64_t* p_nnz, int
 
 cpc_status cpc_get_ilu(cpc_handle h, double* lu) {
   if (!h || !lu) return set_err(CPC_E_ARG, "null argument");
+  if (h->iluk) return set_err(CPC_E_ARG, "the handle applies ILU(k), k > 0: use cpc_get_ilu_factor");
   std::memcpy(lu, h->lu_host.data(), sizeof(double) * h->lu_host.size());
+  return CPC_OK;
+}
+
+cpc_status cpc_get_ilu_factor(cpc_handle h, int64_t* nnz, int32_t* row_ptr, int32_t* col_idx, double* val) {
+  if (!h || !nnz) return set_err(CPC_E_ARG, "null argument");
+  if (h->batch) return set_err(CPC_E_ARG, "batch handle");
+  const HostCsr& A = h->lev[0].A_host;
+  const std::vector<int>& rp = h->iluk ? h->iluF.rp : A.rp;
+  const std::vector<int>& ci = h->iluk ? h->iluF.ci : A.ci;
+  const std::vector<double>& v = h->iluk ? h->iluF.v : h->lu_host;
+  *nnz = (int64_t)ci.size();
+  if (row_ptr) std::memcpy(row_ptr, rp.data(), sizeof(int) * rp.size());
+  if (col_idx) std::memcpy(col_idx, ci.data(), sizeof(int) * ci.size());
+  if (val) std::memcpy(val, v.data(), sizeof(double) * v.size());
   return CPC_OK;
 }
 
@@ -2164,17 +2221,17 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         ev_end();
         break;
       case CPC_K_ILU_L:
-        launch_fill_sentinel(h->stream, L.lower.d.n, h->y, f32, nullptr);
+        launch_fill_sentinel(h->stream, ilu_lower_sched(h).d.n, h->y, f32, nullptr);
         ev_begin();
-        launch_sweep_packed(h->stream, SWEEP_UNIT_LOWER, L.lower.d, h->ilu_l, f32, h->res, h->y, nullptr, nullptr,
-                            h->sync, nullptr, h->spin_limit);
+        launch_sweep_packed(h->stream, SWEEP_UNIT_LOWER, ilu_lower_sched(h).d, h->ilu_l, f32, h->res, h->y, nullptr,
+                            nullptr, h->sync, nullptr, h->spin_limit);
         ev_end();
         break;
       case CPC_K_ILU_U:
-        launch_fill_sentinel(h->stream, L.upper.d.n, h->w, f32, nullptr);
+        launch_fill_sentinel(h->stream, ilu_upper_sched(h).d.n, h->w, f32, nullptr);
         ev_begin();
-        launch_sweep_packed(h->stream, SWEEP_UPPER_OUT, L.upper.d, h->ilu_u, f32, h->y, h->w, h->u1, h->u2,
-                            h->sync, nullptr, h->spin_limit);
+        launch_sweep_packed(h->stream, SWEEP_UPPER_OUT, ilu_upper_sched(h).d, h->ilu_u, f32, h->y, h->w, h->u1,
+                            h->u2, h->sync, nullptr, h->spin_limit);
         ev_end();
         break;
       case CPC_K_RESIDUAL:

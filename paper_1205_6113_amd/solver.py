@@ -35,7 +35,7 @@ def _dev_vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
 
 def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, theta=0.25, swap_roles=False,
             check_symmetry=True, use_graph=True, check_every=4, sweep_block_rows=0,
-            sweep_threads=0, dense_smoother=0, tune=True, verbose=False) -> _lib.Options:
+            sweep_threads=0, dense_smoother=0, tune=True, verbose=False, ilu_fill=0) -> _lib.Options:
     lib = load()
     o = _lib.Options()
     lib.cpc_default_options(ctypes.byref(o))
@@ -52,6 +52,7 @@ def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, th
     o.sweep_threads = int(sweep_threads)
     o.tune = int(bool(tune))
     o.verbose = int(bool(verbose))
+    o.ilu_fill = int(ilu_fill)
     o.dense_smoother = _lib.DENSE[dense_smoother] if isinstance(dense_smoother, str) else int(dense_smoother)
     return o
 
@@ -190,6 +191,17 @@ class Solver:
         out = np.empty(self.nnz, np.float64)
         check(self._lib.cpc_get_ilu(self._h, _ptr(out)))
         return out
+
+    def ilu_factor(self):
+        """The ILU(k) factor applied as B: (row_ptr, col, values), L strictly lower with a
+        unit diagonal implied, U on and above the diagonal."""
+        nnz = ctypes.c_int64(0)
+        check(self._lib.cpc_get_ilu_factor(self._h, ctypes.byref(nnz), None, None, None))
+        rp = np.empty(self.n + 1, np.int32)
+        ci = np.empty(nnz.value, np.int32)
+        v = np.empty(nnz.value, np.float64)
+        check(self._lib.cpc_get_ilu_factor(self._h, ctypes.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v)))
+        return rp, ci, v
 
     def time_kernel(self, kernel: str | int, level: int = -1, reps: int = 10) -> dict:
         """HIP-event timing of one kernel family (see cpc_time_kernel)."""

@@ -22,6 +22,8 @@ def lib():
         L = ctypes.CDLL(str(HOST_LIB))
         P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.cpch_ilu0.argtypes = [I, P, P, P, P]
+        L.cpch_iluk.argtypes = [I, P, P, P, I, P, P, P, P]
+        L.cpch_iluk.restype = ctypes.c_long
         L.cpch_rs_coarsen.argtypes = [I, P, P, P, D, P]
         L.cpch_rs_interp.argtypes = [I, P, P, P, D, P, P, P, P]
         L.cpch_rs_interp.restype = ctypes.c_long
@@ -41,6 +43,19 @@ def ilu0(n, rp, ci, v):
     lu = np.empty_like(v)
     st = lib().cpch_ilu0(n, _p(rp), _p(ci), _p(v), _p(lu))
     return lu, st
+
+
+def iluk(n, rp, ci, v, k):
+    rp, ci, v = _csr(rp, ci, v)
+    nnz = lib().cpch_iluk(n, _p(rp), _p(ci), _p(v), int(k), None, None, None, None)
+    if nnz < 0:
+        return None, int(-nnz)
+    frp = np.empty(n + 1, np.int32)
+    fci = np.empty(nnz, np.int32)
+    fv = np.empty(nnz, np.float64)
+    lev = np.empty(nnz, np.int32)
+    lib().cpch_iluk(n, _p(rp), _p(ci), _p(v), int(k), _p(frp), _p(fci), _p(fv), _p(lev))
+    return (frp, fci, fv, lev), 0
 
 
 def rs_coarsen(n, rp, ci, v, theta=0.25):

@@ -42,6 +42,20 @@ def test_ilu0_bitwise(hiers):
         assert np.array_equal(lu, h.ilu()), k
 
 
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_iluk_bitwise(k):
+    """ILU(k) of the library (heap-ordered pivots) and of the oracle (linked row list):
+    same pattern, levels and values bit for bit."""
+    for name in ("c1", "c2s"):
+        p = problems()[name]
+        h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val, ilu_k=k)
+        got, st = host_lib.iluk(p.n, p.row_ptr, p.col, p.val, k)
+        assert st == 0
+        ref = h.ilu_factor()
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), (name, k)
+
+
 def test_coarsening_and_interpolation_bitwise(hiers):
     """C/F splitting and P identical to the oracle on every level of the oracle's
     hierarchy (the library's splitting of the oracle's A_l)."""
