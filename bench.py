@@ -198,6 +198,46 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_table(args):
+    """The comparison of Table 5.2 on a synthetic workload: iterations and solve time of
+    PCG with each preconditioner (one handle for the ILU(0)-based ones, one with ILU(1)
+    as B), setup time per handle. Prints one JSON line of its own."""
+    import torch
+    import paper_1205_6113_amd as cpc
+    p, desc = workload(args.workload)
+    dev = torch.device("cuda:0")
+    b = torch.as_tensor(p.b, device=dev)
+    rows = []
+    for fill, entries in ((0, [("ILU(0)", "ilu"), ("AMG(GS)", "amg"), ("AMG(ILU(0))", "amg_ilu"),
+                               ("additive B^", "additive"), ("B_co (multiplicative)", "combined"),
+                               ("wrong-order B-bar", "bbar")]),
+                          (1, [("ILU(1)", "ilu"), ("B_co with ILU(1)", "combined")])):
+        t0 = time.perf_counter()
+        s = cpc.Solver(p.n, p.row_ptr, p.col, p.val, device=dev, precision=args.precision,
+                       tune=not args.rules, ilu_fill=fill)
+        setup_s = time.perf_counter() - t0
+        log(f"handle with ILU({fill}): setup {setup_s:.2f}s")
+        for name, prec in entries:
+            x, it, rel, st = s.solve(b, tol=p.tol, maxit=10000, prec=prec)
+            times = []
+            for _ in range(max(1, args.steps)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, it, rel, st = s.solve(b, tol=p.tol, maxit=10000, prec=prec)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            times.sort()
+            ms = 1000.0 * times[len(times) // 2]
+            rows.append({"preconditioner": name, "ilu_fill": fill, "iters": it, "status": st, "relres": rel,
+                         "solve_ms": round(ms, 3), "setup_s": round(setup_s, 3)})
+            log(f"{name}: {it} iterations, status {st}, {ms:.2f} ms")
+        s.close()
+    out = {"metric": "Table 5.2 analogue: PCG iterations and solve time per preconditioner",
+           "unit": "ms", "n_gpus": 1, "data": "synthetic", "dtype": "f64" if args.precision == "fp64" else
+           "f64-pcg/f32-precond", "config": {"workload": desc, "n": p.n, "nnz": p.nnz, "tol": p.tol}, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +254,8 @@ def main():
                          "calibrating memory counters)")
     ap.add_argument("--rules", action="store_true", help="rule-based setup instead of the timing tuner")
     ap.add_argument("--verbose", action="store_true", help="print setup progress")
+    ap.add_argument("--table", action="store_true",
+                    help="instead of the benchmark line, the Table 5.2 comparison of preconditioners")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is "
@@ -224,6 +266,8 @@ def main():
     import torch
     import paper_1205_6113_amd as cpc
 
+    if args.table:
+        return bench_table(args)
     if args.workload == "c4":
         return bench_batch(args)
     if args.workload == "c5":
