@@ -150,3 +150,31 @@ def test_setup_rejects_bad_input_on_host():
     st, msg = cpc.setup_status(3, np.array([0, 2, 5, 7]), np.array([0, 1, 0, 1, 2, 1, 2]),
                                np.array([1, 2, 2, 1, .5, .5, 1.]))
     assert st == _lib.CPC_E_NOT_SPD and "ILU" in msg
+
+
+def test_option_and_ilu_fill_errors_on_host():
+    """Options out of range are rejected before any GPU call; ILU(k) pivot failures are
+    reported as for ILU(0); a batch asks for ILU(0) only."""
+    import ctypes
+    import paper_1205_6113_amd as cpc
+    from paper_1205_6113_amd import _lib
+    p = gen.config1(6, 5)
+    assert cpc.setup_status(p.n, p.row_ptr, p.col, p.val, ilu_fill=17)[0] == _lib.CPC_E_ARG
+    assert cpc.setup_status(p.n, p.row_ptr, p.col, p.val, ilu_fill=-1)[0] == _lib.CPC_E_ARG
+    assert cpc.setup_status(p.n, p.row_ptr, p.col, p.val, prec=7)[0] == _lib.CPC_E_ARG
+    st, msg = cpc.setup_status(3, np.array([0, 2, 5, 7]), np.array([0, 1, 0, 1, 2, 1, 2]),
+                               np.array([1, 2, 2, 1, .5, .5, 1.]), ilu_fill=1)
+    assert st == _lib.CPC_E_NOT_SPD and "ILU" in msg
+    lib = _lib.load()
+    o = cpc.options(ilu_fill=1)
+    n = (ctypes.c_int32 * 1)(p.n)
+    rp = np.ascontiguousarray(p.row_ptr, np.int32)
+    ci = np.ascontiguousarray(p.col, np.int32)
+    v = np.ascontiguousarray(p.val, np.float64)
+    P = ctypes.c_void_p
+    rps = (P * 1)(rp.ctypes.data)
+    cis = (P * 1)(ci.ctypes.data)
+    vs = (P * 1)(v.ctypes.data)
+    h = ctypes.c_void_p()
+    st = lib.cpc_setup_batch(1, n, rps, cis, vs, ctypes.byref(o), None, ctypes.byref(h))
+    assert st == _lib.CPC_E_ARG and "single systems" in _lib.last_error()
