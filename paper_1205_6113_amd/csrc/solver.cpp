@@ -152,6 +152,7 @@ struct cpc_solver {
   bool f32 = false;  // preconditioner precision
   std::vector<cpc::Level> lev;
   std::vector<double> lu_host;
+  double setup_t0 = 0.0;  // wall clock at the start of setup (progress lines)
   // ILU(k) with k > 0 (options.ilu_fill): its own factor, sweep schedules and packs
   bool iluk = false;
   cpc::HostCsr iluF;
@@ -333,7 +334,7 @@ static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncol
 
 static void progress(const cpc_solver* h, const std::string& what) {
   if (h->opt.verbose) {
-    std::fprintf(stderr, "[cpc setup] %s\n", what.c_str());
+    std::fprintf(stderr, "[cpc setup %7.2f s] %s\n", now_s() - h->setup_t0, what.c_str());
     std::fflush(stderr);
   }
 }
@@ -978,6 +979,7 @@ static void tune_sweeps(cpc_solver* h) {
       });
     };
     const bool try_r = L.sweep_rows <= 2000000 && !(L.dense_smooth && !ilu);
+    progress(h, "level " + std::to_string(d) + ": timing sweep block sizes");
     float best = try_r ? cost() : 0.f;
     for (int R : {1024, 2048, 4096, 8192}) {
       if (!try_r || R == L.sweep_R || R >= L.sweep_rows) continue;
@@ -1050,6 +1052,7 @@ static void tune_sweeps(cpc_solver* h) {
         keep.bd_entries = L.bd_entries;
         L.bdense = false;
         bool better = false;
+        progress(h, "level " + std::to_string(d) + ": block substitution with " + std::to_string(B) + "-row blocks");
         if (build_blockdense(h, L, sub, B)) {
           L.bdense = true;
           L.dense_smooth = false;
@@ -1857,6 +1860,7 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
   if (vs != CPC_OK) return set_err((cpc_status)vs, msg);
   auto h = std::make_unique<cpc_solver>();
   h->opt = o;
+  h->setup_t0 = t0;
   h->n = n;
   h->nnz = row_ptr[n];
   h->f32 = (o.precision == CPC_FP32_PRECOND);
@@ -1934,6 +1938,7 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
   if (o.ilu_fill > 0) return set_err(CPC_E_ARG, "ilu_fill > 0 is offered for single systems only");
   auto h = std::make_unique<cpc_solver>();
   h->opt = o;
+  h->setup_t0 = t0;
   h->batch = true;
   h->nsys = nsys;
   h->f32 = (o.precision == CPC_FP32_PRECOND);
