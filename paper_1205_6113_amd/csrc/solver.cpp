@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -979,10 +980,42 @@ static void tune_sweeps(cpc_solver* h) {
       });
     };
     const bool try_r = L.sweep_rows <= 2000000 && !(L.dense_smooth && !ilu);
-    progress(h, "level " + std::to_string(d) + ": timing sweep block sizes");
-    float best = try_r ? cost() : 0.f;
+    const bool bd_ok = L.sweep_rows > 8192 && d + 1 < h->lev.size() && h->opt.dense_smoother == 0;
+    auto gs_cost = [&] {
+      return time_ms(h, 3, [&] {
+        if (L.bdense) {
+          bdense_solve(h, L, false, f, u, L.r, nullptr);
+          bdense_solve(h, L, true, f, u, L.r, nullptr);
+        } else if (L.dense_smooth) {
+          launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, nullptr);
+          launch_dense_lower_t(h->stream, L.dtri, f32, f32, f, u, nullptr);
+        } else {
+          run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
+          run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
+        }
+      });
+    };
+    // quick look: where block substitution with 4096-row blocks already beats the sweeps
+    // by half, tuning the sweeps' block size cannot change the outcome and is skipped
+    // (the block form stays as the candidate to beat)
+    std::map<int, float> bd_time;  // measured block-substitution candidates
+    bool skip_r = false;
+    if (try_r && bd_ok && !L.dense_smooth && 4096 < L.sweep_rows) {
+      const float ts = gs_cost();
+      progress(h, "level " + std::to_string(d) + ": block substitution with 4096-row blocks");
+      if (build_blockdense(h, L, sub, 4096)) {
+        L.bdense = true;
+        const float tb = gs_cost();
+        bd_time[4096] = tb;
+        if (tb * 1.5f < ts) skip_r = true;
+        else free_blockdense(h, L);
+      }
+    }
+    progress(h, "level " + std::to_string(d) + (skip_r ? ": block substitution well ahead, sweep block size kept"
+                                                        : ": timing sweep block sizes"));
+    float best = try_r && !skip_r ? cost() : 0.f;
     for (int R : {1024, 2048, 4096, 8192}) {
-      if (!try_r || R == L.sweep_R || R >= L.sweep_rows) continue;
+      if (!try_r || skip_r || R == L.sweep_R || R >= L.sweep_rows) continue;
       // keep the current build aside, try the candidate in a list of its own
       DevSweepSched lo = L.lower, up = L.upper;
       SweepPackDev fg = L.fgs, bg = L.bgs, il = h->ilu_l, iu = h->ilu_u;
@@ -1021,24 +1054,20 @@ static void tune_sweeps(cpc_solver* h) {
     }
     if (L.sweep_rows > 8192 && d + 1 < h->lev.size() && h->opt.dense_smoother != 1 &&
         h->opt.dense_smoother != 2) {
-      auto gs_cost = [&] {
-        return time_ms(h, 3, [&] {
-          if (L.bdense) {
-            bdense_solve(h, L, false, f, u, L.r, nullptr);
-            bdense_solve(h, L, true, f, u, L.r, nullptr);
-          } else if (L.dense_smooth) {
-            launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, nullptr);
-            launch_dense_lower_t(h->stream, L.dtri, f32, f32, f, u, nullptr);
-          } else {
-            run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
-            run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
-          }
-        });
-      };
       float gbest = gs_cost();
       const bool was_dense = L.dense_smooth;
-      for (int B : {1024, 2048, 4096, 8192}) {
+      // block sizes from the middle out; 1024 and 8192 only where the model
+      // t(B) = a / B + c B fitted to the 2048 and 4096 timings predicts a gain
+      for (int B : {4096, 2048, 8192, 1024}) {
         if (B >= L.sweep_rows) continue;
+        if (L.bdense && L.bd_B == B) continue;  // kept from the quick look
+        if ((B == 8192 || B == 1024) && bd_time.count(2048) && bd_time.count(4096)) {
+          const double t2 = bd_time[2048], t4 = bd_time[4096];
+          const double c = (2.0 * t4 - t2) / (2.0 * 4096.0 - 2048.0);  // from t2 = a/2048 + 2048c, t4 = a/4096 + 4096c
+          const double a = (t2 - 2048.0 * c) * 2048.0;
+          const double pred = a / B + c * B;
+          if (!(pred < 0.97 * gbest)) continue;
+        }
         // the current best block-dense form (if any) is set aside while B is tried
         Level keep;
         keep.bdense = L.bdense;
@@ -1057,6 +1086,7 @@ static void tune_sweeps(cpc_solver* h) {
           L.bdense = true;
           L.dense_smooth = false;
           const float t = gs_cost();
+          bd_time[B] = t;
           L.dense_smooth = was_dense && !(t < gbest);
           better = t < gbest;
           if (better) gbest = t;
