@@ -115,158 +115,124 @@ __global__ __launch_bounds__(kNT) void to_type_kernel(long n, const double* __re
   for (long i = (long)blockIdx.x * kNT + threadIdx.x; i < n; i += (long)gridDim.x * kNT) y[i] = (MT)a[i];
 }
 
+// 16-byte vector of MT, loaded non-temporally: the inverses are streamed once per
+// product, and marking them so keeps them from displacing what the small kernels between
+// two products read (the off-block rows, the level vectors, the convergence flag).
 template <typename MT>
-struct Vec16;  // 16-byte vector of MT
-template <>
-struct Vec16<double> {
-  using T = double2;
-  static constexpr int N = 2;
-  __device__ static double at(const T& v, int k) { return k == 0 ? v.x : v.y; }
-};
-template <>
-struct Vec16<float> {
-  using T = float4;
-  static constexpr int N = 4;
-  __device__ static double at(const T& v, int k) {
-    return (double)(k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w)));
-  }
+struct Vec16 {
+  static constexpr int N = 16 / sizeof(MT);
+  using T = MT __attribute__((ext_vector_type(N)));
+  __device__ static T load(const char* p) { return __builtin_nontemporal_load(reinterpret_cast<const T*>(p)); }
+  __device__ static double at(const T& v, int k) { return (double)v[k]; }
 };
 
-// Column modes of one group of rows over a run of aligned vectors: no row of the group
-// holds an entry there, every row holds every entry, or some entries are masked.
-enum { kNone = 0, kFull = 1, kMask = 2 };
-
-// Per-item context of the row products: the two row groups of the item and the rows'
-// triangles (lower rows i hold [0, i], upper rows [i, n)).
-template <bool UPPER, typename MT, typename XT>
-struct RowItem {
-  using V = Vec16<MT>;
-  using VT = typename V::T;
-  static constexpr int W = V::N;
-  const VT* ra;  // first row of group A, as vectors
-  const VT* rb;  // first row of group B
-  long vs;       // row stride in vectors
-  const XT* fs;  // the system's part of the input vector
-  int n, a0, b0, na, nb;
-  __device__ bool holds(int row, int j) const { return UPPER ? (j >= row && j < n) : j <= row; }
-};
-
-// Adds the products of the vectors at j, j + W*kNT, ... < q for the rows of groups A and B
-// in the given modes. Every loaded vector entry of the input is shared by all 8 rows.
-template <int MA, int MB, bool UPPER, typename MT, typename XT>
-__device__ __forceinline__ void add_run(const RowItem<UPPER, MT, XT>& it, int j, int q, double (&acc)[2 * kHalfRows]) {
-  using V = Vec16<MT>;
-  using VT = typename V::T;
-  constexpr int W = V::N, H = kHalfRows;
-#pragma unroll 2
-  for (; j < q; j += W * kNT) {
-    const long c = j / W;
-    VT m[2 * H];
-#pragma unroll
-    for (int r = 0; r < H; ++r) {
-      m[r] = (MA != kNone && r < it.na) ? it.ra[r * it.vs + c] : VT{};
-      m[H + r] = (MB != kNone && r < it.nb) ? it.rb[r * it.vs + c] : VT{};
-    }
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      const int jj = j + k;
-      if (MA == kMask || MB == kMask) {
-        if (jj >= it.n) break;
-      }
-      const double fv = (double)it.fs[jj];
-#pragma unroll
-      for (int r = 0; r < H; ++r) {
-        if (MA == kFull || (MA == kMask && it.holds(it.a0 + r, jj))) acc[r] += V::at(m[r], k) * fv;
-        if (MB == kFull || (MB == kMask && it.holds(it.b0 + r, jj))) acc[H + r] += V::at(m[H + r], k) * fv;
-      }
-    }
-  }
-}
-
-// Vector-aligned bounds of one group's columns: [s, e) holds every entry of the group,
-// [fl, fh) is where every row of the group holds whole vectors.
-struct GroupSpan {
-  int s, fl, fh, e;
-};
-template <bool UPPER, int W>
-__device__ __forceinline__ GroupSpan group_span(int r0, int nr, int n) {
-  if (nr == 0) return {0, 0, 0, 0};
-  const int last = r0 + nr - 1;
-  const int nv = ((n + W - 1) / W) * W;  // end of the vectors that cover [0, n)
-  if (UPPER)  // rows hold [r, n): all rows full from the last row's start to the last whole vector
-    return {(r0 / W) * W, min(((last + W - 1) / W) * W, (n / W) * W), (n / W) * W, nv};
-  // rows hold [0, r]: all rows full up to the first row's end
-  return {0, 0, ((r0 + 1) / W) * W, min((last / W + 1) * W, nv)};
-}
-__device__ __forceinline__ int group_mode(const GroupSpan& g, int j) {
-  if (j < g.s || j >= g.e) return kNone;
-  return (j >= g.fl && j < g.fh) ? kFull : kMask;
-}
+// Entries of the flat vector list a thread loads before it uses any of them: 8 x (4 row
+// vectors + 2 input entries) in FP64, 4 x (4 + 4) in FP32 (a vector spans twice the
+// columns), about 200 registers, two waves per SIMD.
+template <typename MT>
+constexpr int row_steps() { return sizeof(MT) == 8 ? 8 : 4; }
 
 // y = M f with M lower (y = T^{-1} f) or upper (y = T^{-T} g from the stored
 // transpose) triangular. An item holds two groups of at most four rows, one from each end
 // of the system (rows 4k.. and the mirrored rows from the bottom), so that every item
 // carries about the same number of entries and no workgroup of a launch lags far behind
-// the others. The workgroup walks the columns of the item's rows together, each thread
-// taking 16 bytes of each row per step (rows are 16-byte aligned), so each vector entry
-// is loaded once for all the rows. The column range is cut at the groups' triangle edges
-// into runs where each group is absent, whole, or masked per entry; the 256 partials of
-// each row are then added in a fixed order.
+// the others. Each group reads the 16-byte vectors that cover its rows' triangle: lower
+// rows [a, a+4) the columns [0, a+4), upper rows the columns [a, n), rounded out to whole
+// vectors. The few entries this takes beyond a row's own triangle, and the padding
+// columns past n, are zeros of the stored square, so they add nothing (the input entry
+// index is clamped to the system there). A group of fewer than four rows reads its last
+// row again in place of the missing ones (those sums are never stored). The two groups'
+// vector ranges are laid end to end and dealt to the threads as one list (thread t takes
+// entries t, t + 256, ...); each entry is the four row vectors at one column vector and
+// the input entries there, shared by the four rows. A thread issues the loads of
+// several entries before it uses any of them, with no branch between, so most of a
+// launch's traffic is in flight at once rather than in a chain of dependent rounds. An
+// entry's products go to its own group's sums; the other group's sums take exact zeros
+// (a product with a zero factor of finite entries). The 256 partials of each row are
+// then added in a fixed order.
 template <bool UPPER, typename MT, typename XT>
-__global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
                                                             XT* __restrict__ y, const int* __restrict__ done) {
   using V = Vec16<MT>;
   using VT = typename V::T;
-  constexpr int W = V::N, H = kHalfRows;
+  constexpr int W = V::N, H = kHalfRows, D = row_steps<MT>();
   __shared__ double red[kNT / 64][2 * H];
   if (done && *done) return;
-  const int4 iv = dt.item_n[blockIdx.x];
-  const int s = iv.x;
-  RowItem<UPPER, MT, XT> it;
-  it.n = dt.n[s];
-  it.a0 = iv.y;
-  it.b0 = iv.z;
-  it.na = iv.w & 15;
-  it.nb = (iv.w >> 4) & 15;
-  const long ld = dense_ld(it.n);
-  const int voff = dt.voff[s];
-  const MT* __restrict__ M = reinterpret_cast<const MT*>(UPPER ? dt.MT : dt.M) + dt.moff[s];
-  it.ra = reinterpret_cast<const VT*>(M + it.a0 * ld);
-  it.rb = reinterpret_cast<const VT*>(M + it.b0 * ld);
-  it.vs = ld / W;
-  it.fs = f + voff;
+  int n, a0, b0, na, nb, voff;
+  long moff;
+  if (dt.one_n > 0) {  // item k: rows 4k.. and the mirrored group m-1-k, if it lies below
+    n = dt.one_n;
+    voff = dt.one_voff;
+    moff = dt.one_moff;
+    const int m = (n + H - 1) / H, k = blockIdx.x, kb = m - 1 - k;
+    a0 = k * H;
+    na = min(H, n - a0);
+    b0 = kb > k ? kb * H : 0;
+    nb = kb > k ? min(H, n - b0) : 0;
+  } else {
+    const int4 iv = dt.item_n[blockIdx.x];
+    const int s = iv.x;
+    n = dt.n[s];
+    a0 = iv.y;
+    b0 = iv.z;
+    na = iv.w & 15;
+    nb = (iv.w >> 4) & 15;
+    voff = dt.voff[s];
+    moff = dt.moff[s];
+  }
+  const long vs = dense_ld(n) / W;  // row stride in vectors
+  const VT* __restrict__ M = reinterpret_cast<const VT*>(reinterpret_cast<const MT*>(UPPER ? dt.MT : dt.M) + moff);
+  const XT* __restrict__ fs = f + voff;
+  // the groups' column-vector ranges [sa, sa + la) and [sb, sb + lb)
+  const int nv = (n + W - 1) / W;
+  const int sa = UPPER ? a0 / W : 0, la = UPPER ? nv - sa : (a0 + na + W - 1) / W;
+  const int sb = UPPER ? b0 / W : 0, lb = nb == 0 ? 0 : (UPPER ? nv - sb : (b0 + nb + W - 1) / W);
+  const int len = la + lb;
+  // byte offsets from M fit 32 bits (a system's inverse is at most 16384^2 entries), so
+  // each load takes the uniform base and one per-lane register
+  const char* __restrict__ Mb = reinterpret_cast<const char*>(M);
+  const char* __restrict__ fb = reinterpret_cast<const char*>(fs);
+  unsigned oa[H], ob[H];
+#pragma unroll
+  for (int r = 0; r < H; ++r) {
+    oa[r] = (unsigned)((a0 + min(r, na - 1)) * vs) * (unsigned)sizeof(VT);
+    ob[r] = (unsigned)((b0 + min(r, max(nb - 1, 0))) * vs) * (unsigned)sizeof(VT);
+  }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double acc[2 * H];
 #pragma unroll
   for (int r = 0; r < 2 * H; ++r) acc[r] = 0.0;
-  const GroupSpan ga = group_span<UPPER, W>(it.a0, it.na, it.n);
-  const GroupSpan gb = group_span<UPPER, W>(it.b0, it.nb, it.n);
-  // run boundaries: the groups' span bounds, sorted (all multiples of W)
-  int cut[8] = {ga.s, ga.fl, ga.fh, ga.e, gb.s, gb.fl, gb.fh, gb.e};
+  for (int v0 = tid; v0 < len; v0 += D * kNT) {
+    VT m[D][H];
+    XT fv[D][W];
+    double sel[D];  // 1: group A, 0: group B, -1: past the list
 #pragma unroll
-  for (int i = 1; i < 8; ++i)
+    for (int d = 0; d < D; ++d) {
+      const int vd = v0 + d * kNT;
+      const int v = vd < len ? vd : v0;  // a step past the list reads the first one again
+      const bool ina = v < la;
+      const int c = ina ? sa + v : sb + (v - la);
+      const unsigned oc = (unsigned)c * (unsigned)sizeof(VT);
 #pragma unroll
-    for (int k = 7; k >= i; --k)
-      if (cut[k] < cut[k - 1]) {
-        const int t = cut[k];
-        cut[k] = cut[k - 1];
-        cut[k - 1] = t;
+      for (int r = 0; r < H; ++r) m[d][r] = V::load(Mb + ((ina ? oa[r] : ob[r]) + oc));
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+        fv[d][k] = *reinterpret_cast<const XT*>(fb + (unsigned)min(c * W + k, n - 1) * (unsigned)sizeof(XT));
+      sel[d] = vd < len ? (ina ? 1.0 : 0.0) : -1.0;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const double fk = (double)fv[d][k];
+        const double fa = sel[d] == 1.0 ? fk : 0.0, fb = sel[d] == 0.0 ? fk : 0.0;
+#pragma unroll
+        for (int r = 0; r < H; ++r) {
+          const double e = V::at(m[d][r], k);
+          acc[r] = fma(e, fa, acc[r]);
+          acc[H + r] = fma(e, fb, acc[H + r]);
+        }
       }
-  for (int i = 0; i < 7; ++i) {
-    const int p = cut[i], q = cut[i + 1];
-    if (p >= q) continue;
-    const int ma = group_mode(ga, p), mb = group_mode(gb, p);
-    const int j = p + W * tid;
-    switch (ma * 3 + mb) {
-      case kNone * 3 + kFull: add_run<kNone, kFull>(it, j, q, acc); break;
-      case kNone * 3 + kMask: add_run<kNone, kMask>(it, j, q, acc); break;
-      case kFull * 3 + kNone: add_run<kFull, kNone>(it, j, q, acc); break;
-      case kFull * 3 + kFull: add_run<kFull, kFull>(it, j, q, acc); break;
-      case kFull * 3 + kMask: add_run<kFull, kMask>(it, j, q, acc); break;
-      case kMask * 3 + kNone: add_run<kMask, kNone>(it, j, q, acc); break;
-      case kMask * 3 + kFull: add_run<kMask, kFull>(it, j, q, acc); break;
-      case kMask * 3 + kMask: add_run<kMask, kMask>(it, j, q, acc); break;
-      default: break;
     }
   }
 #pragma unroll
@@ -276,8 +242,8 @@ __global__ __launch_bounds__(kNT) void gemv_tri_rows_kernel(DenseTriDev dt, cons
   }
   __syncthreads();
   if (tid < 2 * H) {
-    const bool ok = tid < H ? tid < it.na : tid - H < it.nb;
-    const int row = tid < H ? it.a0 + tid : it.b0 + tid - H;
+    const bool ok = tid < H ? tid < na : tid - H < nb;
+    const int row = tid < H ? a0 + tid : b0 + tid - H;
     if (ok) y[voff + row] = (XT)((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
   }
 }

@@ -155,6 +155,13 @@ struct DenseTriDev {
   int nred;            // column sums of the partials: {system, first column, first slot, slots}
   const int4* red;
   double* part;        // [slots][kTCols]
+  // A launch over one system (a diagonal block of the block-dense form, or a level held
+  // whole): one_n > 0 gives its rows, its first row in the level vector and the offset
+  // of its inverse, and the row items follow from the block index (the items of
+  // dense_row_items), so the kernel reads no item or system entry before the inverse.
+  int one_n;
+  int one_voff;
+  long one_moff;
 };
 // Row stride of a stored n x n inverse: n rounded up to a multiple of 4 elements, so
 // that every row starts 16-byte aligned (the padding columns hold zeros).

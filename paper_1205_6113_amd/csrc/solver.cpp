@@ -135,6 +135,7 @@ struct Level {
   std::vector<int> bd_start;     // K + 1 block starts
   DenseTriDev bd_dt{};           // the diagonal blocks as systems
   std::vector<int> bd_item_off;  // K + 1 offsets of each block's row items
+  std::vector<long> bd_moff;     // K element offsets of the blocks' inverses
   DevCsr bd_Loff, bd_Uoff;       // lower / upper entries outside the row's block
   std::vector<void*> bd_owned;
   double bd_entries = 0.0;       // stored inverse entries (byte model)
@@ -574,7 +575,9 @@ static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::
 }
 
 // Explicit inverses of T = D + L for the smoothed systems of a level (all of them or
-// none): at most 16384 rows each (larger levels take the block form) and 64 GB.
+// none): at most 16384 rows each (larger levels take the block form) and 64 GB. The
+// row products address one system's inverse with 32-bit byte offsets, which holds up to
+// 16384 rows (2 GiB in FP64); diagonal blocks of the block form obey the same limit.
 static constexpr int kDenseMaxRows = 16384;
 static constexpr double kDenseMaxBytes = 64e9;
 static constexpr int kDenseTransRows = 16384;
@@ -656,6 +659,11 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
   dt.M = M;
   dt.nitem_n = (int)itn.size();
   dt.item_n = dupload(itn, h->owned, h->stream);
+  if (ns.size() == 1) {
+    dt.one_n = ns[0];
+    dt.one_voff = voffs[0];
+    dt.one_moff = moff[0];
+  }
   dt.nitem_t = (int)itt.size();
   dt.item_t = dupload(itt, h->owned, h->stream);
   dt.nred = (int)red.size();
@@ -791,6 +799,7 @@ static const DevSweepSched& ilu_upper_sched(const cpc_solver* h) { return h->ilu
 // with the entries right of the block and x_b = T_bb^{-T} g_b. Returns false (nothing
 // kept) when it does not fit or a step fails.
 static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B) {
+  if (B <= 0 || B > kDenseMaxRows) return false;
   const int n = sub.n;
   std::vector<int> st;
   for (int r = 0; r < n; r += B) st.push_back(r);
@@ -901,6 +910,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   L.bd_B = B;
   L.bd_start = st;
   L.bd_item_off = ioff;
+  L.bd_moff = moff;
   L.bd_entries = ent;
   L.bd_owned.swap(own);
   return true;
@@ -913,9 +923,24 @@ static void free_blockdense(cpc_solver* h, Level& L) {
   L.bd_dt = DenseTriDev{};
   L.bd_start.clear();
   L.bd_item_off.clear();
+  L.bd_moff.clear();
   L.bd_B = 0;
   L.bd_entries = 0.0;
   L.bdense = false;
+}
+
+// The block-dense form's launch over diagonal block b.
+static DenseTriDev bd_block(const Level& L, int b) {
+  if (b < 0 || (size_t)b + 1 >= L.bd_start.size() || L.bd_moff.size() + 1 != L.bd_start.size() ||
+      L.bd_item_off.size() != L.bd_start.size())
+    throw HipError{hipErrorInvalidValue, "block-dense form: inconsistent block tables"};
+  DenseTriDev dt = L.bd_dt;
+  dt.item_n += L.bd_item_off[b];
+  dt.nitem_n = L.bd_item_off[b + 1] - L.bd_item_off[b];
+  dt.one_n = L.bd_start[b + 1] - L.bd_start[b];
+  dt.one_voff = L.bd_start[b];
+  dt.one_moff = L.bd_moff[b];
+  return dt;
 }
 
 // x = T^{-1} f (upper = false) or x = T^{-T} f (upper = true) through the block-dense
@@ -932,9 +957,7 @@ static void bdense_solve(cpc_solver* h, Level& L, bool upper, const void* f, voi
     m.n = nb;
     m.rp = off.rp + r0;
     spmv_or_throw(h, m, 1, x, f32, (const char*)f + es * r0, f32, (char*)g + es * r0, f32, off.tpr, done);
-    DenseTriDev dt = L.bd_dt;
-    dt.item_n += L.bd_item_off[b];
-    dt.nitem_n = L.bd_item_off[b + 1] - L.bd_item_off[b];
+    const DenseTriDev dt = bd_block(L, b);
     if (upper) launch_dense_lower_t(h->stream, dt, f32, f32, g, x, done);
     else launch_dense_lower(h->stream, dt, f32, f32, g, x, done);
   }
@@ -1075,6 +1098,7 @@ static void tune_sweeps(cpc_solver* h) {
         keep.bd_start.swap(L.bd_start);
         keep.bd_dt = L.bd_dt;
         keep.bd_item_off.swap(L.bd_item_off);
+        keep.bd_moff.swap(L.bd_moff);
         keep.bd_Loff = L.bd_Loff;
         keep.bd_Uoff = L.bd_Uoff;
         keep.bd_owned.swap(L.bd_owned);
@@ -1101,6 +1125,7 @@ static void tune_sweeps(cpc_solver* h) {
           L.bd_start.swap(keep.bd_start);
           L.bd_dt = keep.bd_dt;
           L.bd_item_off.swap(keep.bd_item_off);
+          L.bd_moff.swap(keep.bd_moff);
           L.bd_Loff = keep.bd_Loff;
           L.bd_Uoff = keep.bd_Uoff;
           L.bd_owned.swap(keep.bd_owned);
@@ -2313,9 +2338,7 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         if (L.bdense) {
           const int K = (int)L.bd_start.size() - 1;
           for (int b = 0; b < K; ++b) {
-            DenseTriDev dt = L.bd_dt;
-            dt.item_n += L.bd_item_off[b];
-            dt.nitem_n = L.bd_item_off[b + 1] - L.bd_item_off[b];
+            const DenseTriDev dt = bd_block(L, b);
             const double nb = L.bd_start[b + 1] - L.bd_start[b];
             both(dt, 0.5 * nb * (nb + 1), nb);
           }
