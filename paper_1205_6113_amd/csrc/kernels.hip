@@ -81,18 +81,37 @@ __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict_
                                                    const VT* __restrict__ v, const XT* __restrict__ x,
                                                    const FT* __restrict__ f, YT* __restrict__ y, int mode,
                                                    const int* __restrict__ done) {
-  if (done && *done) return;
   constexpr int RPB = kNT / TPR;
   const int lane = threadIdx.x % TPR;
-  for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
-    const int b = rp[i], e = rp[i + 1];
+  const int stride = gridDim.x * RPB;
+  int i = blockIdx.x * RPB + threadIdx.x / TPR;
+  // A row's bounds and the term its product is combined with (f_i, or y_i when adding)
+  // are read before they are needed: the first row's together with the convergence flag,
+  // the next row's while this one is summed, so the flag and those reads add no step to
+  // the chain of dependent loads (rows bounds, then entries, then x).
+  int b = 0, e = 0;
+  double g = 0.0;
+  if (i < n) {
+    b = rp[i];
+    e = rp[i + 1];
+    g = mode == 1 ? ld(f, i) : (mode == 2 ? ld(y, i) : 0.0);
+  }
+  if (done && *done) return;
+  for (; i < n; i += stride) {
     double s = 0.0;
     for (int p = b + lane; p < e; p += TPR) s += (double)v[p] * ld(x, ci[p]);
+    const int in = i + stride;
+    const double gi = g;
+    if (in < n) {
+      b = rp[in];
+      e = rp[in + 1];
+      g = mode == 1 ? ld(f, in) : (mode == 2 ? ld(y, in) : 0.0);
+    }
     s = group_sum<TPR>(s);
     if (lane == 0) {
       if (mode == 0) st(y, i, s);
-      else if (mode == 1) st(y, i, ld(f, i) - s);
-      else st(y, i, ld(y, i) + s);
+      else if (mode == 1) st(y, i, gi - s);
+      else st(y, i, gi + s);
     }
   }
 }
