@@ -88,7 +88,9 @@ typedef struct {
   int32_t swap_roles;     /* 0: S = V-cycle, B = ILU(0) (Section 3); 1: S = ILU(0), B = V   */
   int32_t check_symmetry; /* 1: reject CSR that is not numerically symmetric (O(nnz) check) */
   int32_t use_graph;      /* 1: replay each PCG iteration as a captured HIP graph           */
-  int32_t check_every;    /* PCG iterations between host reads of the convergence flag (4)  */
+  int32_t check_every;    /* PCG iterations between host reads of the convergence flag; 0
+                             (default): predicted from the mean residual reduction so far
+                             (single systems; a batch then reads it after every iteration) */
   int32_t rap_on_gpu;     /* 1: Galerkin products on the GPU (default); 0 is not offered     */
   int32_t sweep_block_rows; /* rows per workgroup block of the triangular sweeps (0 = auto)  */
   int32_t sweep_threads;  /* threads per sweep workgroup: 64 (one wave) or 256; 0 = auto     */

@@ -7,8 +7,9 @@
 //
 // SOLVE: PCG with all scalars on the device; each iteration is one fixed sequence
 // of kernels (optionally replayed from a captured HIP graph); the host reads the
-// convergence flag every `check_every` iterations and kernels after convergence
-// return immediately, so the iteration count is exact.
+// convergence state after every `check_every` iterations, or, by default, after as
+// many as the residual history predicts, and kernels after convergence return
+// immediately, so the iteration count is exact.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -688,6 +689,21 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
   }
   L.dense_M = M;
   L.dense_entries = ent;
+}
+
+// Iterations to launch before the next read of the convergence state when no fixed
+// count is set: the mean residual reduction per iteration so far predicts how many
+// remain, and three quarters of that (at least one, at most 64) are launched, so a solve
+// rarely replays an iteration past convergence (a full graph of launches that return at
+// once) and reads the state a few times instead of after every iteration.
+static int predicted_chunk(const PcgState& hs, int it0, double rel0) {
+  const int done_its = hs.iters - it0;
+  if (done_its < 1 || !(rel0 > 0.0) || !(hs.relres > 0.0) || !(hs.tol > 0.0) || !(hs.relres > hs.tol)) return 1;
+  const double q = std::pow(hs.relres / rel0, 1.0 / done_its);
+  if (!(q > 0.0 && q < 1.0)) return 1;
+  const double m = std::log(hs.tol / hs.relres) / std::log(q);
+  if (!(m > 0.0)) return 1;
+  return std::max(1, std::min(64, (int)(0.75 * m)));
 }
 
 // Average milliseconds of fn() over reps launches after one warm-up (events on the
@@ -1671,7 +1687,7 @@ static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x,
     PcgState hs{};
     HIPCHK(hipMemcpyAsync(&hs, h->st, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    const int every = std::max(1, (int)h->opt.check_every);
+    const int every = h->opt.check_every;
     bool use_graph = h->opt.use_graph != 0;
     if (use_graph && (!h->graph[prec] || h->graph_x[prec] != x)) {
       if (h->graph[prec]) {
@@ -1701,8 +1717,10 @@ static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x,
       h->graph_x[prec] = x;
     }
     int launched = 0;
+    const int it0 = hs.iters;
+    const double rel0 = hs.relres;
     while (!hs.done && launched < maxit) {
-      const int k = std::min(every, maxit - launched);
+      const int k = std::min(every > 0 ? every : predicted_chunk(hs, it0, rel0), maxit - launched);
       for (int i = 0; i < k; ++i) {
         if (use_graph) HIPCHK(hipGraphLaunch(h->graph[prec], h->stream));
         else enqueue_iteration(h, prec, x);
@@ -1804,7 +1822,7 @@ static cpc_status run_solve_batch(cpc_solver* h, int prec, const double* b, doub
       h->bgraph[prec] = ge;
       h->bgraph_x[prec] = x;
     }
-    const int every = std::max(1, (int)h->opt.check_every);
+    const int every = std::max(1, (int)h->opt.check_every);  // batch: every iteration unless set
     int launched = 0;
     while (!all_done() && launched < maxit) {
       const int k = std::min(every, maxit - launched);
@@ -1873,7 +1891,7 @@ void cpc_default_options(cpc_options* o) {
   o->swap_roles = 0;
   o->check_symmetry = 1;
   o->use_graph = 1;
-  o->check_every = 4;
+  o->check_every = 0;
   o->rap_on_gpu = 1;
   o->sweep_block_rows = 0;
   o->sweep_threads = 0;
@@ -1900,6 +1918,7 @@ static cpc_status read_options(const cpc_options* opt, cpc_options& o) {
     return set_err(CPC_E_ARG, "sweep_threads must be 0, 64 or 256");
   if (o.dense_smoother < 0 || o.dense_smoother > 3) return set_err(CPC_E_ARG, "dense_smoother must be 0, 1, 2 or 3");
   if (o.ilu_fill < 0 || o.ilu_fill > 16) return set_err(CPC_E_ARG, "ilu_fill must lie in [0, 16]");
+  if (o.check_every < 0) return set_err(CPC_E_ARG, "check_every must be >= 0 (0: predicted)");
   return CPC_OK;
 }
 

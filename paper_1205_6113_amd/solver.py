@@ -34,7 +34,7 @@ def _dev_vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
 
 
 def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, theta=0.25, swap_roles=False,
-            check_symmetry=True, use_graph=True, check_every=4, sweep_block_rows=0,
+            check_symmetry=True, use_graph=True, check_every=0, sweep_block_rows=0,
             sweep_threads=0, dense_smoother=0, tune=True, verbose=False, ilu_fill=0) -> _lib.Options:
     lib = load()
     o = _lib.Options()

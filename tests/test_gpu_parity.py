@@ -197,6 +197,15 @@ def test_graph_and_eager_agree(cases):
             xg, itg, _, _ = sg.solve(dev(p.b), tol=1e-9)
             assert itg == ite
             assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy()), rep
+    # the default predicts how many iterations to launch between reads of the state;
+    # the result and the count must not depend on it (tight tolerance: many iterations)
+    with cpc.Solver(p.n, p.row_ptr, p.col, p.val, use_graph=True) as sp:
+        for tol in (1e-9, 1e-12):
+            with cpc.Solver(p.n, p.row_ptr, p.col, p.val, use_graph=True, check_every=1) as s1:
+                x1, it1, _, _ = s1.solve(dev(p.b), tol=tol)
+            xp, itp, _, _ = sp.solve(dev(p.b), tol=tol)
+            assert itp == it1, tol
+            assert np.array_equal(xp.cpu().numpy(), x1.cpu().numpy()), tol
 
 
 def test_single_unknown_and_one_level():
