@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "wave_sum.hpp"
 
 namespace cpc {
 
@@ -35,13 +36,6 @@ namespace {
 
 constexpr int kLeaf = 128;  // diagonal blocks inverted by substitution
 constexpr int kNT = 256;
-
-template <int W>
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-  return v;
-}
 
 // The diagonal block of T on rows and columns [voff, voff + n) of a CSR into the dense
 // row-major array M (leading dimension n): lower triangle only (upper entries stay zero).
@@ -132,6 +126,61 @@ struct Vec16 {
 template <typename MT>
 constexpr int row_steps() { return sizeof(MT) == 8 ? 8 : 4; }
 
+// One item's products into acc[0..8) (rows of group A, then of group B); the list and
+// the loads are as described at the kernel below. FV: the input entries of a column
+// vector are read as one 16-byte vector, which needs the system's part of the input
+// 16-byte aligned and n a multiple of the vector width (every vector then lies inside
+// it); otherwise they are read one by one, the index clamped to the system.
+template <bool FV, typename MT, typename XT>
+__device__ __forceinline__ void item_products(const char* __restrict__ Mb, const char* __restrict__ fb, int n,
+                                              int sa, int la, int sb, int len, const unsigned (&oa)[kHalfRows],
+                                              const unsigned (&ob)[kHalfRows], double (&acc)[2 * kHalfRows]) {
+  using V = Vec16<MT>;
+  using VT = typename V::T;
+  constexpr int W = V::N, H = kHalfRows, D = row_steps<MT>();
+  static_assert(!FV || sizeof(XT) == sizeof(MT), "vector input reads assume input and inverse of one type");
+  for (int v0 = threadIdx.x; v0 < len; v0 += D * kNT) {
+    VT m[D][H];
+    XT fv[D][W];
+    double sel[D];  // 1: group A, 0: group B, -1: past the list
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int vd = v0 + d * kNT;
+      const int v = vd < len ? vd : v0;  // a step past the list reads the first one again
+      const bool ina = v < la;
+      const int c = ina ? sa + v : sb + (v - la);
+      const unsigned oc = (unsigned)c * (unsigned)sizeof(VT);
+#pragma unroll
+      for (int r = 0; r < H; ++r) m[d][r] = V::load(Mb + ((ina ? oa[r] : ob[r]) + oc));
+      if constexpr (FV) {
+        using FT = typename Vec16<XT>::T;
+        const FT t = *reinterpret_cast<const FT*>(fb + oc);
+#pragma unroll
+        for (int k = 0; k < W; ++k) fv[d][k] = t[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+          fv[d][k] = *reinterpret_cast<const XT*>(fb + (unsigned)min(c * W + k, n - 1) * (unsigned)sizeof(XT));
+      }
+      sel[d] = vd < len ? (ina ? 1.0 : 0.0) : -1.0;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const double fk = (double)fv[d][k];
+        const double fka = sel[d] == 1.0 ? fk : 0.0, fkb = sel[d] == 0.0 ? fk : 0.0;
+#pragma unroll
+        for (int r = 0; r < H; ++r) {
+          const double e = V::at(m[d][r], k);
+          acc[r] = fma(e, fka, acc[r]);
+          acc[H + r] = fma(e, fkb, acc[H + r]);
+        }
+      }
+    }
+  }
+}
+
 // y = M f with M lower (y = T^{-1} f) or upper (y = T^{-T} g from the stored
 // transpose) triangular. An item holds two groups of at most four rows, one from each end
 // of the system (rows 4k.. and the mirrored rows from the bottom), so that every item
@@ -149,7 +198,9 @@ constexpr int row_steps() { return sizeof(MT) == 8 ? 8 : 4; }
 // launch's traffic is in flight at once rather than in a chain of dependent rounds. An
 // entry's products go to its own group's sums; the other group's sums take exact zeros
 // (a product with a zero factor of finite entries). The 256 partials of each row are
-// then added in a fixed order.
+// then added in a fixed order: within each wave by lane exchanges taken for all eight
+// rows at once (DPP and one swizzle, so no row's chain of waits holds up the others),
+// then the four waves' sums.
 template <bool UPPER, typename MT, typename XT>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
                                                             XT* __restrict__ y, const int* __restrict__ done) {
@@ -202,44 +253,14 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   double acc[2 * H];
 #pragma unroll
   for (int r = 0; r < 2 * H; ++r) acc[r] = 0.0;
-  for (int v0 = tid; v0 < len; v0 += D * kNT) {
-    VT m[D][H];
-    XT fv[D][W];
-    double sel[D];  // 1: group A, 0: group B, -1: past the list
+  if ((reinterpret_cast<unsigned long>(fs) & 15) == 0 && n % W == 0)
+    item_products<true, MT, XT>(Mb, fb, n, sa, la, sb, len, oa, ob, acc);
+  else
+    item_products<false, MT, XT>(Mb, fb, n, sa, la, sb, len, oa, ob, acc);
+  wave_sums(acc);  // valid in lane 0
+  if (lane == 0)
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int vd = v0 + d * kNT;
-      const int v = vd < len ? vd : v0;  // a step past the list reads the first one again
-      const bool ina = v < la;
-      const int c = ina ? sa + v : sb + (v - la);
-      const unsigned oc = (unsigned)c * (unsigned)sizeof(VT);
-#pragma unroll
-      for (int r = 0; r < H; ++r) m[d][r] = V::load(Mb + ((ina ? oa[r] : ob[r]) + oc));
-#pragma unroll
-      for (int k = 0; k < W; ++k)
-        fv[d][k] = *reinterpret_cast<const XT*>(fb + (unsigned)min(c * W + k, n - 1) * (unsigned)sizeof(XT));
-      sel[d] = vd < len ? (ina ? 1.0 : 0.0) : -1.0;
-    }
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        const double fk = (double)fv[d][k];
-        const double fa = sel[d] == 1.0 ? fk : 0.0, fb = sel[d] == 0.0 ? fk : 0.0;
-#pragma unroll
-        for (int r = 0; r < H; ++r) {
-          const double e = V::at(m[d][r], k);
-          acc[r] = fma(e, fa, acc[r]);
-          acc[H + r] = fma(e, fb, acc[H + r]);
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < 2 * H; ++r) {
-    const double v = wsum<64>(acc[r]);
-    if (lane == 0) red[w][r] = v;
-  }
+    for (int r = 0; r < 2 * H; ++r) red[w][r] = acc[r];
   __syncthreads();
   if (tid < 2 * H) {
     const bool ok = tid < H ? tid < na : tid - H < nb;

@@ -30,6 +30,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "wave_sum.hpp"
 
 namespace cpc {
 
@@ -44,33 +45,6 @@ __device__ __forceinline__ bool is_sentinel(double v) {
   return (unsigned long long)__double_as_longlong(v) == kSentinel64;
 }
 __device__ __forceinline__ bool is_sentinel(float v) { return __float_as_uint(v) == kSentinel32; }
-
-template <int CTRL>
-__device__ __forceinline__ double dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-// Sum over aligned groups of W lanes; the total is valid in each group's first lane.
-// Lane exchanges: xor 1, xor 2 (quad permutations), mirror within 8 and within 16
-// (DPP), xor 16 within 32 (swizzle), lane 32 read into lane 0.
-template <int W>
-__device__ __forceinline__ double gsum(double v) {
-  if constexpr (W >= 2) v += dpp<0xB1>(v);
-  if constexpr (W >= 4) v += dpp<0x4E>(v);
-  if constexpr (W >= 8) v += dpp<0x141>(v);
-  if constexpr (W >= 16) v += dpp<0x140>(v);
-  if constexpr (W >= 32) {
-    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
-    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
-    v += __hiloint2double(hi, lo);
-  }
-  if constexpr (W >= 64)
-    v += __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
-                          __builtin_amdgcn_readlane(__double2loint(v), 32));
-  return v;
-}
 
 // Makes the compiler complete the loads of v here, where the number of loads issued
 // since is known, rather than at a later use that follows loops with loads of their own
