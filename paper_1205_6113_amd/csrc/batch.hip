@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "wave_sum.hpp"
 
 namespace cpc {
 
@@ -17,15 +18,8 @@ namespace {
 
 constexpr int kNT = 256;
 
-template <int W>
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-  return v;
-}
-
 __device__ double bsum(double v, double* sh) {
-  v = wsum<64>(v);
+  v = gsum<64>(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[wid] = v;
@@ -76,7 +70,7 @@ __global__ __launch_bounds__(kNT) void bspmv_pq_kernel(BatchDev bd, const int* _
   for (int i = r0 + threadIdx.x / TPR; i < r1; i += kNT / TPR) {
     double t = 0.0;
     for (int k = rp[i] + lane; k < rp[i + 1]; k += TPR) t += v[k] * p[ci[k]];
-    t = wsum<TPR>(t);
+    t = gsum<TPR>(t);
     if (lane == 0) {
       q[i] = t;
       acc += t * p[i];
@@ -203,7 +197,7 @@ __global__ __launch_bounds__(kNT) void bdense_kernel(DenseListDev dl, const void
     const double* ff = reinterpret_cast<const double*>(f) + off;
     for (int j = lane; j < n0; j += 64) s += inv[(long)row * n0 + j] * ff[j];
   }
-  s = wsum<64>(s);
+  s = gsum<64>(s);
   if (lane == 0) {
     if (fp32) reinterpret_cast<float*>(e)[off + row] = (float)s;
     else reinterpret_cast<double*>(e)[off + row] = s;

@@ -10,6 +10,7 @@
 //  * Dense coarsest-level matvec, elementwise vector kernels, FP64->FP32 copies.
 //  The level-scheduled sweeps live in sweep.hip.
 #include "kernels.hpp"
+#include "wave_sum.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -30,16 +31,9 @@ __device__ __forceinline__ void st(T* p, long i, double v) {
   p[i] = (T)v;
 }
 
-template <int W>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-  return v;
-}
-
 // Sum over the workgroup (kNT threads). Fixed tree: deterministic.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = group_sum<64>(v);
+  v = gsum<64>(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[wid] = v;
@@ -107,7 +101,7 @@ __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict_
       e = rp[in + 1];
       g = mode == 1 ? ld(f, in) : (mode == 2 ? ld(y, in) : 0.0);
     }
-    s = group_sum<TPR>(s);
+    s = gsum<TPR>(s);
     if (lane == 0) {
       if (mode == 0) st(y, i, s);
       else if (mode == 1) st(y, i, gi - s);
@@ -129,7 +123,7 @@ __global__ __launch_bounds__(kNT) void spmv_pq_kernel(int n, const int* __restri
     const int b = rp[i], e = rp[i + 1];
     double s = 0.0;
     for (int k = b + lane; k < e; k += TPR) s += v[k] * p[ci[k]];
-    s = group_sum<TPR>(s);
+    s = gsum<TPR>(s);
     if (lane == 0) {
       q[i] = s;
       acc += s * p[i];
@@ -216,7 +210,7 @@ __global__ __launch_bounds__(kNT) void pcg_init_kernel(int n, const int* __restr
     double s = 0.0;
     if (use_x0) {
       for (int k = rp[i] + lane; k < rp[i + 1]; k += TPR) s += v[k] * x[ci[k]];
-      s = group_sum<TPR>(s);
+      s = gsum<TPR>(s);
     }
     if (lane == 0) {
       if (!use_x0) x[i] = 0.0;
@@ -273,7 +267,7 @@ __global__ __launch_bounds__(kNT) void dense_matvec_kernel(int n, const double* 
   if (row >= n) return;
   double s = 0.0;
   for (int j = lane; j < n; j += 64) s += inv[(long)row * n + j] * (double)f[j];
-  s = group_sum<64>(s);
+  s = gsum<64>(s);
   if (lane == 0) e[row] = (ET)s;
 }
 
