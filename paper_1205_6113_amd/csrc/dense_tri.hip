@@ -201,12 +201,14 @@ __device__ __forceinline__ void item_products(const char* __restrict__ Mb, const
 // then added in a fixed order: within each wave by lane exchanges taken for all eight
 // rows at once (DPP and one swizzle, so no row's chain of waits holds up the others),
 // then the four waves' sums.
+// At most two waves per SIMD: the compiler may then keep a whole batch of loads in
+// registers (it otherwise schedules for eight waves and issues one load at a time).
 template <bool UPPER, typename MT, typename XT>
-__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemv_tri_rows_kernel(DenseTriDev dt, const XT* __restrict__ f,
-                                                            XT* __restrict__ y, const int* __restrict__ done) {
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemv_tri_rows_kernel(
+    DenseTriDev dt, const XT* __restrict__ f, XT* __restrict__ y, const int* __restrict__ done) {
   using V = Vec16<MT>;
   using VT = typename V::T;
-  constexpr int W = V::N, H = kHalfRows, D = row_steps<MT>();
+  constexpr int W = V::N, H = kHalfRows;
   __shared__ double red[kNT / 64][2 * H];
   if (done && *done) return;
   int n, a0, b0, na, nb, voff;
