@@ -70,6 +70,36 @@ __device__ bool arrive(double part, double* partials, unsigned* counter, double*
 
 // ----------------------------------------------------------------------------
 // SpMV family
+
+// One lane's part of a row product: entries p, p + TPR, ... < e, added in that order.
+// Four of them are taken at once: their columns and values are loaded, then the four
+// x entries, then the products added, so a row of up to 4 TPR entries costs two
+// dependent memory rounds instead of two per TPR entries. A step past the row reads the
+// lane's first entry again and contributes an exact zero (its product is not added).
+template <int TPR, typename VT, typename XT>
+__device__ __forceinline__ double row_dot(int p, int e, const int* __restrict__ ci, const VT* __restrict__ v,
+                                          const XT* __restrict__ x) {
+  constexpr int U = 4;
+  double s = 0.0;
+  for (; p < e; p += U * TPR) {
+    int c[U];
+    VT w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = p + u * TPR < e ? p + u * TPR : p;
+      c[u] = ci[q];
+      w[u] = v[q];
+    }
+    double xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = ld(x, c[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (p + u * TPR < e) s += (double)w[u] * xv[u];
+  }
+  return s;
+}
+
 template <int TPR, typename VT, typename XT, typename FT, typename YT>
 __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const VT* __restrict__ v, const XT* __restrict__ x,
@@ -92,8 +122,7 @@ __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict_
   }
   if (done && *done) return;
   for (; i < n; i += stride) {
-    double s = 0.0;
-    for (int p = b + lane; p < e; p += TPR) s += (double)v[p] * ld(x, ci[p]);
+    const double s0 = row_dot<TPR>(b + lane, e, ci, v, x);
     const int in = i + stride;
     const double gi = g;
     if (in < n) {
@@ -101,7 +130,7 @@ __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict_
       e = rp[in + 1];
       g = mode == 1 ? ld(f, in) : (mode == 2 ? ld(y, in) : 0.0);
     }
-    s = gsum<TPR>(s);
+    const double s = gsum<TPR>(s0);
     if (lane == 0) {
       if (mode == 0) st(y, i, s);
       else if (mode == 1) st(y, i, gi - s);
