@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "csr_row.hpp"
 #include "wave_sum.hpp"
 
 namespace cpc {
@@ -68,8 +69,7 @@ __global__ __launch_bounds__(kNT) void bspmv_pq_kernel(BatchDev bd, const int* _
   const int lane = threadIdx.x % TPR;
   double acc = 0.0;
   for (int i = r0 + threadIdx.x / TPR; i < r1; i += kNT / TPR) {
-    double t = 0.0;
-    for (int k = rp[i] + lane; k < rp[i + 1]; k += TPR) t += v[k] * p[ci[k]];
+    double t = row_dot<TPR>(rp[i] + lane, rp[i + 1], ci, v, p);
     t = gsum<TPR>(t);
     if (lane == 0) {
       q[i] = t;

@@ -10,6 +10,7 @@
 //  * Dense coarsest-level matvec, elementwise vector kernels, FP64->FP32 copies.
 //  The level-scheduled sweeps live in sweep.hip.
 #include "kernels.hpp"
+#include "csr_row.hpp"
 #include "wave_sum.hpp"
 
 #include <hip/hip_runtime.h>
@@ -71,34 +72,6 @@ __device__ bool arrive(double part, double* partials, unsigned* counter, double*
 // ----------------------------------------------------------------------------
 // SpMV family
 
-// One lane's part of a row product: entries p, p + TPR, ... < e, added in that order.
-// Four of them are taken at once: their columns and values are loaded, then the four
-// x entries, then the products added, so a row of up to 4 TPR entries costs two
-// dependent memory rounds instead of two per TPR entries. A step past the row reads the
-// lane's first entry again and contributes an exact zero (its product is not added).
-template <int TPR, typename VT, typename XT>
-__device__ __forceinline__ double row_dot(int p, int e, const int* __restrict__ ci, const VT* __restrict__ v,
-                                          const XT* __restrict__ x) {
-  constexpr int U = 4;
-  double s = 0.0;
-  for (; p < e; p += U * TPR) {
-    int c[U];
-    VT w[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int q = p + u * TPR < e ? p + u * TPR : p;
-      c[u] = ci[q];
-      w[u] = v[q];
-    }
-    double xv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = ld(x, c[u]);
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (p + u * TPR < e) s += (double)w[u] * xv[u];
-  }
-  return s;
-}
 
 template <int TPR, typename VT, typename XT, typename FT, typename YT>
 __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -150,8 +123,7 @@ __global__ __launch_bounds__(kNT) void spmv_pq_kernel(int n, const int* __restri
   double acc = 0.0;
   for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
     const int b = rp[i], e = rp[i + 1];
-    double s = 0.0;
-    for (int k = b + lane; k < e; k += TPR) s += v[k] * p[ci[k]];
+    double s = row_dot<TPR>(b + lane, e, ci, v, p);
     s = gsum<TPR>(s);
     if (lane == 0) {
       q[i] = s;
@@ -238,7 +210,7 @@ __global__ __launch_bounds__(kNT) void pcg_init_kernel(int n, const int* __restr
   for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
     double s = 0.0;
     if (use_x0) {
-      for (int k = rp[i] + lane; k < rp[i + 1]; k += TPR) s += v[k] * x[ci[k]];
+      s = row_dot<TPR>(rp[i] + lane, rp[i + 1], ci, v, x);
       s = gsum<TPR>(s);
     }
     if (lane == 0) {
