@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kNT) void bspmv_pq_kernel(BatchDev bd, const int* _
   const int lane = threadIdx.x % TPR;
   double acc = 0.0;
   for (int i = r0 + threadIdx.x / TPR; i < r1; i += kNT / TPR) {
-    double t = row_dot<TPR>(rp[i] + lane, rp[i + 1], ci, v, p);
+    double t = row_dot<TPR, 1>(rp[i] + lane, rp[i + 1], ci, v, p);
     t = gsum<TPR>(t);
     if (lane == 0) {
       q[i] = t;

@@ -73,7 +73,7 @@ __device__ bool arrive(double part, double* partials, unsigned* counter, double*
 // SpMV family
 
 
-template <int TPR, typename VT, typename XT, typename FT, typename YT>
+template <int TPR, int U, typename VT, typename XT, typename FT, typename YT>
 __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const VT* __restrict__ v, const XT* __restrict__ x,
                                                    const FT* __restrict__ f, YT* __restrict__ y, int mode,
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict_
   }
   if (done && *done) return;
   for (; i < n; i += stride) {
-    const double s0 = row_dot<TPR>(b + lane, e, ci, v, x);
+    const double s0 = row_dot<TPR, U>(b + lane, e, ci, v, x);
     const int in = i + stride;
     const double gi = g;
     if (in < n) {
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kNT) void spmv_pq_kernel(int n, const int* __restri
   double acc = 0.0;
   for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
     const int b = rp[i], e = rp[i + 1];
-    double s = row_dot<TPR>(b + lane, e, ci, v, p);
+    double s = row_dot<TPR, 1>(b + lane, e, ci, v, p);
     s = gsum<TPR>(s);
     if (lane == 0) {
       q[i] = s;
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kNT) void pcg_init_kernel(int n, const int* __restr
   for (int i = blockIdx.x * RPB + threadIdx.x / TPR; i < n; i += gridDim.x * RPB) {
     double s = 0.0;
     if (use_x0) {
-      s = row_dot<TPR>(rp[i] + lane, rp[i + 1], ci, v, x);
+      s = row_dot<TPR, 1>(rp[i] + lane, rp[i + 1], ci, v, x);
       s = gsum<TPR>(s);
     }
     if (lane == 0) {
@@ -322,16 +322,30 @@ int grid_for(long work, int per_block, int cap = 8192) {
     default: CALL(64); break;       \
   }
 
-template <typename VT, typename XT, typename FT, typename YT>
-static void spmv_typed(hipStream_t s, const MatDev& A, int mode, const void* x, const void* f, void* y, int tpr,
-                       const int* done) {
+// Launches of more rows than this have waves enough to hide the dependent loads of a
+// row product; smaller ones (coarse levels, the blocks of the block substitution) take
+// the matrix's batched steps.
+constexpr int kLatencyRows = 32768;
+
+template <int U, typename VT, typename XT, typename FT, typename YT>
+static void spmv_typed_u(hipStream_t s, const MatDev& A, int mode, const void* x, const void* f, void* y, int tpr,
+                         const int* done) {
   const int rpb = kNT / tpr;
   const int grid = grid_for(A.n, rpb);
 #define CPC_SPMV_CALL(T)                                                                                  \
-  spmv_kernel<T, VT, XT, FT, YT><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const VT*)A.v, (const XT*)x,     \
-                                                      (const FT*)f, (YT*)y, mode, done)
+  spmv_kernel<T, U, VT, XT, FT, YT><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const VT*)A.v, (const XT*)x,  \
+                                                         (const FT*)f, (YT*)y, mode, done)
   CPC_TPR_DISPATCH(tpr, CPC_SPMV_CALL)
 #undef CPC_SPMV_CALL
+}
+
+template <typename VT, typename XT, typename FT, typename YT>
+static void spmv_typed(hipStream_t s, const MatDev& A, int mode, const void* x, const void* f, void* y, int tpr,
+                       const int* done) {
+  const int u = A.n > kLatencyRows ? 1 : A.steps;
+  if (u >= 4) spmv_typed_u<4, VT, XT, FT, YT>(s, A, mode, x, f, y, tpr, done);
+  else if (u == 2) spmv_typed_u<2, VT, XT, FT, YT>(s, A, mode, x, f, y, tpr, done);
+  else spmv_typed_u<1, VT, XT, FT, YT>(s, A, mode, x, f, y, tpr, done);
 }
 
 bool launch_spmv(hipStream_t s, const MatDev& A, int mode, const void* x, bool xf32, const void* f, bool ff32,

@@ -68,6 +68,7 @@ struct MatDev {  // CSR on the device; values of type T
   const int* dpos;  // position of the diagonal in each row (square matrices)
   const void* v;
   bool fp32;
+  int steps;  // entries per lane a small launch takes at once in a row product: 1, 2 or 4
 };
 
 // ---- launchers (all asynchronous on `s`) -----------------------------------

@@ -72,6 +72,13 @@ int pick_tpr(double avg_row) {
   return t;
 }
 
+// Entries per lane taken at once by a row product of a small launch: the average a lane
+// holds, rounded up to 1, 2 or 4.
+int pick_steps(double avg_row, int tpr) {
+  const double per_lane = avg_row / tpr;
+  return per_lane <= 1.0 ? 1 : (per_lane <= 2.0 ? 2 : 4);
+}
+
 }  // namespace
 
 namespace cpc {
@@ -85,6 +92,7 @@ struct DevCsr {
   float* v32 = nullptr;
   int* dpos = nullptr;
   int tpr = 1;
+  int steps = 1;
   MatDev mat(bool fp32) const {
     MatDev m;
     m.n = n;
@@ -93,6 +101,7 @@ struct DevCsr {
     m.dpos = dpos;
     m.v = fp32 ? (const void*)v32 : (const void*)v;
     m.fp32 = fp32;
+    m.steps = steps;
     return m;
   }
 };
@@ -231,6 +240,7 @@ static void upload_csr(cpc_solver* h, const HostCsr& a, DevCsr& d, bool with_dpo
     d.dpos = dupload(dp, own, h->stream);
   }
   d.tpr = pick_tpr(a.n ? (double)d.nnz / a.n : 1.0);
+  d.steps = pick_steps(a.n ? (double)d.nnz / a.n : 1.0, d.tpr);
   if (h->f32 && with_f32) {
     d.v32 = dalloc<float>((size_t)d.nnz, own);
     launch_to_f32(h->stream, d.nnz, d.v, d.v32);
@@ -908,6 +918,16 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   try {
     upload_csr(h, lo, L.bd_Loff, false, &own);
     upload_csr(h, up, L.bd_Uoff, false, &own);
+    // one block's off-block product is a small launch that ends with its longest row:
+    // lanes enough for that row to take a single batch of four entries per lane
+    for (auto* m : {&lo, &up}) {
+      int longest = 0;
+      for (int i = 0; i < m->n; ++i) longest = std::max(longest, m->rp[i + 1] - m->rp[i]);
+      DevCsr& d = m == &lo ? L.bd_Loff : L.bd_Uoff;
+      d.tpr = 1;
+      while (d.tpr < 64 && 4 * d.tpr < longest) d.tpr <<= 1;
+      d.steps = 4;
+    }
     DenseTriDev& dt = L.bd_dt;
     dt = DenseTriDev{};
     dt.n = dupload(nbs, own, h->stream);
