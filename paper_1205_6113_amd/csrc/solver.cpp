@@ -1073,8 +1073,11 @@ static void tune_sweeps(cpc_solver* h) {
     progress(h, "level " + std::to_string(d) + (skip_r ? ": block substitution well ahead, sweep block size kept"
                                                         : ": timing sweep block sizes"));
     float best = try_r && !skip_r ? cost() : 0.f;
-    for (int R : {1024, 2048, 4096, 8192}) {
+    // 1024 .. 8192, then halving below 1024 for as long as the smallest one wins (the
+    // wide coarse stencils of L1 favour short blocks)
+    for (int R : {1024, 2048, 4096, 8192, 512, 256}) {
       if (!try_r || skip_r || R == L.sweep_R || R >= L.sweep_rows) continue;
+      if (R < 1024 && L.sweep_R != 2 * R) continue;
       // keep the current build aside, try the candidate in a list of its own
       DevSweepSched lo = L.lower, up = L.upper;
       SweepPackDev fg = L.fgs, bg = L.bgs, il = h->ilu_l, iu = h->ilu_u;
