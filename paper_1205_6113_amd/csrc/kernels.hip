@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kNT = 256;          // threads per workgroup for the streaming kernels
 constexpr int kRedGrid = 1024;    // workgroups of the reduction kernels (grid-stride)
+static_assert(2 * kRedGrid <= kPartials, "the initial residual's two reductions share the partials");
 
 template <typename T>
 __device__ __forceinline__ double ld(const T* p, long i) {
@@ -362,6 +363,8 @@ bool launch_spmv(hipStream_t s, const MatDev& A, int mode, const void* x, bool x
 void launch_spmv_pq(hipStream_t s, const MatDev& A, const double* p, double* q, double* partials, PcgState* stt,
                     int tpr) {
   const int rpb = kNT / tpr;
+  // at most kRedGrid workgroups: each one's arrival is a fence and an atomic on one
+  // counter, which serialise (4096 workgroups took twice as long on the finest level)
   const int grid = grid_for(A.n, rpb, kRedGrid);
 #define CPC_PQ_CALL(T) \
   spmv_pq_kernel<T><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const double*)A.v, p, q, partials, stt)

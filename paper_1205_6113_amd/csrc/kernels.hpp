@@ -10,6 +10,10 @@
 namespace cpc {
 
 // Scalars of one PCG run, kept on the device so that no iteration needs the host.
+// Entries of the PCG's partial-sum buffer: the grid of a last-workgroup reduction is at
+// most this (two reductions of at most half of it share the buffer in the first step).
+constexpr int kPartials = 4096;
+
 struct PcgState {
   double rz;      // <r, z> of the current iterate
   double pq;      // <p, A p>

@@ -1325,7 +1325,7 @@ static void allocate_work(cpc_solver* h) {
   h->w = valloc(h, n);
   h->t = valloc(h, n);
   h->st = dalloc<PcgState>(1, h->owned);
-  h->partials = dalloc<double>(4096, h->owned);
+  h->partials = dalloc<double>(kPartials, h->owned);
   h->sync.ticket = dalloc<unsigned>(1, h->owned);
   h->sync.exited = dalloc<unsigned>(1, h->owned);
   h->sync.err = dalloc<unsigned>(1, h->owned);
