@@ -133,7 +133,10 @@ void cpc_default_options(cpc_options* opt);
 cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const double* val,
                      const cpc_options* opt, void* hip_stream, cpc_handle* out);
 
-/* SOLVE: PCG (preconditioner from the options) for A x = b.
+/* SOLVE: preconditioned conjugate gradients (Section 2, the PCG of eq. 2.1 with the
+ * preconditioner of Algorithm 2.1 by default, else the one the options name) for
+ * A x = b, stopped on the relative residual as in the experiments of Section 5
+ * (Table 5.2: relative residual below a tolerance, a cap on the iterations).
  *   b_dev, x_dev : device FP64 vectors of length n. x_dev is read as the initial
  *                  guess when use_x0 != 0, otherwise overwritten from 0.
  *   tol          : stop when ||r_k||_2 / ||b||_2 <= tol (recursively updated r_k;
@@ -152,12 +155,17 @@ cpc_status cpc_solve_with(cpc_handle h, int32_t prec, const double* b_dev, doubl
 /* z_dev = M r_dev for the operator `op` (cpc_op), device FP64 vectors of length n. */
 cpc_status cpc_apply_op(cpc_handle h, int32_t op, const double* r_dev, double* z_dev);
 
-/* y_dev = A_l x_dev on level `level` (0 = finest); device FP64 vectors of length n_l. */
+/* y_dev = A_l x_dev on level `level` of the hierarchy (0 = finest, A_0 = A; coarser
+ * levels are the Galerkin products A_{l+1} = P_l^T A_l P_l of Section 3.2, Algorithm
+ * 3.2); device FP64 vectors of length n_l. CPC_E_ARG for a level out of range. */
 cpc_status cpc_spmv(cpc_handle h, int32_t level, const double* x_dev, double* y_dev);
 
-/* Hierarchy description. Caller arrays hold at least max_levels entries:
- * n_l[l], nnz_l[l] for each level l (0 = finest); depth_l[l] = number of
- * level sets of the lower-triangular dependency graph of A_l. */
+/* Description of the AMG hierarchy the SETUP built (Section 3.2: classical
+ * coarsening, Galerkin coarse matrices, coarsest level solved exactly). Caller host
+ * arrays hold at least max_levels entries: *nlev = number of levels; n_l[l], nnz_l[l]
+ * for each level l (0 = finest); depth_l[l] = number of level sets of the
+ * lower-triangular dependency graph of A_l (the dependent steps of one natural-order
+ * Gauss-Seidel sweep of Algorithm 3.2). Null arrays are skipped. */
 cpc_status cpc_hierarchy_info(cpc_handle h, int32_t* nlev, int32_t* n_l, int64_t* nnz_l, int32_t* depth_l);
 
 /* How the Gauss-Seidel smoother of Algorithm 3.2 is applied on level `level`:
