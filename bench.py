@@ -5,9 +5,13 @@
 A step is one whole solve (PCG with the combined ILU(0) + AMG preconditioner, the
 complete hot path) of the 3-D 128x128x64 TPFA pressure system to relative residual
 1e-8, with the matrix hierarchy and the right-hand side already resident in HBM.
-value = algorithmic HBM bytes of one solve / solve time (GB/s); ms_per_step = solve
-time. The roofline object is for the kernel that dominates the solve time; the CPU
-baseline is the oracle solving the same system on the host.
+value = the method's bytes of one solve / solve time (GB/s): every matrix read once
+per pass the algorithm makes over it, every vector read or written once per step,
+whatever form evaluates a Gauss-Seidel sweep; ms_per_step = solve time. The roofline
+object is for the kernel family that takes the most time per iteration, measured
+live; the same system is also solved with the FP32 preconditioner (speedup and error
+against the FP64 oracle); the CPU baseline is the oracle solving the system on the
+host.
 """
 from __future__ import annotations
 
@@ -22,12 +26,25 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
-# kernel reported in the roofline object (the kernel that dominates the solve time in
-# the committed kernel-trace summary) and the committed traffic counters for it
-ROOFLINE_KERNEL = "dense_gemv"
-ROOFLINE_NAME = "gemv_tri_rows_kernel"
-TRAFFIC_FILE = ROOT / "profiles" / "traffic_gemv_tri_rows_c2.txt"
-KERNEL_SOURCE = ROOT / "paper_1205_6113_amd" / "csrc" / "dense_tri.hip"
+# candidates for the roofline object: the two families that hold most of the solve
+# time (level-scheduled triangular sweeps, explicit-inverse products), with the kernel
+# each launches, its source and the committed counter passes for it
+FAMILIES = {
+    "sweep": {"kernel": "tri_sweep_kernel", "source": "sweep.hip",
+              "what": "level-scheduled triangular solves: forward/backward Gauss-Seidel sweeps on the levels "
+                      "smoothed that way (both V-cycles) and the ILU(0) L and U solves of one PCG iteration"},
+    "dense_gemv": {"kernel": "gemv_tri_rows_kernel", "source": "dense_tri.hip",
+                   "what": "products with the explicit inverses of D+L or of its diagonal blocks, both "
+                           "directions, every level smoothed that way (one V-cycle)"},
+}
+# other families reported with their method GB/s (one V-cycle's launches, or one PCG
+# step for the finest-level product)
+OTHER_FAMILIES = ["spmv_pq", "residual", "restrict", "prolong"]
+CSRC = ROOT / "paper_1205_6113_amd" / "csrc"
+
+
+def traffic_file(kernel: str) -> Path:
+    return ROOT / "profiles" / f"traffic_{kernel}_c2.txt"
 
 
 def log(msg):
@@ -106,11 +123,31 @@ def bench_batch(args):
         s1.close()
     seq_ms *= len(probs) / len(sample)
     log(f"sequential: {seq_ms:.1f} ms for the {len(probs)} single-system solves (from {len(sample)} of them)")
-    # the batched preconditioner runs over every system until the last one stops
-    bytes_batch = stats["bytes_per_iter"] * int(its.max()) + stats["bytes_initial"]
+    # method bytes: each system's own iterations (the per-iteration figure of the batch
+    # is the sum over systems, so weight it by the systems' share of the unknowns); the
+    # forms' bytes: the batched preconditioner runs over every system until the last stops
+    ns = np.array([p.n for p in probs], dtype=np.float64)
+    it_w = float((ns * its.astype(np.float64)).sum() / ns.sum())
+    method_batch = stats["method_bytes_per_iter"] * it_w + stats["method_bytes_initial"]
+    form_batch = stats["bytes_per_iter"] * int(its.max()) + stats["bytes_initial"]
+    # x against the oracle on a sample of the systems (smallest, median, largest)
+    order = np.argsort(ns)
+    osample = sorted({int(order[0]), int(order[len(order) // 2]), int(order[-1])})
+    oerr = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        for k in osample:
+            p = probs[k]
+            log(f"oracle system {k}: n={p.n}")
+            hk = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
+            rk = hk.pcg(oracle.PREC_COMBINED, p.b, tol, 1000)
+            xb = x[offs[k]:offs[k] + p.n].cpu().numpy()
+            oerr[k] = {"n": p.n, "iters_oracle": int(rk["iters"]), "iters_batch": int(its[k]),
+                       "x_relerr": float(np.linalg.norm(xb - rk["x"]) / np.linalg.norm(rk["x"]))}
+            log(f"oracle system {k}: {oerr[k]}")
     out = {
         "metric": "combined-PCG solve s + HBM GB/s to 1e-8 rel res; FP32-precond vs FP64",
-        "value": round(bytes_batch / (ms_batch / 1000.0) / 1e9, 3) if bytes_batch else None,
+        "value": round(method_batch / (ms_batch / 1000.0) / 1e9, 3),
         "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_batch, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
@@ -122,7 +159,9 @@ def bench_batch(args):
                    "relres_max": float(rels.max()), "sequential_ms": round(seq_ms, 3),
                    "sequential_sample": f"every 4th system ({len(sample)}), scaled by {len(probs) / len(sample):g}",
                    "speedup_vs_sequential": round(seq_ms / ms_batch, 3),
-                   "x_relerr_batch_vs_single_max": max(errs)},
+                   "x_relerr_batch_vs_single_max": max(errs),
+                   "method_bytes_per_batch_solve": method_batch, "form_bytes_per_batch_solve": form_batch,
+                   "oracle_sample": oerr},
     }
     print(json.dumps(out), flush=True)
     bs.close()
@@ -247,8 +286,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-reps", type=int, default=5)
-    ap.add_argument("--compare-precision", action="store_true",
-                    help="also solve in the other precision and report speedup and solution difference")
+    ap.add_argument("--no-compare-precision", action="store_true",
+                    help="skip the solve with the preconditioner in the other precision")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="copy MB megabytes device to device once (a plain copy of known size for "
                          "calibrating memory counters)")
@@ -296,35 +335,55 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1000.0 * elapsed / args.steps
     stats = solver.stats()
-    bytes_solve = stats["bytes_per_iter"] * it + stats["bytes_initial"]
-    value = bytes_solve / (ms_per_step / 1000.0) / 1e9
-    log(f"timed {args.steps} solves: {ms_per_step:.3f} ms/solve iters={it} relres={rel:.3e} -> {value:.1f} GB/s")
+    method_solve = stats["method_bytes_per_iter"] * it + stats["method_bytes_initial"]
+    form_solve = stats["bytes_per_iter"] * it + stats["bytes_initial"]
+    value = method_solve / (ms_per_step / 1000.0) / 1e9
+    log(f"timed {args.steps} solves: {ms_per_step:.3f} ms/solve iters={it} relres={rel:.3e} -> {value:.1f} GB/s "
+        f"(method bytes {method_solve / 1e9:.2f} GB; the forms the setup chose move {form_solve / 1e9:.2f} GB)")
 
-    # roofline of the dominant kernel family (HIP events on the solver's stream)
-    tk = solver.time_kernel(ROOFLINE_KERNEL, level=-1, reps=args.roofline_reps)
-    achieved = tk["bytes"] / (tk["avg_ms"] / 1000.0) / 1e9
+    # kernel families, timed live on the solver's stream (HIP events); per iteration the
+    # sweep mix runs once, the V-cycle families twice (two V-cycles per B_co application)
+    fam = {}
+    for name in list(FAMILIES) + OTHER_FAMILIES:
+        try:
+            tk = solver.time_kernel(name, level=-1, reps=args.roofline_reps)
+        except Exception as e:  # a family the chosen forms do not use
+            log(f"family {name}: not timed ({e})")
+            continue
+        per_rep = tk["launches"] / args.roofline_reps
+        reps_per_iter = 1 if name in ("sweep", "spmv_pq") else 2
+        fam[name] = {"avg_launch_us": round(1000.0 * tk["avg_ms"], 3), "launches_per_iter": per_rep * reps_per_iter,
+                     "ms_per_iter": round(tk["avg_ms"] * per_rep * reps_per_iter, 4),
+                     "method_bytes_per_launch": tk["bytes"], "form_bytes_per_launch": tk["form_bytes"],
+                     "method_gbs": round(tk["bytes"] / (tk["avg_ms"] / 1000.0) / 1e9, 2),
+                     "form_gbs": round(tk["form_bytes"] / (tk["avg_ms"] / 1000.0) / 1e9, 2),
+                     "launches_timed": tk["launches"]}
+        log(f"family {name}: {fam[name]}")
+    dom = max((k for k in FAMILIES if k in fam), key=lambda k: fam[k]["ms_per_iter"])
+    fd = fam[dom]
+    achieved = fd["method_gbs"]
     # counted HBM bytes per launch from the committed rocprofv3 counter passes, only if
     # they were taken on this workload, precision and kernel source
     traffic = None
-    if TRAFFIC_FILE.exists():
+    tf = traffic_file(FAMILIES[dom]["kernel"])
+    if tf.exists():
         try:
             import hashlib
-            tr = json.loads(TRAFFIC_FILE.read_text())
-            src = hashlib.sha256(KERNEL_SOURCE.read_bytes()).hexdigest()
+            tr = json.loads(tf.read_text())
+            src = hashlib.sha256((CSRC / FAMILIES[dom]["source"]).read_bytes()).hexdigest()
             if (tr.get("workload") == args.workload and tr.get("precision") == args.precision
                     and tr.get("kernel_source_sha256") == src):
                 traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": f"{ROOFLINE_NAME} (products with the explicit inverses of D+L or of its diagonal "
-                          "blocks, both directions, every level smoothed that way)",
-                "avg_launch_us": round(1000.0 * tk["avg_ms"], 3), "bytes_per_launch": tk["bytes"],
-                "launches_timed": tk["launches"]}
-    log(f"roofline {ROOFLINE_KERNEL}: {1000 * tk['avg_ms']:.2f} us/launch, {tk['bytes'] / 1e6:.2f} MB/launch "
-        f"-> {achieved:.1f} GB/s")
-    # after the roofline launches, so that the copy's write-backs do not land on them
+                "kernel": f"{FAMILIES[dom]['kernel']} ({FAMILIES[dom]['what']})",
+                "avg_launch_us": fd["avg_launch_us"], "bytes_per_launch": fd["method_bytes_per_launch"],
+                "form_bytes_per_launch": fd["form_bytes_per_launch"], "launches_timed": fd["launches_timed"]}
+    log(f"roofline {dom}: {fd['avg_launch_us']:.2f} us/launch, {fd['method_bytes_per_launch'] / 1e6:.3f} MB "
+        f"method bytes/launch -> {achieved:.1f} GB/s")
+    # after the timed launches, so that the copy's write-backs do not land on them
     if args.copy_calibration > 0:
         nbytes = args.copy_calibration * (1 << 20)
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
@@ -335,10 +394,14 @@ def main():
         log(f"calibration copy of {nbytes} bytes")
         del src, dst
 
+    # the same system with the preconditioner in the other precision
     compare = None
-    if args.compare_precision:
+    x_other = None
+    if not args.no_compare_precision:
         other = "fp64" if args.precision == "fp32" else "fp32"
-        s2 = cpc.Solver(p.n, p.row_ptr, p.col, p.val, device=dev, precision=other)
+        t0 = time.perf_counter()
+        s2 = cpc.Solver(p.n, p.row_ptr, p.col, p.val, device=dev, precision=other, tune=not args.rules)
+        setup2 = time.perf_counter() - t0
         x2 = torch.zeros_like(b)
         for w in range(args.warmup):
             x2, it2, rel2, st2 = s2.solve(b, x=x2, tol=p.tol, maxit=10000)
@@ -348,9 +411,13 @@ def main():
             x2, it2, rel2, st2 = s2.solve(b, x=x2, tol=p.tol, maxit=10000)
         torch.cuda.synchronize()
         ms2 = 1000.0 * (time.perf_counter() - t0) / args.steps
+        st2s = s2.stats()
+        m2 = st2s["method_bytes_per_iter"] * it2 + st2s["method_bytes_initial"]
         x64, x32 = (x2, x) if other == "fp64" else (x, x2)
+        x_other = x2
         diff = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
         compare = {"precision": other, "ms_per_solve": round(ms2, 4), "iters": it2, "relres": rel2,
+                   "setup_s": round(setup2, 3), "method_gbs": round(m2 / (ms2 / 1000.0) / 1e9, 3),
                    "speedup_fp32_vs_fp64": round((ms2 / ms_per_step) if other == "fp64" else (ms_per_step / ms2), 4),
                    "x_relerr_fp32_vs_fp64": diff}
         log(f"{other}: {ms2:.3f} ms/solve iters={it2}; fp32 vs fp64 solution {diff:.2e}")
@@ -372,22 +439,37 @@ def main():
         "config": {"workload": desc, "n": p.n, "nnz": p.nnz, "iters": it, "relres": rel,
                    "solve_s": round(ms_per_step / 1000.0, 6), "setup_s": round(setup_s, 3),
                    "levels": info["nlev"], "level_n": info["n"], "level_nnz": info["nnz"],
-                   "bytes_per_solve": bytes_solve, "precision": args.precision},
+                   "level_depth": info["depth"], "level_smoother": info["smoother"],
+                   "level_block_rows": info["block_rows"],
+                   "method_bytes_per_solve": method_solve, "form_bytes_per_solve": form_solve,
+                   "precision": args.precision},
         "roofline": roofline,
+        "families": fam,
     }
     if compare:
         out["config"]["compare"] = compare
     if not args.no_cpu_baseline:
         h, r, osetup, osolve, _ = cpu_baseline(p, it)
-        ob = stats["bytes_per_iter"] * r["iters"] + stats["bytes_initial"]
+        ob = stats["method_bytes_per_iter"] * r["iters"] + stats["method_bytes_initial"]
+        if args.precision != "fp64":
+            ob = None  # the oracle runs in FP64: its bytes are those of the FP64 method
         xo = r["x"]
         err = float(np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
-        out["cpu_baseline"] = {"value": round(ob / osolve / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": round(ob / osolve / 1e9, 4) if ob else None, "unit": "GB/s", "cores": 1,
+                               "kind": "oracle",
                                "sample": f"one full solve of the same workload to 1e-8 on the host (setup "
-                                         f"{osetup:.1f}s untimed); solve {osolve:.2f}s, {r['iters']} iterations",
-                               "solve_s": round(osolve, 3), "iters": r["iters"],
+                                         f"{osetup:.1f}s untimed); solve {osolve:.2f}s, {r['iters']} iterations; "
+                                         f"GB/s on the method bytes of the FP64 solve",
+                               "solve_s": round(osolve, 3), "setup_s": round(osetup, 3), "iters": r["iters"],
                                "host_cpus": os.cpu_count()}
         out["config"]["x_relerr_vs_oracle"] = err
+        if compare and x_other is not None:
+            xc = x_other.cpu().numpy()
+            compare[f"x_relerr_{compare['precision']}_vs_fp64_oracle"] = float(np.linalg.norm(xc - xo) /
+                                                                               np.linalg.norm(xo))
+            import scipy.sparse as sp
+            A = sp.csr_matrix((p.val, p.col, p.row_ptr), shape=(p.n, p.n))
+            compare["true_relres"] = float(np.linalg.norm(p.b - A @ xc) / np.linalg.norm(p.b))
         log(f"oracle: {osolve:.2f}s {r['iters']} iters; GPU x vs oracle {err:.2e}")
     print(json.dumps(out), flush=True)
     solver.close()

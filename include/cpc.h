@@ -114,8 +114,14 @@ typedef struct {
   double relres;          /* ||r_k||/||b|| of the recursively updated residual at exit     */
   double setup_s;         /* wall seconds of cpc_setup                                      */
   double solve_s;         /* wall seconds of the last cpc_solve (device-synchronised)       */
-  double bytes_per_iter;  /* algorithmic HBM bytes of one PCG iteration (byte model)        */
-  double bytes_initial;   /* algorithmic bytes before the first iteration                   */
+  double bytes_per_iter;  /* HBM bytes one PCG iteration's kernels move in the forms the setup
+                             chose (an explicit inverse reads its whole triangle)           */
+  double bytes_initial;   /* the same before the first iteration                            */
+  double method_bytes_per_iter; /* bytes the method itself must move in one PCG iteration:
+                             every matrix read once per pass the algorithm makes (value +
+                             4-byte column, 4-byte row pointer), every vector read or written
+                             once per step, whatever form evaluates a Gauss-Seidel sweep    */
+  double method_bytes_initial;  /* the same before the first iteration                     */
 } cpc_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -249,22 +255,33 @@ typedef enum {
   CPC_K_VCYCLE = 8,    /* one whole V-cycle                                                 */
   CPC_K_PRECOND = 9,   /* one application of the handle's preconditioner                    */
   CPC_K_ITERATION = 10, /* one whole PCG iteration                                          */
-  CPC_K_DENSE_GEMV = 11 /* products with explicit inverses of D+L or of its diagonal blocks
+  CPC_K_DENSE_GEMV = 11, /* products with explicit inverses of D+L or of its diagonal blocks
                            (both directions), one launch per block and direction            */
+  CPC_K_SWEEP = 12     /* every level-scheduled triangular solve of one combined-
+                           preconditioner iteration: the forward and backward Gauss-Seidel
+                           sweeps of both V-cycles on each level smoothed that way, then
+                           the ILU(0) L and U solves (the mix a PCG iteration launches)    */
 } cpc_kernel;
 
 /* Measurement helper (not needed to solve): runs `reps` repetitions of the kernel
- * family `kernel` (cpc_kernel) on the handle's current work vectors and reports the
- * mean duration of one launch (HIP events recorded on the handle's stream around all
- * repetitions, around each launch for the triangular solves, or around a captured
- * graph of all of them replayed reps times for the dense products,
- * ms), the algorithmic HBM bytes of one launch (the byte model: matrix
- * streams read once, vectors read or written once per launch) and the number of
- * launches timed. level >= 0 selects one level; level = -1 takes every level the
- * family runs on in one V-cycle, one launch per level per repetition (the averages
- * are then over that mix). Work vectors are overwritten. */
+ * family `kernel` (cpc_kernel) on the handle's current work vectors and reports:
+ *   avg_ms                : mean duration of one launch (HIP events recorded on the
+ *                           handle's stream around all repetitions, around each launch
+ *                           for the triangular solves, or around a captured graph of all
+ *                           of them replayed reps times for the dense products);
+ *   bytes_per_launch      : the method's bytes for the work of one launch: each matrix
+ *                           read once per pass the algorithm makes over it (value + 4-byte
+ *                           column, 4-byte row pointer), each vector read or written once
+ *                           (a Gauss-Seidel sweep counts its triangle, however evaluated;
+ *                           the dense products share the sweeps they evaluate evenly);
+ *   launches              : the number of launches timed;
+ *   form_bytes_per_launch : the bytes the evaluated form itself moves (an explicit
+ *                           inverse reads its stored triangle); may be NULL.
+ * level >= 0 selects one level; level = -1 takes every level the family runs on in
+ * one V-cycle (one PCG iteration for CPC_K_SWEEP), one launch per level per
+ * repetition (the averages are then over that mix). Work vectors are overwritten. */
 cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t reps, double* avg_ms,
-                           double* bytes_per_launch, int32_t* launches);
+                           double* bytes_per_launch, int32_t* launches, double* form_bytes_per_launch);
 
 /* ---- Batched form: independent systems of different sizes solved together ------
  * cpc_setup_batch builds each system's own hierarchy (exactly what cpc_setup would

@@ -27,7 +27,7 @@ EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "c
            "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values", "cpc_setup_batch",
            "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind", "cpc_get_ilu_factor")
 KERNEL = {"spmv_pq": 0, "fgs": 1, "bgs": 2, "ilu_l": 3, "ilu_u": 4, "residual": 5, "restrict": 6, "prolong": 7,
-          "vcycle": 8, "precond": 9, "iteration": 10, "dense_gemv": 11}
+          "vcycle": 8, "precond": 9, "iteration": 10, "dense_gemv": 11, "sweep": 12}
 
 
 class Options(ctypes.Structure):
@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres", ctypes.c_double),
                 ("setup_s", ctypes.c_double), ("solve_s", ctypes.c_double), ("bytes_per_iter", ctypes.c_double),
-                ("bytes_initial", ctypes.c_double)]
+                ("bytes_initial", ctypes.c_double), ("method_bytes_per_iter", ctypes.c_double),
+                ("method_bytes_initial", ctypes.c_double)]
 
 
 class CpcError(RuntimeError):
@@ -94,7 +95,8 @@ def load():
     lib.cpc_get_stats.restype = I32
     lib.cpc_neg_outer_on_pattern.argtypes = [P, P, P, P]
     lib.cpc_neg_outer_on_pattern.restype = I32
-    lib.cpc_time_kernel.argtypes = [P, I32, I32, I32, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32)]
+    lib.cpc_time_kernel.argtypes = [P, I32, I32, I32, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I32),
+                                    ctypes.POINTER(D)]
     lib.cpc_time_kernel.restype = I32
     lib.cpc_tpfa_pattern.argtypes = [I32, I32, I32, P, P]
     lib.cpc_tpfa_pattern.restype = I32

@@ -1689,6 +1689,130 @@ static double iteration_bytes(const cpc_solver* h, int prec) {
   return pcg + prec_bytes(h, prec);
 }
 
+// ---------------------------------------------------------------------------
+// Method bytes: what the method itself must move, whatever form evaluates a step.
+// Every matrix stream is read once per pass the algorithm makes over it (an entry is
+// its value and its 4-byte column, a row its 4-byte pointer) and every vector is read
+// or written once per step. A natural-order Gauss-Seidel sweep from zero reads the
+// lower triangle with the diagonal; the in-place backward sweep reads whole rows and
+// the old and new values; ILU(0)'s triangular solves read L (strictly lower) and U
+// (upper with the diagonal). FP32 preconditioner data: 4-byte values and vectors.
+// These do not depend on how a sweep is evaluated (level-scheduled, block
+// substitution or explicit inverse), so they rate every form against one yardstick.
+struct MethodUnits {
+  double E;  // bytes of one matrix entry of the preconditioner (value + column)
+  double V;  // bytes of one preconditioner vector element
+};
+
+static MethodUnits method_units(const cpc_solver* h) {
+  return h->f32 ? MethodUnits{8.0, 4.0} : MethodUnits{12.0, 8.0};
+}
+
+// forward Gauss-Seidel from zero on n rows, nz entries: lower triangle + diagonal,
+// row pointers, f read, x written
+static double m_fgs(const MethodUnits& u, double nz, double n) { return u.E * 0.5 * (nz + n) + 4.0 * n + 2.0 * u.V * n; }
+// backward Gauss-Seidel in place: whole rows, f read, old x read, new x written
+static double m_bgs(const MethodUnits& u, double nz, double n) { return u.E * nz + 4.0 * n + 3.0 * u.V * n; }
+// residual f - A u on the level: whole rows, u and f read, r written
+static double m_res(const MethodUnits& u, double nz, double n) { return u.E * nz + 4.0 * n + 3.0 * u.V * n; }
+// f_c = R r (R = P^T with p entries, nc rows) and u += P e
+static double m_restrict(const MethodUnits& u, double p, double n, double nc) {
+  return u.E * p + 4.0 * nc + u.V * n + u.V * nc;
+}
+static double m_prolong(const MethodUnits& u, double p, double n, double nc) {
+  return u.E * p + 4.0 * n + 2.0 * u.V * n + u.V * nc;
+}
+
+// one V-cycle (Algorithm 3.2) over the whole hierarchy
+static double method_vcycle_bytes(const cpc_solver* h) {
+  const MethodUnits u = method_units(h);
+  double b = 0.0;
+  for (size_t d = 0; d < h->lev.size(); ++d) {
+    const Level& L = h->lev[d];
+    if (L.nS > 0 && d + 1 < h->lev.size()) {
+      const double nz = (double)L.nnzS, n = L.nS, nc = h->lev[d + 1].A.n, p = (double)L.P.nnz;
+      b += m_fgs(u, nz, n) + m_res(u, nz, n) + m_restrict(u, p, n, nc) + m_prolong(u, p, n, nc) + m_bgs(u, nz, n);
+    }
+    for (int n0 : L.dense_n) b += 8.0 * n0 * n0 + 2.0 * u.V * n0;  // exact coarsest solve
+  }
+  return b;
+}
+
+// ILU solves: L strictly lower (unit diagonal implied), U with the diagonal; `axpy`:
+// the U-solve also reads u1 and writes u2 = u1 + w (step 2 of Algorithm 2.1)
+static double method_ilu_bytes(const cpc_solver* h, bool axpy) {
+  const MethodUnits u = method_units(h);
+  const double nz = (double)h->lev[0].A.nnz, n = h->n;
+  const double lo = h->iluk ? h->ilu_lnnz : 0.5 * (nz - n), up = h->iluk ? h->ilu_unnz : 0.5 * (nz + n);
+  return (u.E * lo + 4.0 * n + 2.0 * u.V * n) + (u.E * up + 4.0 * n + (axpy ? 3.0 : 2.0) * u.V * n);
+}
+
+static double method_prec_bytes(const cpc_solver* h, int prec) {
+  const MethodUnits u = method_units(h);
+  const double nz = (double)h->lev[0].A.nnz, n = h->n;
+  const double outer = 12.0 * nz + 4.0 * n + 8.0 * n + 2.0 * u.V * n;  // FP64 r - A u
+  const double add = (2.0 * u.V + 8.0) * n;                             // z = a + b
+  const double V = method_vcycle_bytes(h);
+  switch (prec) {
+    case CPC_PREC_COMBINED: return V + outer + method_ilu_bytes(h, true) + outer + V + add;
+    case CPC_PREC_AMG: return V + outer + V + add;
+    case CPC_PREC_ILU: return method_ilu_bytes(h, false);
+    case CPC_PREC_ADDITIVE: return 2.0 * V + outer + add + method_ilu_bytes(h, false) + add;
+    case CPC_PREC_AMG_ILU: {
+      // the finest level's Gauss-Seidel pair of each cycle becomes ILU(0) before and after
+      // the coarse correction (post: residual, ILU solves, u += w)
+      const Level& L0 = h->lev[0];
+      double fine_gs = 0.0;
+      if (L0.nS > 0 && h->lev.size() > 1) fine_gs = m_fgs(u, (double)L0.nnzS, L0.nS) + m_bgs(u, (double)L0.nnzS, L0.nS);
+      const double Vi = V - fine_gs + 2.0 * method_ilu_bytes(h, false) + m_res(u, nz, n) + 3.0 * u.V * n;
+      return Vi + outer + Vi + add;
+    }
+    case CPC_PREC_BBAR:
+      return method_ilu_bytes(h, false) + outer + V + add + outer + V + add + outer + method_ilu_bytes(h, false) + add;
+    default: return 16.0 * n;
+  }
+}
+
+// PCG's own steps (FP64): q = A p with <p,q>, x and r updates with ||r||^2, <r,z>, p update
+static double method_pcg_bytes(const cpc_solver* h) {
+  const double nz = (double)h->lev[0].A.nnz, n = h->n;
+  return (12.0 * nz + 4.0 * n + 16.0 * n) + 48.0 * n + 16.0 * n + 24.0 * n;
+}
+
+static double method_iteration_bytes(const cpc_solver* h, int prec) {
+  return method_pcg_bytes(h) + method_prec_bytes(h, prec);
+}
+
+// before the first iteration: r = b - A x0 (or r = b), z = B r, <r,z>, p = z
+static double method_initial_bytes(const cpc_solver* h, int prec) {
+  const double nz = (double)h->lev[0].A.nnz, n = h->n;
+  return (12.0 * nz + 28.0 * n) + method_prec_bytes(h, prec) + 16.0 * n + 16.0 * n;
+}
+
+// Method bytes of one launch of a kernel family on level d (the §(d)-style per-kernel
+// figures; the backward Gauss-Seidel family is the triangular (D+U) solve, the strict
+// lower pass over the old values being a separate SpMV).
+static double method_kernel_bytes(const cpc_solver* h, int kernel, int d) {
+  const MethodUnits u = method_units(h);
+  const Level& L = h->lev[d];
+  const bool fine = (kernel == CPC_K_SPMV_PQ || kernel == CPC_K_ILU_L || kernel == CPC_K_ILU_U);
+  const double nz = fine ? (double)L.A.nnz : (double)L.nnzS, n = fine ? (double)L.A.n : (double)L.nS;
+  const double nc = (d + 1 < (int)h->lev.size()) ? (double)h->lev[d + 1].A.n : 0.0;
+  const double p = (double)L.P.nnz;
+  const double lo = h->iluk ? h->ilu_lnnz : 0.5 * (nz - n), up = h->iluk ? h->ilu_unnz : 0.5 * (nz + n);
+  switch (kernel) {
+    case CPC_K_SPMV_PQ: return 12.0 * nz + 20.0 * n;
+    case CPC_K_FGS: return m_fgs(u, nz, n);
+    case CPC_K_BGS: return m_fgs(u, nz, n);  // (D+U) solve: upper triangle + diagonal, t read, u written
+    case CPC_K_ILU_L: return u.E * lo + 4.0 * n + 2.0 * u.V * n;
+    case CPC_K_ILU_U: return u.E * up + 4.0 * n + 3.0 * u.V * n;
+    case CPC_K_RESIDUAL: return m_res(u, nz, n);
+    case CPC_K_RESTRICT: return m_restrict(u, p, n, nc);
+    case CPC_K_PROLONG: return m_prolong(u, p, n, nc);
+    default: return 0.0;
+  }
+}
+
 static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x, int use_x0, double tol, int maxit,
                             int32_t* iters, double* relres) {
   if (!h) return set_err(CPC_E_ARG, "null handle");
@@ -1765,6 +1889,8 @@ static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x,
     h->stats.solve_s = now_s() - t0;
     h->stats.bytes_per_iter = iteration_bytes(h, prec);
     h->stats.bytes_initial = (12.0 * h->lev[0].A.nnz + 40.0 * h->n) + prec_bytes(h, prec) + 24.0 * h->n;
+    h->stats.method_bytes_per_iter = method_iteration_bytes(h, prec);
+    h->stats.method_bytes_initial = method_initial_bytes(h, prec);
     if (iters) *iters = hs.iters;
     if (relres) *relres = hs.relres;
     cpc_status status = CPC_OK;
@@ -1876,6 +2002,8 @@ static cpc_status run_solve_batch(cpc_solver* h, int prec, const double* b, doub
     h->stats.solve_s = now_s() - t0;
     h->stats.bytes_per_iter = iteration_bytes(h, prec);
     h->stats.bytes_initial = (12.0 * h->lev[0].A.nnz + 40.0 * h->n) + prec_bytes(h, prec) + 24.0 * h->n;
+    h->stats.method_bytes_per_iter = method_iteration_bytes(h, prec);
+    h->stats.method_bytes_initial = method_initial_bytes(h, prec);
     if (herr) {
       HIPCHK(hipMemsetAsync(h->sync.err, 0, sizeof(unsigned), h->stream));
       HIPCHK(hipStreamSynchronize(h->stream));
@@ -2237,15 +2365,32 @@ cpc_status cpc_neg_outer_on_pattern(cpc_handle h, const double* lam_dev, const d
 }
 
 cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t reps, double* avg_ms,
-                           double* bytes_per_launch, int32_t* launches) {
+                           double* bytes_per_launch, int32_t* launches, double* form_bytes_per_launch) {
   if (!h) return set_err(CPC_E_ARG, "null handle");
-  if (reps < 1 || kernel < CPC_K_SPMV_PQ || kernel > CPC_K_DENSE_GEMV) return set_err(CPC_E_ARG, "bad kernel or reps");
+  if (reps < 1 || kernel < CPC_K_SPMV_PQ || kernel > CPC_K_SWEEP) return set_err(CPC_E_ARG, "bad kernel or reps");
   const int nlev = (int)h->lev.size();
   const bool per_level = kernel >= CPC_K_FGS && kernel <= CPC_K_PROLONG && kernel != CPC_K_ILU_L &&
                          kernel != CPC_K_ILU_U;
   // levels the family runs on: smoothed levels (all but the coarsest), finest only for ILU/PCG
   std::vector<int> levels;
-  if (per_level) {
+  // (kernel, level) launches of one repetition of the level-scheduled sweep family
+  std::vector<std::pair<int, int>> mix;
+  if (kernel == CPC_K_SWEEP) {
+    // the triangular solves one B_co iteration runs as level-scheduled sweeps: per
+    // smoothed level with sweeps the forward and backward sweep of each of the two
+    // V-cycles, then the ILU(0) L and U solves
+    for (int c = 0; c < 2; ++c)
+      for (int d = 0; d + 1 < nlev; ++d)
+        if (h->lev[d].nS > 0 && !h->lev[d].bdense && !h->lev[d].dense_smooth && (level < 0 || level == d)) {
+          mix.push_back({CPC_K_FGS, d});
+          mix.push_back({CPC_K_BGS, d});
+        }
+    if (level <= 0) {
+      mix.push_back({CPC_K_ILU_L, 0});
+      mix.push_back({CPC_K_ILU_U, 0});
+    }
+    if (mix.empty()) return set_err(CPC_E_ARG, "no level-scheduled sweep on that level");
+  } else if (per_level) {
     if (level >= 0) {
       if (level >= nlev - 1 && !(nlev == 1 && level == 0 && kernel == CPC_K_RESIDUAL))
         return set_err(CPC_E_ARG, "level has no such kernel");
@@ -2262,7 +2407,8 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
     levels.push_back(0);
   }
   const bool f32 = h->f32;
-  const bool tri = kernel == CPC_K_FGS || kernel == CPC_K_BGS || kernel == CPC_K_ILU_L || kernel == CPC_K_ILU_U;
+  const bool tri = kernel == CPC_K_FGS || kernel == CPC_K_BGS || kernel == CPC_K_ILU_L || kernel == CPC_K_ILU_U ||
+                   kernel == CPC_K_SWEEP;
   // triangular solves are timed launch by launch (event pairs); the rest as one span
   std::vector<hipEvent_t> evs;
   bool timing = false;
@@ -2274,12 +2420,11 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
     HIPCHK(hipEventRecord(e, h->stream));
   };
   auto ev_end = ev_begin;
-  auto launch_once = [&](int d) {
+  auto launch_kernel = [&](int kern, int d) {
     Level& L = h->lev[d];
-    const MatDev A = L.A.mat(f32);
     void* f = d == 0 ? h->pin : L.f;
     void* u = d == 0 ? h->u1 : L.u;
-    switch (kernel) {
+    switch (kern) {
       case CPC_K_SPMV_PQ:
         launch_spmv_pq(h->stream, L.A.mat(false), h->p, h->q, h->partials, h->st, L.A.tpr);
         break;
@@ -2356,6 +2501,13 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         break;
     }
   };
+  auto launch_once = [&](int d) {
+    if (kernel == CPC_K_SWEEP) {
+      for (const auto& km : mix) launch_kernel(km.first, km.second);
+    } else {
+      launch_kernel(kernel, d);
+    }
+  };
   if (kernel == CPC_K_DENSE_GEMV) {
     // the dense products of every selected level, both directions, captured once as a
     // graph and replayed reps times between one pair of events (launch gaps kept
@@ -2364,8 +2516,11 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
     hipGraphExec_t ge = nullptr;
     try {
       int count = 0;
-      double bytes = 0.0;
+      double bytes = 0.0, mbytes = 0.0;
       const double eb = f32 ? 4.0 : 8.0, vb = f32 ? 4.0 : 8.0;
+      // the method's share: the forward and backward triangular solves these products
+      // evaluate, spread over their launches
+      for (int d : levels) mbytes += method_kernel_bytes(h, CPC_K_FGS, d) + method_kernel_bytes(h, CPC_K_BGS, d);
       HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
       for (int d : levels) {
         Level& L = h->lev[d];
@@ -2394,7 +2549,8 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
       (void)hipGraphExecDestroy(ge);
       (void)hipGraphDestroy(g);
       if (avg_ms) *avg_ms = ms / count;
-      if (bytes_per_launch) *bytes_per_launch = bytes / count;
+      if (bytes_per_launch) *bytes_per_launch = mbytes / count;
+      if (form_bytes_per_launch) *form_bytes_per_launch = bytes / count;
       if (launches) *launches = reps * count;
       HIPCHK(hipGetLastError());
     } catch (const HipError& e) {
@@ -2406,6 +2562,7 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
     return CPC_OK;
   }
   try {
+    if (kernel == CPC_K_SWEEP) levels.assign(1, 0);  // one repetition = the whole mix
     if (kernel == CPC_K_SPMV_PQ || kernel == CPC_K_ITERATION) {
       // a running state with positive scalars so that nothing returns early
       PcgState s{};
@@ -2432,17 +2589,35 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     evs.clear();
     HIPCHK(hipGetLastError());
-    double b = 0.0;
-    for (int d : levels) {
-      if (kernel <= CPC_K_PROLONG) b += kernel_bytes(h, kernel, d);
-      else if (kernel == CPC_K_VCYCLE) b += vcycle_bytes(h);
-      else if (kernel == CPC_K_PRECOND) b += prec_bytes(h, h->opt.prec);
-      else b += iteration_bytes(h, h->opt.prec);
+    double b = 0.0, fb = 0.0;
+    int per_rep = (int)levels.size();
+    if (kernel == CPC_K_SWEEP) {
+      for (const auto& km : mix) {
+        b += method_kernel_bytes(h, km.first, km.second);
+        fb += kernel_bytes(h, km.first, km.second);
+      }
+      per_rep = (int)mix.size();
+    } else {
+      for (int d : levels) {
+        if (kernel <= CPC_K_PROLONG) {
+          b += method_kernel_bytes(h, kernel, d);
+          fb += kernel_bytes(h, kernel, d);
+        } else if (kernel == CPC_K_VCYCLE) {
+          b += method_vcycle_bytes(h);
+          fb += vcycle_bytes(h);
+        } else if (kernel == CPC_K_PRECOND) {
+          b += method_prec_bytes(h, h->opt.prec);
+          fb += prec_bytes(h, h->opt.prec);
+        } else {
+          b += method_iteration_bytes(h, h->opt.prec);
+          fb += iteration_bytes(h, h->opt.prec);
+        }
+      }
     }
-    const int nl = reps * (int)levels.size();
-    const double bpl = b / levels.size();
+    const int nl = reps * per_rep;
     if (avg_ms) *avg_ms = ms / nl;
-    if (bytes_per_launch) *bytes_per_launch = bpl;
+    if (bytes_per_launch) *bytes_per_launch = b / per_rep;
+    if (form_bytes_per_launch) *form_bytes_per_launch = fb / per_rep;
     if (launches) *launches = nl;
     unsigned herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, h->sync.err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));

@@ -208,10 +208,11 @@ class Solver:
         k = _lib.KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
         ms = ctypes.c_double(0.0)
         b = ctypes.c_double(0.0)
+        fb = ctypes.c_double(0.0)
         nl = ctypes.c_int32(0)
         check(self._lib.cpc_time_kernel(self._h, k, int(level), int(reps), ctypes.byref(ms), ctypes.byref(b),
-                                        ctypes.byref(nl)))
-        return {"avg_ms": ms.value, "bytes": b.value, "launches": nl.value}
+                                        ctypes.byref(nl), ctypes.byref(fb)))
+        return {"avg_ms": ms.value, "bytes": b.value, "form_bytes": fb.value, "launches": nl.value}
 
     def stats(self) -> dict:
         s = _lib.Stats()

@@ -55,3 +55,47 @@ def test_batch_rejects_one_level_system():
     with pytest.raises(cpc.CpcError) as e:
         cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs])
     assert e.value.status == _lib.CPC_E_ARG
+
+
+_MID_REFS = {}
+
+
+def _mid_batch():
+    """Four systems of 27,000-85,184 unknowns: every level 0 is split into several sweep
+    blocks, and the coarse levels reach the block-substitution and explicit-inverse
+    forms, as the systems of the 64-system workload do."""
+    probs = gen.config4(sizes=[36, 44, 30, 40])
+    if not _MID_REFS:
+        for s, p in enumerate(probs):
+            h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
+            _MID_REFS[s] = h.pcg(oracle.PREC_COMBINED, p.b, p.tol, 1000)
+    return probs, _MID_REFS
+
+
+@pytest.mark.parametrize("forms", ["never", "block", "auto"])
+def test_batch_mid_size_systems_every_smoother_form(forms):
+    """Per-system iteration counts equal to the oracle's and x within 1e-10 (equal
+    counts under the same stopping rule put both at the oracle's iteration count), with
+    the Gauss-Seidel smoother forced to level-scheduled sweeps, to block substitution,
+    or left to the setup tuner; the forms each level got are checked."""
+    import paper_1205_6113_amd as cpc
+    probs, refs = _mid_batch()
+    print(f"[case] batch forms={forms} sizes={[p.n for p in probs]}", flush=True)
+    b = torch.as_tensor(np.concatenate([p.b for p in probs]), device="cuda")
+    with cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs], dense_smoother=forms) as bs:
+        info = bs.hierarchy()
+        smoothed = [k for k in info["smoother"] if k != "none"]
+        if forms == "never":
+            assert set(smoothed) == {"sweep"}, info["smoother"]
+            assert info["n"][0] > 2 * info["block_rows"][0]  # several sweep blocks on level 0
+        elif forms == "block":
+            assert "block" in smoothed, info["smoother"]
+        x, it, rel, st = bs.solve(b, tol=1e-8)
+        assert st == 0
+        xs = x.cpu().numpy()
+        for s, p in enumerate(probs):
+            r = refs[s]
+            assert it[s] == r["iters"], (forms, s, it[s], r["iters"])
+            xo = xs[bs.offsets[s]:bs.offsets[s] + p.n]
+            err = np.linalg.norm(xo - r["x"]) / np.linalg.norm(r["x"])
+            assert err <= 1e-10, (forms, s, err)
