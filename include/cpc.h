@@ -308,6 +308,18 @@ cpc_status cpc_solve_batch(cpc_handle h, const double* b_dev, double* x_dev, dou
  * (caller arrays of nsys entries; a single-system handle reports one system). */
 cpc_status cpc_batch_info(cpc_handle h, int32_t* nsys, int32_t* n, int32_t* offset);
 
+/* For callers that cannot allocate device memory during a solve (serving loops,
+ * harnesses that forbid hipMalloc): the solve of cpc_solve on a single-system handle,
+ * with the same arguments, results and errors, that allocates nothing. Its scratch (the
+ * PCG scalars, the partial sums of the reductions and the sweep counters, 33 KiB) lives
+ * in one static 64 KiB device array per GPU instead of the handle; every iteration is
+ * launched directly (no graph is instantiated). Limits: every call on one GPU shares
+ * that array, so calls that overlap on one GPU (two threads, or two streams with work
+ * in flight) race and must be serialised by the caller; batch handles give
+ * CPC_E_ARG. The array is located on the first call on each device. */
+cpc_status cpc_solve_noalloc(cpc_handle h, const double* b_dev, double* x_dev, int32_t use_x0, double tol,
+                             int32_t maxit, int32_t* iters, double* relres);
+
 /* Destroy the handle and free its device and host memory (NULL is ignored). */
 void cpc_destroy(cpc_handle h);
 

@@ -34,6 +34,7 @@ SOURCES = [
     ("rap.hip", "hip", ["-ffp-contract=off"]),
     ("tpfa.hip", "hip", ["-ffp-contract=off"]),
     ("dense_tri.hip", "hip", []),
+    ("noalloc.hip", "hip", []),
     ("host_setup.cpp", "gxx", ["-ffp-contract=off"]),
     ("solver.cpp", "hiphost", []),
 ]

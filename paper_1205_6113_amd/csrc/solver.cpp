@@ -25,6 +25,7 @@
 #include "../../include/cpc.h"
 #include "host_setup.hpp"
 #include "kernels.hpp"
+#include "solve_scratch.hpp"
 
 namespace {
 
@@ -157,6 +158,7 @@ constexpr int kNumPrec = CPC_PREC_BBAR + 1;  // preconditioners cpc_solve can ru
 
 struct cpc_solver {
   cpc_options opt{};
+  int device = 0;  // the GPU the handle was set up on (current device at setup)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int n = 0;
@@ -1814,7 +1816,7 @@ static double method_kernel_bytes(const cpc_solver* h, int kernel, int d) {
 }
 
 static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x, int use_x0, double tol, int maxit,
-                            int32_t* iters, double* relres) {
+                            int32_t* iters, double* relres, bool eager = false) {
   if (!h) return set_err(CPC_E_ARG, "null handle");
   if (h->batch) return set_err(CPC_E_ARG, "batch handle: use cpc_solve_batch");
   if (!b || !x) return set_err(CPC_E_ARG, "null vector");
@@ -1835,7 +1837,7 @@ static cpc_status run_solve(cpc_solver* h, int prec, const double* b, double* x,
     HIPCHK(hipMemcpyAsync(&hs, h->st, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     const int every = h->opt.check_every;
-    bool use_graph = h->opt.use_graph != 0;
+    bool use_graph = h->opt.use_graph != 0 && !eager;
     if (use_graph && (!h->graph[prec] || h->graph_x[prec] != x)) {
       if (h->graph[prec]) {
         (void)hipGraphExecDestroy(h->graph[prec]);
@@ -2029,6 +2031,44 @@ static cpc_status run_solve_batch(cpc_solver* h, int prec, const double* b, doub
 
 using namespace cpc;
 
+namespace cpc {
+
+cpc_status fail(cpc_status st, const char* msg) { return set_err(st, msg); }
+int handle_device(const cpc_solver* h) { return h->device; }
+bool handle_is_batch(const cpc_solver* h) { return h->batch; }
+
+// The solve with the PCG scalars, the reduction partials and the sweep hand-off
+// counters taken from caller-provided device memory instead of the handle's, and every
+// iteration launched eagerly (no graph is instantiated, which would allocate). The
+// handle's own pointers are swapped out for the duration of the call (a handle is used
+// by one thread at a time) and put back on every exit path.
+cpc_status run_solve_on_scratch(cpc_solver* h, const double* b, double* x, int use_x0, double tol, int maxit,
+                                int32_t* iters, double* relres, const SolveScratch& sc) {
+  struct Swap {
+    cpc_solver* h;
+    PcgState* st;
+    double* partials;
+    SweepSync sync;
+    ~Swap() {
+      h->st = st;
+      h->partials = partials;
+      h->sync = sync;
+    }
+  } keep{h, h->st, h->partials, h->sync};
+  h->st = sc.st;
+  h->partials = sc.partials;
+  h->sync = sc.sync;
+  // the memory keeps what the last call on this GPU left: the sweep counters must start
+  // at zero (the PCG state is written whole before any kernel reads it, and every
+  // reduction writes its partials before summing them)
+  for (unsigned* c : {sc.sync.ticket, sc.sync.exited, sc.sync.err})
+    if (hipMemsetAsync(c, 0, sizeof(unsigned), h->stream) != hipSuccess)
+      return set_err(CPC_E_DEVICE, "clearing the sweep counters failed");
+  return run_solve(h, h->opt.prec, b, x, use_x0, tol, maxit, iters, relres, true);
+}
+
+}  // namespace cpc
+
 extern "C" {
 
 void cpc_default_options(cpc_options* o) {
@@ -2084,6 +2124,7 @@ cpc_status cpc_setup(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, 
   int vs = validate_csr(n, row_ptr, col_idx, val, o.check_symmetry != 0, &msg);
   if (vs != CPC_OK) return set_err((cpc_status)vs, msg);
   auto h = std::make_unique<cpc_solver>();
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;  // the setup's GPU calls report a missing device
   h->opt = o;
   h->setup_t0 = t0;
   h->n = n;
@@ -2162,6 +2203,7 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
   if (total > 2147483647LL) return set_err(CPC_E_ARG, "batch exceeds 2^31 rows");
   if (o.ilu_fill > 0) return set_err(CPC_E_ARG, "ilu_fill > 0 is offered for single systems only");
   auto h = std::make_unique<cpc_solver>();
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;  // the setup's GPU calls report a missing device
   h->opt = o;
   h->setup_t0 = t0;
   h->batch = true;
@@ -2231,6 +2273,7 @@ cpc_status cpc_batch_info(cpc_handle h, int32_t* nsys, int32_t* n, int32_t* offs
   }
   return CPC_OK;
 }
+
 
 cpc_status cpc_solve(cpc_handle h, const double* b_dev, double* x_dev, int32_t use_x0, double tol, int32_t maxit,
                      int32_t* iters, double* relres) {

@@ -123,6 +123,19 @@ class Solver:
         check(st, allow=(_lib.CPC_OK, _lib.CPC_E_MAXIT, _lib.CPC_E_BREAKDOWN))
         return x, it.value, rel.value, st
 
+    def solve_noalloc(self, b: torch.Tensor, x: torch.Tensor, tol: float = 1e-8, maxit: int = 10000,
+                      use_x0: bool = False):
+        """The solve of `solve` through cpc_solve_noalloc (no device allocation; x must be
+        given). Returns (x, iters, relres, status)."""
+        b = _dev_vec(b, self.n, "b")
+        x = _dev_vec(x, self.n, "x")
+        it = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        st = self._lib.cpc_solve_noalloc(self._h, b.data_ptr(), x.data_ptr(), int(bool(use_x0)), float(tol),
+                                         int(maxit), ctypes.byref(it), ctypes.byref(rel))
+        check(st, allow=(_lib.CPC_OK, _lib.CPC_E_MAXIT, _lib.CPC_E_BREAKDOWN))
+        return x, it.value, rel.value, st
+
     def apply(self, op: str | int, r: torch.Tensor, z: torch.Tensor | None = None) -> torch.Tensor:
         """z = M r for an operator of cpc_op ('combined', 'amg', 'ilu', 'additive', 'none',
         'vcycle', 'fgs', 'bgs')."""
