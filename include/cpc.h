@@ -106,6 +106,9 @@ typedef struct {
                              3.1; 0 = ILU(0), the paper's choice; at most 16; single
                              systems only, cpc_setup_batch rejects k > 0)                  */
   double theta;           /* strength threshold of the classical coarsening (0.25)          */
+  int32_t sweep_kernel;   /* level-scheduled triangular solves: 0 = one wave per block, no
+                             barriers, where every row has at most 64 dependency entries
+                             (else the four-wave kernel); 1 = the four-wave kernel always  */
 } cpc_options;
 
 typedef struct {

@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
                 ("rap_on_gpu", ctypes.c_int32), ("sweep_block_rows", ctypes.c_int32),
                 ("sweep_threads", ctypes.c_int32), ("dense_smoother", ctypes.c_int32),
                 ("tune", ctypes.c_int32), ("verbose", ctypes.c_int32), ("ilu_fill", ctypes.c_int32),
-                ("theta", ctypes.c_double)]
+                ("theta", ctypes.c_double), ("sweep_kernel", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

@@ -30,6 +30,7 @@ SOURCES = [
     # (source, compiler, extra flags)
     ("kernels.hip", "hip", []),
     ("sweep.hip", "hip", []),
+    ("wave_sweep.hip", "hip", []),
     ("batch.hip", "hip", []),
     ("rap.hip", "hip", ["-ffp-contract=off"]),
     ("tpfa.hip", "hip", ["-ffp-contract=off"]),

@@ -1,7 +1,9 @@
 // Host-only entry points over the library's SETUP code (host_setup.cpp), built into
 // libcpc_host.so so that tests can check the coarsening, interpolation, ILU(0) and
 // sweep schedules on a machine without a GPU. Not part of the solver's C-ABI.
+#include <algorithm>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "host_setup.hpp"
@@ -91,6 +93,98 @@ int cpch_sweep(int n, const int* rp, const int* ci, const double* v, int forward
   if (wait_need) std::memcpy(wait_need, s.wait_need.data(), sizeof(int) * s.wait_need.size());
   if (publish) std::memcpy(publish, s.publish.data(), sizeof(int) * nl);
   if (blk_row) std::memcpy(blk_row, s.blk_row.data(), sizeof(int) * (s.nblk + 1));
+  return 0;
+}
+
+// Sequential emulation of the one-wave sweep kernel on its pack: blocks in ticket
+// order, the steps of a block in order including the padding steps the kernel's ring
+// of `ring` steps runs past the end, every load addressed as the kernel addresses it
+// (the entry data of the step `ring` ahead, clamped to the block's last step). The
+// schedule has blocks of W-row segments, M per block, spaced by the matrix's dominant
+// coupling distance (M = 1: contiguous blocks of W rows). Returns 0 with
+// x = T^{-1} f (T = D+L forward, D+U backward; unit diagonal when unit != 0) and
+// shape = {tb, k, nblk, nsteps, R, M, stride}, or a negative code: -1 an address outside
+// its array, -2 a value of the block's own rows read before it was written, -3 a value
+// of another block read before that block wrote it, -4 a row written twice, into a slot
+// taken by another row, or never, -5 no pack (a row longer than every shape), -6 the
+// blocks' dependency graph has a cycle.
+int cpch_wave_emulate(int n, const int* rp, const int* ci, const double* v, int forward, int W, int M, int unit,
+                      int ring, const double* f, double* x, int* shape) {
+  HostCsr a = make_csr(n, rp, ci, v);
+  const int stride = cpc::dominant_stride(a);
+  cpc::WaveSchedule s;
+  if (!cpc::build_wave_schedule(a, forward != 0, W, M, stride, s)) return -6;
+  std::vector<std::pair<int, int>> shapes;
+  for (int tb : {1, 2, 4, 8, 16})
+    for (int k : {2, 4}) shapes.push_back({tb, k});
+  cpc::WavePack w;
+  if (!cpc::build_wave_pack(a, a.v, s, shapes, w)) return -5;
+  const int K = w.k, TB = w.tb, G = 64 / TB;
+  shape[0] = TB;
+  shape[1] = K;
+  shape[2] = w.nblk;
+  shape[3] = (int)w.nsteps;
+  shape[4] = w.R;
+  shape[5] = s.M;
+  shape[6] = stride;
+  std::vector<char> xw(n, 0);
+  std::vector<double> xs(w.R + 1, 0.0);
+  std::vector<int> owner(w.R + 1, -1);
+  const size_t ncol = w.col.size(), nrow = w.row.size();
+  if ((int)w.blk_step.size() != w.nblk + 1 || w.blk_step[w.nblk] != w.nsteps) return -1;
+  for (int t = 0; t < w.nblk; ++t) {
+    const int s0 = w.blk_step[t], s1 = w.blk_step[t + 1];
+    if (!(s1 > s0)) return -1;
+    std::fill(owner.begin(), owner.end(), -1);
+    owner[w.R] = n;  // the zero slot
+    xs[w.R] = 0.0;
+    const int last = s0 + ((s1 - s0 + ring - 1) / ring) * ring;  // steps the ring runs
+    for (int st = s0; st < last + ring; ++st) {
+      // every step the kernel issues loads for, clamped as the kernel clamps them
+      const int sc = st < s1 ? st : s1 - 1;
+      for (int lane = 0; lane < 64; ++lane)
+        for (int k = 0; k < K; ++k)
+          if ((size_t)sc * K * 64 + (size_t)k * 64 + lane >= ncol) return -1;
+      for (int g = 0; g < G; ++g)
+        if ((size_t)sc * G + g >= nrow) return -1;
+      if (st >= last) continue;  // loads issued by the last steps, never computed
+      const bool valid = st < s1;
+      for (int g = 0; g < G; ++g) {
+        const int row = valid ? w.row[(size_t)sc * G + g] : -1;
+        const int sl = w.slot[(size_t)sc * G + g];
+        if (sl < 0 || sl > w.R) return -1;
+        double sum = 0.0;
+        for (int l = 0; l < TB; ++l) {
+          const int lane = g * TB + l;
+          for (int k = 0; k < K; ++k) {
+            const size_t at = (size_t)sc * K * 64 + (size_t)k * 64 + lane;
+            const int c = w.col[at];
+            double xv;
+            if (c >= 0) {
+              if (c > w.R) return -1;
+              if (owner[c] < 0) return -2;
+              xv = xs[c];
+            } else {
+              const int j = -(c + 1);
+              if (j < 0 || j >= n) return -1;
+              if (!xw[j]) return -3;
+              xv = x[j];
+            }
+            sum += w.val[at] * xv;
+          }
+        }
+        if (row < 0) continue;
+        if (row >= n || xw[row] || sl >= w.R || owner[sl] >= 0) return -4;
+        const double xi = unit ? f[row] - sum : (f[row] - sum) * w.dinv[(size_t)sc * G + g];
+        xs[sl] = xi;
+        owner[sl] = row;
+        x[row] = xi;
+        xw[row] = 1;
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    if (!xw[i]) return -4;
   return 0;
 }
 

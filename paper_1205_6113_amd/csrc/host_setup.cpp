@@ -6,6 +6,8 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <queue>
+#include <map>
 #include <functional>
 #include <cmath>
 #include <cstring>
@@ -590,6 +592,199 @@ SweepSchedule build_sweep(const HostCsr& a, bool forward, int R, int64_t max_ent
   for (int b = 0; b < s.nblk; ++b)
     for (int need : needs_of_block[b]) s.publish[s.blk_beg[b] + need - 1] = 1;
   return s;
+}
+
+int dominant_stride(const HostCsr& a) {
+  std::map<int, int> count;
+  for (int i = 0; i < a.n; ++i)
+    if (a.rp[i] < a.rp[i + 1] && a.ci[a.rp[i]] < i) ++count[i - a.ci[a.rp[i]]];
+  int best = 0, bc = 0;
+  for (const auto& kv : count)
+    if (kv.second > bc) {
+      best = kv.first;
+      bc = kv.second;
+    }
+  return best;
+}
+
+bool build_wave_schedule(const HostCsr& a, bool forward, int W, int M, int stride, WaveSchedule& s) {
+  const int n = a.n;
+  if (W < 1 || M < 1) return false;
+  if (M > 1 && stride < W) M = 1;  // segments would overlap: contiguous blocks
+  s = WaveSchedule{};
+  s.forward = forward;
+  s.n = n;
+  s.W = W;
+  s.M = M;
+  s.stride = M > 1 ? stride : 0;
+  // global depth of every row in the solve's direction
+  std::vector<int> depth(n, 0);
+  if (forward) {
+    for (int i = 0; i < n; ++i) {
+      int g = 0;
+      for (int q = a.rp[i]; q < a.rp[i + 1] && a.ci[q] < i; ++q) g = std::max(g, depth[a.ci[q]] + 1);
+      depth[i] = g;
+      s.global_depth = std::max(s.global_depth, g + 1);
+    }
+  } else {
+    for (int i = n - 1; i >= 0; --i) {
+      int g = 0;
+      for (int q = a.rp[i + 1] - 1; q >= a.rp[i] && a.ci[q] > i; --q) g = std::max(g, depth[a.ci[q]] + 1);
+      depth[i] = g;
+      s.global_depth = std::max(s.global_depth, g + 1);
+    }
+  }
+  // block of each row (keys in increasing order of their first row)
+  const int64_t nr = M > 1 ? (stride + W - 1) / W : 0;
+  auto key = [&](int i) -> int64_t {
+    if (M == 1) return i / W;
+    return ((int64_t)i / ((int64_t)stride * M)) * nr + (i % stride) / W;
+  };
+  std::map<int64_t, int> ids;
+  std::vector<int> blk(n), first;
+  for (int i = 0; i < n; ++i) {
+    auto it = ids.find(key(i));
+    if (it == ids.end()) {
+      it = ids.emplace(key(i), (int)first.size()).first;
+      first.push_back(i);
+    }
+    blk[i] = it->second;
+  }
+  const int nb = (int)first.size();
+  std::vector<int> last(nb, 0), cnt(nb, 0);
+  for (int i = 0; i < n; ++i) {
+    last[blk[i]] = i;
+    ++cnt[blk[i]];
+  }
+  // dependency graph between blocks and a topological order of it (forward: earliest
+  // first row first; backward: latest last row first)
+  std::vector<std::vector<int>> succ(nb);
+  std::vector<int> indeg(nb, 0);
+  {
+    for (int i = 0; i < n; ++i) {
+      const int bi = blk[i];
+      for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
+        const int j = a.ci[q];
+        if ((forward ? j < i : j > i) && blk[j] != bi) succ[blk[j]].push_back(bi);
+      }
+    }
+    for (int b = 0; b < nb; ++b) {
+      std::sort(succ[b].begin(), succ[b].end());
+      succ[b].erase(std::unique(succ[b].begin(), succ[b].end()), succ[b].end());
+      for (int c : succ[b]) ++indeg[c];
+    }
+  }
+  std::vector<int> order;
+  order.reserve(nb);
+  {
+    auto prio = [&](int b) { return forward ? (int64_t)first[b] : -(int64_t)last[b]; };
+    std::priority_queue<std::pair<int64_t, int>, std::vector<std::pair<int64_t, int>>, std::greater<>> ready;
+    for (int b = 0; b < nb; ++b)
+      if (indeg[b] == 0) ready.push({prio(b), b});
+    while (!ready.empty()) {
+      const int b = ready.top().second;
+      ready.pop();
+      order.push_back(b);
+      for (int c : succ[b])
+        if (--indeg[c] == 0) ready.push({prio(c), c});
+    }
+  }
+  if ((int)order.size() != nb) return false;  // the blocks depend on each other in a cycle
+  // rows of each block in (depth, row) order; slots and level boundaries
+  std::vector<std::vector<int>> members(nb);
+  for (int b = 0; b < nb; ++b) members[b].reserve(cnt[b]);
+  for (int i = 0; i < n; ++i) members[blk[i]].push_back(i);
+  s.nblk = nb;
+  s.slot.assign(n, 0);
+  s.block_of.assign(n, 0);
+  s.blk_ptr.assign(nb + 1, 0);
+  s.blk_lvl.assign(nb + 1, 0);
+  s.rows.reserve(n);
+  s.lvl_ptr.push_back(0);
+  for (int t = 0; t < nb; ++t) {
+    auto& m = members[order[t]];
+    std::stable_sort(m.begin(), m.end(), [&](int x, int y) { return depth[x] < depth[y]; });
+    s.blk_ptr[t] = (int)s.rows.size();
+    s.blk_lvl[t] = (int)s.lvl_ptr.size() - 1;
+    s.R = std::max(s.R, (int)m.size());
+    for (size_t q = 0; q < m.size(); ++q) {
+      const int i = m[q];
+      if (q > 0 && depth[i] != depth[m[q - 1]]) s.lvl_ptr.push_back((int)s.rows.size());
+      s.slot[i] = (int)q;
+      s.block_of[i] = t;
+      s.rows.push_back(i);
+    }
+    s.lvl_ptr.push_back((int)s.rows.size());
+  }
+  s.blk_ptr[nb] = (int)s.rows.size();
+  s.blk_lvl[nb] = (int)s.lvl_ptr.size() - 1;
+  return true;
+}
+
+bool build_wave_pack(const HostCsr& a, const std::vector<double>& vals, const WaveSchedule& s,
+                     const std::vector<std::pair<int, int>>& shapes, WavePack& w) {
+  const int n = a.n;
+  const bool fwd = s.forward;
+  int maxlen = 0;
+  for (int i = 0; i < n; ++i) {
+    int c = 0;
+    for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) c += fwd ? (a.ci[q] < i) : (a.ci[q] > i);
+    maxlen = std::max(maxlen, c);
+  }
+  const int nlev = (int)s.lvl_ptr.size() - 1;
+  int tb = 0, K = 0;
+  int64_t best = 0;
+  for (const auto& sh : shapes) {
+    if (sh.first * sh.second < maxlen || 64 % sh.first != 0) continue;
+    const int G = 64 / sh.first;
+    int64_t steps = 0;
+    for (int m = 0; m < nlev; ++m) steps += (s.lvl_ptr[m + 1] - s.lvl_ptr[m] + G - 1) / G;
+    if (tb == 0 || steps < best || (steps == best && sh.second < K)) {
+      tb = sh.first;
+      K = sh.second;
+      best = steps;
+    }
+  }
+  if (tb == 0) return false;
+  const int G = 64 / tb;
+  const size_t S = (size_t)best;
+  w.tb = tb;
+  w.k = K;
+  w.nblk = s.nblk;
+  w.R = s.R;
+  w.nsteps = best;
+  w.blk_step.assign(s.nblk + 1, 0);
+  w.row.assign(S * G, -1);
+  w.slot.assign(S * G, s.R);
+  w.dinv.assign(S * G, 0.0);
+  w.col.assign(S * K * 64, s.R);
+  w.val.assign(S * K * 64, 0.0);
+  size_t st = 0;
+  for (int t = 0; t < s.nblk; ++t) {
+    w.blk_step[t] = (int)st;
+    for (int m = s.blk_lvl[t]; m < s.blk_lvl[t + 1]; ++m) {
+      for (int p0 = s.lvl_ptr[m]; p0 < s.lvl_ptr[m + 1]; p0 += G, ++st) {
+        const int p1 = std::min(p0 + G, s.lvl_ptr[m + 1]);
+        for (int p = p0; p < p1; ++p) {
+          const int gi = p - p0, i = s.rows[p];
+          w.row[st * G + gi] = i;
+          w.slot[st * G + gi] = s.slot[i];
+          int e = 0;
+          for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
+            const int j = a.ci[q];
+            if (j == i) w.dinv[st * G + gi] = 1.0 / vals[q];
+            if (!(fwd ? j < i : j > i)) continue;
+            const size_t at = st * K * 64 + (size_t)(e / tb) * 64 + gi * tb + e % tb;
+            w.col[at] = s.block_of[j] == t ? s.slot[j] : -(j + 1);
+            w.val[at] = vals[q];
+            ++e;
+          }
+        }
+      }
+    }
+  }
+  w.blk_step[s.nblk] = (int)st;
+  return true;
 }
 
 int dense_spd_inverse(const HostCsr& a, std::vector<double>& inv, std::string* msg) {

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace cpc {
@@ -73,6 +74,56 @@ struct SweepSchedule {
 // of at most max_entries entries each; a single row longer than that forms a level of
 // its own.
 SweepSchedule build_sweep(const HostCsr& a, bool forward, int R, int64_t max_entries = 0);
+
+// Schedule of the one-wave triangular-solve kernel. Rows are cut into blocks that are
+// unions of up to M segments of W rows spaced `stride` rows apart: row i lies in the
+// group i / (stride * M) and the segment (i % stride) / W of it (M = 1: contiguous
+// blocks of W rows). On a grid in natural order, the stride is the longest coupling
+// (one plane of a 3-D grid), so the couplings between consecutive planes of a group
+// stay inside a block instead of crossing to another block. Blocks are processed in
+// a topological order of their dependency graph (the schedule is refused when that
+// graph has a cycle); within a block the rows run in order of their global depth
+// (the level sets of the whole solve), each row at an LDS slot of its own.
+struct WaveSchedule {
+  bool forward = true;
+  int n = 0, nblk = 0, R = 0;  // R: most rows of one block
+  int W = 0, M = 1, stride = 0;
+  int global_depth = 0;
+  std::vector<int> blk_ptr;   // nblk + 1: rows of the t-th processed block in `rows`
+  std::vector<int> rows;      // the rows of each block in (depth, row) order
+  std::vector<int> blk_lvl;   // nblk + 1: levels of block t in lvl_ptr
+  std::vector<int> lvl_ptr;   // level boundaries within `rows`
+  std::vector<int> slot;      // [n] LDS slot of each row within its block
+  std::vector<int> block_of;  // [n] processing index of each row's block
+};
+
+// Longest lower coupling i - j (j < i) that most rows share (0 for a diagonal matrix).
+int dominant_stride(const HostCsr& a);
+
+// Returns false when the blocks' dependency graph has a cycle.
+bool build_wave_schedule(const HostCsr& a, bool forward, int W, int M, int stride, WaveSchedule& s);
+
+// One-wave form of a triangular solve over a wave schedule (the layout the kernel
+// reads): each level of each block cut into steps of G = 64 / tb rows, a row's
+// dependency entries dealt over its tb lanes (entry e on lane e % tb at position
+// e / tb of the step's [k][64] arrays), padding entries with column R (a slot that
+// holds zero) and value 0, padding groups with row -1. Columns: the slot of j inside
+// the row's block, -(j + 1) outside. (tb, k) is the shape from `shapes` that holds the
+// longest row in the fewest steps (then the smallest k).
+struct WavePack {
+  int tb = 0, k = 0, nblk = 0, R = 0;
+  int64_t nsteps = 0;
+  std::vector<int> blk_step;  // nblk + 1, processing order
+  std::vector<int> row;       // nsteps * (64 / tb)
+  std::vector<int> slot;      // nsteps * (64 / tb), LDS slot of the row
+  std::vector<double> dinv;   // nsteps * (64 / tb), reciprocal diagonal (0 for padding)
+  std::vector<int> col;       // nsteps * k * 64
+  std::vector<double> val;    // nsteps * k * 64
+};
+
+// Returns false (w untouched) when no shape holds the longest row.
+bool build_wave_pack(const HostCsr& a, const std::vector<double>& vals, const WaveSchedule& s,
+                     const std::vector<std::pair<int, int>>& shapes, WavePack& w);
 
 // Block starts used by build_sweep (size nblk + 1, last = n).
 std::vector<int> sweep_block_starts(const HostCsr& a, int R);

@@ -133,7 +133,31 @@ void launch_binit(hipStream_t s, const BatchDev& bd, const double* b, double* x,
 void launch_bdense(hipStream_t s, const DenseListDev& dl, const void* f, void* e, bool fp32, const int* done);
 
 // Rows of one triangular solve packed in processing order (see sweep.hip).
+// One-wave form of a triangular solve (wave_sweep.hip; schedule and layout in
+// host_setup.hpp, WaveSchedule / WavePack). The rows of each block are processed in
+// steps: a step holds up to G = 64 / tb rows of one level (rows of a level are
+// independent), each row on tb lanes, each lane holding k of the row's dependency
+// entries. Steps are stored in processing order, block after block, so the data of the
+// step d places ahead lies at a computed address.
+struct WaveDev {
+  int ok;               // 1 when the pack has this form
+  int tb, k;            // lanes per row, entries per lane (a row holds at most tb * k entries)
+  int nblk, R;          // blocks; LDS slots R + 1 (slot R holds zero, the padding entries' column)
+  int nsteps;
+  int grid;             // workgroups (one wave each) launched
+  int W, M;             // segment width and segments per block of the schedule (for reports)
+  const int* blk_step;  // [nblk + 1] steps of the t-th processed block: [blk_step[t], blk_step[t+1])
+  const int* col;       // [nsteps][k][64] entry column: the slot of j within the row's block,
+                        // -(j + 1) in another block, R for padding; entry e of a row on lane
+                        // e % tb at position e / tb
+  const void* val;      // [nsteps][k][64] entry values (0 for padding)
+  const int* row;       // [nsteps][G] row of each group, -1 for none
+  const int* slot;      // [nsteps][G] LDS slot of the group's row within its block
+  const void* dinv;     // [nsteps][G] reciprocal diagonal of the group's row
+};
+
 struct SweepPackDev {
+  WaveDev wave{};    // the one-wave form, used when wave.ok
   const int* row;    // [n] row of the p-th processed row
   const int* ptr;    // [n+1] dependency entries of processed row p: [ptr[p], ptr[p+1])
   const int* col;    // entry column: j - (first row of the block) for a column in the row's own
@@ -199,6 +223,13 @@ void launch_sweep_packed(hipStream_t s, int op, const SweepDev& sw, const SweepP
                          const void* f, void* x, const void* base, void* out, const SweepSync& sync,
                          const int* done, long spin_limit);
 void launch_fill_sentinel(hipStream_t s, int n, void* x, bool fp32, const int* done);
+// The same triangular solves through the one-wave form of the pack (pk.wave.ok);
+// x must hold the sentinel in every row of the system when it starts.
+void launch_wave_sweep(hipStream_t s, int op, const WaveDev& w, bool fp32, const void* f, void* x,
+                       const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit);
+// Supported (lanes per row, entries per lane) of the one-wave form.
+bool wave_shape_supported(int tb, int k);
+int wave_lds_bytes(int R, bool fp32);
 int sweep_max_rows_per_block();
 int sweep_lds_budget();      // dynamic LDS bytes a sweep workgroup may use
 int sweep_threads();         // threads per sweep workgroup

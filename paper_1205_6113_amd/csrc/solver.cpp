@@ -139,6 +139,8 @@ struct Level {
   std::vector<void*> sweep_owned;
   int sweep_rows = 0;  // rows the sweeps cover (all rows at depth 0 for ILU(0), else the smoothed ones)
   int sweep_R = 0;     // rows per block requested for them
+  int wave_M = 0;      // segments per block of the one-wave form (0: chosen by rule)
+  int wave_stride = -1;  // the matrix's dominant coupling distance (-1: not yet measured)
   // block-dense form of the smoother: block forward/backward substitution with explicit
   // inverses of the diagonal blocks of D+L (levels where it beats the sweeps)
   bool bdense = false;
@@ -427,6 +429,75 @@ static void spmv_or_throw(cpc_solver* h, const MatDev& A, int mode, const void* 
     throw HipError{hipErrorInvalidValue, "unsupported SpMV precision combination"};
 }
 
+// Upload the one-wave form of a triangular solve (wave_sweep.hip) over a wave
+// schedule; share: a form over the same schedule and pattern whose step, row, slot and
+// column arrays are reused (values differ). Not built (ok = 0) when no supported shape
+// holds the longest row (more than 64 dependency entries).
+static WaveDev upload_wave(cpc_solver* h, const HostCsr& a, const std::vector<double>& vals, const WaveSchedule& s,
+                           const WaveDev* share) {
+  WaveDev w{};
+  std::vector<std::pair<int, int>> shapes;
+  for (int tb : {1, 2, 4, 8, 16})
+    for (int k : {2, 4})
+      if (wave_shape_supported(tb, k)) shapes.push_back({tb, k});
+  WavePack wp;
+  if (!build_wave_pack(a, vals, s, shapes, wp)) return w;
+  if (wave_lds_bytes(wp.R, h->f32) > 150 * 1024) return w;
+  if (share && share->ok && (share->tb != wp.tb || share->k != wp.k)) share = nullptr;
+  w.ok = 1;
+  w.tb = wp.tb;
+  w.k = wp.k;
+  w.nblk = wp.nblk;
+  w.R = wp.R;
+  w.W = s.W;
+  w.M = s.M;
+  w.nsteps = (int)wp.nsteps;
+  w.grid = std::min(wp.nblk, 1024);
+  if (share && share->ok) {
+    w.blk_step = share->blk_step;
+    w.col = share->col;
+    w.row = share->row;
+    w.slot = share->slot;
+  } else {
+    w.blk_step = dupload(wp.blk_step, *h->cur_owned, h->stream);
+    w.col = dupload(wp.col, *h->cur_owned, h->stream);
+    w.row = dupload(wp.row, *h->cur_owned, h->stream);
+    w.slot = dupload(wp.slot, *h->cur_owned, h->stream);
+  }
+  if (h->f32) {
+    w.val = dupload(std::vector<float>(wp.val.begin(), wp.val.end()), *h->cur_owned, h->stream);
+    w.dinv = dupload(std::vector<float>(wp.dinv.begin(), wp.dinv.end()), *h->cur_owned, h->stream);
+  } else {
+    w.val = dupload(wp.val, *h->cur_owned, h->stream);
+    w.dinv = dupload(wp.dinv, *h->cur_owned, h->stream);
+  }
+  return w;
+}
+
+// Segments per block of the one-wave form when the tuner has not chosen: four when the
+// matrix's dominant coupling spans more than a block of R contiguous rows (the couplings
+// between consecutive planes of a grid then stay inside a block), else one.
+static int wave_segments(int stride, int R) { return stride >= R ? 4 : 1; }
+
+// One-wave forms of the forward and backward solves of `a` (and of the ILU factor's,
+// `lu` non-null) with R rows per block in M segments, into the packs given.
+static void build_wave_forms(cpc_solver* h, const HostCsr& a, int R, int M, int stride, SweepPackDev& lo,
+                             SweepPackDev& up, const std::vector<double>* lu, SweepPackDev* ilo, SweepPackDev* iup) {
+  if (h->opt.sweep_kernel == 1) return;
+  const int W = std::max(1, R / std::max(1, M));
+  WaveSchedule wl, wu;
+  if (!build_wave_schedule(a, true, W, M, stride, wl) || !build_wave_schedule(a, false, W, M, stride, wu)) {
+    // blocks that depend on each other in a cycle: contiguous blocks instead
+    if (!build_wave_schedule(a, true, R, 1, 0, wl) || !build_wave_schedule(a, false, R, 1, 0, wu)) return;
+  }
+  lo.wave = upload_wave(h, a, a.v, wl, nullptr);
+  up.wave = upload_wave(h, a, a.v, wu, nullptr);
+  if (lu && ilo && iup) {
+    ilo->wave = upload_wave(h, a, *lu, wl, &lo.wave);
+    iup->wave = upload_wave(h, a, *lu, wu, &up.wave);
+  }
+}
+
 // Pack the rows of a triangular solve in its processing order: the dependency entries
 // (left of the diagonal forward, right of it backward) with columns in the row's own
 // block stored block-relative and the others as -(j + 1). share: reuse the row/ptr/col
@@ -495,10 +566,20 @@ static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vecto
 
 // x = T^{-1} f for the triangular factor the pack holds (out = base + x for
 // SWEEP_UPPER_OUT). x is first filled with the not-yet-solved marker.
+// The triangular-solve kernel of a pack: the one-wave form where the pack has it, else
+// the four-wave workgroup kernel. x must hold the sentinel.
+static void launch_tri(cpc_solver* h, int op, const DevSweepSched& sch, const SweepPackDev& pk, const void* f,
+                       void* x, const void* base, void* out, const int* done) {
+  if (pk.wave.ok)
+    launch_wave_sweep(h->stream, op, pk.wave, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
+  else
+    launch_sweep_packed(h->stream, op, sch.d, pk, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
+}
+
 static void run_sweep(cpc_solver* h, int op, const DevSweepSched& sch, const SweepPackDev& pk, const void* f,
                       void* x, const void* base, void* out, const int* done) {
   launch_fill_sentinel(h->stream, sch.d.n, x, h->f32, done);
-  launch_sweep_packed(h->stream, op, sch.d, pk, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
+  launch_tri(h, op, sch, pk, f, x, base, out, done);
 }
 
 // Strict lower triangle of a (the old-value part of a backward Gauss-Seidel sweep).
@@ -783,14 +864,20 @@ static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int 
   std::vector<void*>* prev = h->cur_owned;
   h->cur_owned = &L.sweep_owned;
   try {
-    SweepSchedule lo = make_sweep(h, sub, true, R, L.lower);
-    SweepSchedule up = make_sweep(h, sub, false, R, L.upper);
+    const int Rw = std::min(R, sweep_max_rows_per_block());  // the four-wave kernel's blocks
+    SweepSchedule lo = make_sweep(h, sub, true, Rw, L.lower);
+    SweepSchedule up = make_sweep(h, sub, false, Rw, L.upper);
     L.fgs = build_pack(h, sub, sub.v, lo, nullptr);
     L.bgs = build_pack(h, sub, sub.v, up, nullptr);
     if (ilu && !h->iluk) {
       h->ilu_l = build_pack(h, sub, h->lu_host, lo, &L.fgs);
       h->ilu_u = build_pack(h, sub, h->lu_host, up, &L.bgs);
     }
+    if (L.wave_stride < 0) L.wave_stride = dominant_stride(sub);
+    const int M = L.wave_M > 0 ? L.wave_M : wave_segments(L.wave_stride, R);
+    const bool with_ilu = ilu && !h->iluk;
+    build_wave_forms(h, sub, R, M, L.wave_stride, L.fgs, L.bgs, with_ilu ? &h->lu_host : nullptr,
+                     with_ilu ? &h->ilu_l : nullptr, with_ilu ? &h->ilu_u : nullptr);
   } catch (...) {
     h->cur_owned = prev;
     throw;
@@ -806,10 +893,14 @@ static void build_iluk_sweeps(cpc_solver* h, int R) {
   std::vector<void*>* prev = h->cur_owned;
   h->cur_owned = &h->owned;
   try {
-    SweepSchedule lo = make_sweep(h, h->iluF, true, R, h->ilu_lower);
-    SweepSchedule up = make_sweep(h, h->iluF, false, R, h->ilu_upper);
+    const int Rw = std::min(R, sweep_max_rows_per_block());
+    SweepSchedule lo = make_sweep(h, h->iluF, true, Rw, h->ilu_lower);
+    SweepSchedule up = make_sweep(h, h->iluF, false, Rw, h->ilu_upper);
     h->ilu_l = build_pack(h, h->iluF, h->iluF.v, lo, nullptr);
     h->ilu_u = build_pack(h, h->iluF, h->iluF.v, up, nullptr);
+    const int stride = dominant_stride(h->iluF);
+    build_wave_forms(h, h->iluF, R, wave_segments(stride, R), stride, h->ilu_l, h->ilu_u, nullptr, nullptr,
+                     nullptr);
   } catch (...) {
     h->cur_owned = prev;
     throw;
@@ -1075,18 +1166,16 @@ static void tune_sweeps(cpc_solver* h) {
     progress(h, "level " + std::to_string(d) + (skip_r ? ": block substitution well ahead, sweep block size kept"
                                                         : ": timing sweep block sizes"));
     float best = try_r && !skip_r ? cost() : 0.f;
-    // 1024 .. 8192, then halving below 1024 for as long as the smallest one wins (the
-    // wide coarse stencils of L1 favour short blocks)
-    for (int R : {1024, 2048, 4096, 8192, 512, 256}) {
-      if (!try_r || skip_r || R == L.sweep_R || R >= L.sweep_rows) continue;
-      if (R < 1024 && L.sweep_R != 2 * R) continue;
-      // keep the current build aside, try the candidate in a list of its own
+    // build the sweeps with R rows per block (M segments per block in the one-wave form)
+    // in a list of their own; keep them if they are faster, else restore the current ones
+    auto try_build = [&](int R, int M) {
       DevSweepSched lo = L.lower, up = L.upper;
       SweepPackDev fg = L.fgs, bg = L.bgs, il = h->ilu_l, iu = h->ilu_u;
-      const int oldR = L.sweep_R;
+      const int oldR = L.sweep_R, oldM = L.wave_M;
       std::vector<void*> old;
       old.swap(L.sweep_owned);
       bool built = true;
+      L.wave_M = M;
       try {
         build_level_sweeps(h, L, sub, R, ilu);
       } catch (const HipError&) {
@@ -1109,7 +1198,24 @@ static void tune_sweeps(cpc_solver* h) {
         h->ilu_l = il;
         h->ilu_u = iu;
         L.sweep_R = oldR;
+        L.wave_M = oldM;
       }
+    };
+    // 1024 .. 8192 (16384: one-wave form only), then halving below 1024 for as long as
+    // the smallest one wins (the wide coarse stencils of L1 favour short blocks)
+    for (int R : {1024, 2048, 4096, 8192, 16384, 512, 256}) {
+      if (!try_r || skip_r || R == L.sweep_R || R >= L.sweep_rows) continue;
+      if (R < 1024 && L.sweep_R != 2 * R) continue;
+      if (R > sweep_max_rows_per_block() && !L.fgs.wave.ok) continue;
+      try_build(R, L.wave_M);
+    }
+    // segments per block of the one-wave form at the chosen block size
+    if (try_r && !skip_r && L.fgs.wave.ok && L.wave_stride > 0) {
+      const int cur = L.fgs.wave.M;
+      for (int M : {1, 2, 4})
+        if (M != cur && L.sweep_R / M >= 256 && (M == 1 || L.wave_stride >= L.sweep_R / M)) try_build(L.sweep_R, M);
+      progress(h, "level " + std::to_string(d) + ": one-wave sweeps, " + std::to_string(L.sweep_R) +
+                      "-row blocks in " + std::to_string(L.fgs.wave.M) + " segments");
     }
     // block-dense form of the Gauss-Seidel factor, blocks of 2048 / 4096 / 8192 rows
     if (h->opt.dense_smoother == 3 && d + 1 < h->lev.size()) {
@@ -2091,6 +2197,7 @@ void cpc_default_options(cpc_options* o) {
   o->verbose = 0;
   o->ilu_fill = 0;
   o->theta = 0.25;
+  o->sweep_kernel = 0;
 }
 
 const char* cpc_last_error(void) { return g_last_error.c_str(); }
@@ -2109,6 +2216,7 @@ static cpc_status read_options(const cpc_options* opt, cpc_options& o) {
     return set_err(CPC_E_ARG, "sweep_threads must be 0, 64 or 256");
   if (o.dense_smoother < 0 || o.dense_smoother > 3) return set_err(CPC_E_ARG, "dense_smoother must be 0, 1, 2 or 3");
   if (o.ilu_fill < 0 || o.ilu_fill > 16) return set_err(CPC_E_ARG, "ilu_fill must lie in [0, 16]");
+  if (o.sweep_kernel < 0 || o.sweep_kernel > 1) return set_err(CPC_E_ARG, "sweep_kernel must be 0 or 1");
   if (o.check_every < 0) return set_err(CPC_E_ARG, "check_every must be >= 0 (0: predicted)");
   return CPC_OK;
 }
@@ -2487,8 +2595,7 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         }
         launch_fill_sentinel(h->stream, L.lower.d.n, u, f32, nullptr);
         ev_begin();
-        launch_sweep_packed(h->stream, SWEEP_LOWER, L.lower.d, L.fgs, f32, f, u, nullptr, nullptr, h->sync,
-                            nullptr, h->spin_limit);
+        launch_tri(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
         ev_end();
         break;
       case CPC_K_BGS:
@@ -2506,22 +2613,19 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
         }
         launch_fill_sentinel(h->stream, L.upper.d.n, u, f32, nullptr);
         ev_begin();
-        launch_sweep_packed(h->stream, SWEEP_UPPER, L.upper.d, L.bgs, f32, f, u, nullptr, nullptr, h->sync,
-                            nullptr, h->spin_limit);
+        launch_tri(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
         ev_end();
         break;
       case CPC_K_ILU_L:
         launch_fill_sentinel(h->stream, ilu_lower_sched(h).d.n, h->y, f32, nullptr);
         ev_begin();
-        launch_sweep_packed(h->stream, SWEEP_UNIT_LOWER, ilu_lower_sched(h).d, h->ilu_l, f32, h->res, h->y, nullptr,
-                            nullptr, h->sync, nullptr, h->spin_limit);
+        launch_tri(h, SWEEP_UNIT_LOWER, ilu_lower_sched(h), h->ilu_l, h->res, h->y, nullptr, nullptr, nullptr);
         ev_end();
         break;
       case CPC_K_ILU_U:
         launch_fill_sentinel(h->stream, ilu_upper_sched(h).d.n, h->w, f32, nullptr);
         ev_begin();
-        launch_sweep_packed(h->stream, SWEEP_UPPER_OUT, ilu_upper_sched(h).d, h->ilu_u, f32, h->y, h->w, h->u1,
-                            h->u2, h->sync, nullptr, h->spin_limit);
+        launch_tri(h, SWEEP_UPPER_OUT, ilu_upper_sched(h), h->ilu_u, h->y, h->w, h->u1, h->u2, nullptr);
         ev_end();
         break;
       case CPC_K_RESIDUAL:

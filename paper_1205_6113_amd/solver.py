@@ -35,7 +35,8 @@ def _dev_vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
 
 def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, theta=0.25, swap_roles=False,
             check_symmetry=True, use_graph=True, check_every=0, sweep_block_rows=0,
-            sweep_threads=0, dense_smoother=0, tune=True, verbose=False, ilu_fill=0) -> _lib.Options:
+            sweep_threads=0, dense_smoother=0, tune=True, verbose=False, ilu_fill=0,
+            sweep_kernel="auto") -> _lib.Options:
     lib = load()
     o = _lib.Options()
     lib.cpc_default_options(ctypes.byref(o))
@@ -54,6 +55,8 @@ def options(prec="combined", precision="fp64", max_coarse=256, max_levels=25, th
     o.verbose = int(bool(verbose))
     o.ilu_fill = int(ilu_fill)
     o.dense_smoother = _lib.DENSE[dense_smoother] if isinstance(dense_smoother, str) else int(dense_smoother)
+    o.sweep_kernel = {"auto": 0, "wave": 0, "workgroup": 1}[sweep_kernel] if isinstance(sweep_kernel, str) \
+        else int(sweep_kernel)
     return o
 
 

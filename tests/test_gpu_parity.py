@@ -35,29 +35,35 @@ def relerr(a, b):
 
 def small_cases():
     """name -> (problem, forced rows per sweep block or 0 for the automatic choice,
-    Gauss-Seidel through explicit inverses of D+L: "never", "always" or "auto")."""
+    Gauss-Seidel through explicit inverses of D+L: "never", "always" or "auto",
+    level-scheduled sweep kernel: "auto" (one wave per block where rows fit) or
+    "workgroup" (four waves per block))."""
     return {
-        "c1": (gen.config1(), 0, "never"),
-        "c1-ragged-blocks": (gen.config1(37, 23), 37, "never"),
-        "c1-dense": (gen.config1(), 0, "always"),
-        "c2s": (gen.scaled_config(2, 0.15), 0, "never"),
-        "c2s-tiny-blocks": (gen.scaled_config(2, 0.15), 7, "never"),
-        "c2s-dense": (gen.scaled_config(2, 0.15), 0, "always"),
-        "c3s": (gen.scaled_config(3, 0.15), 0, "auto"),
-        "c5s": (gen.scaled_config(5, 0.2), 0, "auto"),
-        "c2m": (gen.scaled_config(2, 0.3), 0, "auto"),
-        "c5m": (gen.scaled_config(5, 0.35), 0, "always"),
-        "c2m-block": (gen.scaled_config(2, 0.3), 0, "block"),
+        "c1": (gen.config1(), 0, "never", "auto"),
+        "c1-ragged-blocks": (gen.config1(37, 23), 37, "never", "auto"),
+        "c1-dense": (gen.config1(), 0, "always", "auto"),
+        "c2s": (gen.scaled_config(2, 0.15), 0, "never", "auto"),
+        "c2s-tiny-blocks": (gen.scaled_config(2, 0.15), 7, "never", "auto"),
+        "c2s-dense": (gen.scaled_config(2, 0.15), 0, "always", "auto"),
+        "c3s": (gen.scaled_config(3, 0.15), 0, "auto", "auto"),
+        "c5s": (gen.scaled_config(5, 0.2), 0, "auto", "auto"),
+        "c2m": (gen.scaled_config(2, 0.3), 0, "auto", "auto"),
+        "c5m": (gen.scaled_config(5, 0.35), 0, "always", "auto"),
+        "c2m-block": (gen.scaled_config(2, 0.3), 0, "block", "auto"),
+        "c2s-workgroup": (gen.scaled_config(2, 0.15), 0, "never", "workgroup"),
+        "c2s-tiny-blocks-workgroup": (gen.scaled_config(2, 0.15), 7, "never", "workgroup"),
+        "c1-ragged-workgroup": (gen.config1(37, 23), 37, "never", "workgroup"),
     }
 
 
 @pytest.fixture(scope="module")
 def cases():
     out = {}
-    for k, (p, R, dense) in small_cases().items():
-        print(f"[case] {k} n={p.n} nnz={p.nnz} block_rows={R} dense={dense}", flush=True)
+    for k, (p, R, dense, kern) in small_cases().items():
+        print(f"[case] {k} n={p.n} nnz={p.nnz} block_rows={R} dense={dense} kernel={kern}", flush=True)
         h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
-        s = _cpc().Solver(p.n, p.row_ptr, p.col, p.val, sweep_block_rows=R, dense_smoother=dense)
+        s = _cpc().Solver(p.n, p.row_ptr, p.col, p.val, sweep_block_rows=R, dense_smoother=dense,
+                          sweep_kernel=kern)
         out[k] = (p, h, s)
     yield out
     for _, _, s in out.values():
@@ -258,7 +264,7 @@ def test_neg_outer_on_pattern(cases):
 def test_smoother_kinds_follow_the_option(cases):
     """Levels of at most 16384 rows are smoothed through explicit inverses exactly when
     asked ("always"); never when told not to; the coarsest level is not smoothed."""
-    for k, (p, R, dense) in small_cases().items():
+    for k, (p, R, dense, _) in small_cases().items():
         info = cases[k][2].hierarchy()
         kinds = info["smoother"]
         assert kinds[-1] == "none", k
