@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # time (level-scheduled triangular sweeps, explicit-inverse products), with the kernel
 # each launches, its source and the committed counter passes for it
 FAMILIES = {
-    "sweep": {"kernel": "tri_sweep_kernel", "source": "sweep.hip",
+    "sweep": {"kernel": "tri_wave_kernel", "source": "wave_sweep.hip",
               "what": "level-scheduled triangular solves: forward/backward Gauss-Seidel sweeps on the levels "
                       "smoothed that way (both V-cycles) and the ILU(0) L and U solves of one PCG iteration"},
     "dense_gemv": {"kernel": "gemv_tri_rows_kernel", "source": "dense_tri.hip",

@@ -269,9 +269,8 @@ typedef enum {
 /* Measurement helper (not needed to solve): runs `reps` repetitions of the kernel
  * family `kernel` (cpc_kernel) on the handle's current work vectors and reports:
  *   avg_ms                : mean duration of one launch (HIP events recorded on the
- *                           handle's stream around all repetitions, around each launch
- *                           for the triangular solves, or around a captured graph of all
- *                           of them replayed reps times for the dense products);
+ *                           handle's stream around each launch for the triangular
+ *                           solves and the dense products, else around all repetitions);
  *   bytes_per_launch      : the method's bytes for the work of one launch: each matrix
  *                           read once per pass the algorithm makes over it (value + 4-byte
  *                           column, 4-byte row pointer), each vector read or written once

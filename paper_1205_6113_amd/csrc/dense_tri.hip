@@ -21,6 +21,7 @@
 // forward product; on larger ones by items (column block of 512, chunk of 1024 rows)
 // whose partial column sums go to a buffer and are added in chunk order
 // (deterministic), which reads each stored entry once without a second copy.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -345,33 +346,44 @@ void dense_row_items(int sys, int n, std::vector<int4>& items) {
   }
 }
 
-void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,
-                        const int* done) {
-  if (dt.nitem_n <= 0) return;
-  if (mfp32 && xfp32)
-    gemv_tri_rows_kernel<false, float, float><<<dt.nitem_n, kNT, 0, s>>>(dt, (const float*)f, (float*)y, done);
+// One row-product launch; with events, the dispatch itself stamps its start and end
+// into them (measurement only).
+template <bool UP, typename T>
+static void rows_launch(hipStream_t s, const DenseTriDev& dt, const void* f, void* y, const int* done,
+                        hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0 && ev1)
+    hipExtLaunchKernelGGL(gemv_tri_rows_kernel<UP, T, T>, dim3(dt.nitem_n), dim3(kNT), 0, s, ev0, ev1, 0, dt,
+                          (const T*)f, (T*)y, done);
   else
-    gemv_tri_rows_kernel<false, double, double><<<dt.nitem_n, kNT, 0, s>>>(dt, (const double*)f, (double*)y, done);
+    gemv_tri_rows_kernel<UP, T, T><<<dt.nitem_n, kNT, 0, s>>>(dt, (const T*)f, (T*)y, done);
+}
+
+void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,
+                        const int* done, hipEvent_t ev0, hipEvent_t ev1) {
+  if (dt.nitem_n <= 0) return;
+  if (mfp32 && xfp32) rows_launch<false, float>(s, dt, f, y, done, ev0, ev1);
+  else rows_launch<false, double>(s, dt, f, y, done, ev0, ev1);
 }
 
 void launch_dense_lower_t(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* g, void* y,
-                          const int* done) {
+                          const int* done, hipEvent_t ev0, hipEvent_t ev1) {
   if (dt.MT) {  // stored transpose: row products of the upper-triangular T^{-T}
     if (dt.nitem_n <= 0) return;
-    if (mfp32 && xfp32)
-      gemv_tri_rows_kernel<true, float, float><<<dt.nitem_n, kNT, 0, s>>>(dt, (const float*)g, (float*)y, done);
-    else
-      gemv_tri_rows_kernel<true, double, double><<<dt.nitem_n, kNT, 0, s>>>(dt, (const double*)g, (double*)y, done);
+    if (mfp32 && xfp32) rows_launch<true, float>(s, dt, g, y, done, ev0, ev1);
+    else rows_launch<true, double>(s, dt, g, y, done, ev0, ev1);
     return;
   }
-  if (dt.nitem_t <= 0) return;
-  if (mfp32 && xfp32) {
-    gemv_lower_t_part_kernel<float, float><<<dt.nitem_t, kNT, 0, s>>>(dt, (const float*)g, done);
-    gemv_lower_t_sum_kernel<float><<<dt.nred, kNT, 0, s>>>(dt, (float*)y, done);
-  } else {
-    gemv_lower_t_part_kernel<double, double><<<dt.nitem_t, kNT, 0, s>>>(dt, (const double*)g, done);
-    gemv_lower_t_sum_kernel<double><<<dt.nred, kNT, 0, s>>>(dt, (double*)y, done);
+  if (ev0) (void)hipEventRecord(ev0, s);  // two kernels: events around both
+  if (dt.nitem_t > 0) {
+    if (mfp32 && xfp32) {
+      gemv_lower_t_part_kernel<float, float><<<dt.nitem_t, kNT, 0, s>>>(dt, (const float*)g, done);
+      gemv_lower_t_sum_kernel<float><<<dt.nred, kNT, 0, s>>>(dt, (float*)y, done);
+    } else {
+      gemv_lower_t_part_kernel<double, double><<<dt.nitem_t, kNT, 0, s>>>(dt, (const double*)g, done);
+      gemv_lower_t_sum_kernel<double><<<dt.nred, kNT, 0, s>>>(dt, (double*)y, done);
+    }
   }
+  if (ev1) (void)hipEventRecord(ev1, s);
 }
 
 void launch_transpose(hipStream_t s, int n, const void* X, void* Y, bool fp32) {

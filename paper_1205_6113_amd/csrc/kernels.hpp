@@ -210,10 +210,12 @@ bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int*
 // Row-product items of one system of n rows (system index sys), appended to items:
 // groups of four rows from the top paired with the mirrored groups from the bottom.
 void dense_row_items(int sys, int n, std::vector<int4>& items);
+// y = T^{-1} f and y = T^{-T} g through the stored inverse. ev0 / ev1 (measurement
+// only): events stamped with the start and end of the dispatch.
 void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,
-                        const int* done);
+                        const int* done, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_dense_lower_t(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* g, void* y,
-                          const int* done);
+                          const int* done, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_to_type(hipStream_t s, long n, const double* a, void* y, bool fp32);
 void launch_transpose(hipStream_t s, int n, const void* X, void* Y, bool fp32);
 
@@ -226,7 +228,8 @@ void launch_fill_sentinel(hipStream_t s, int n, void* x, bool fp32, const int* d
 // The same triangular solves through the one-wave form of the pack (pk.wave.ok);
 // x must hold the sentinel in every row of the system when it starts.
 void launch_wave_sweep(hipStream_t s, int op, const WaveDev& w, bool fp32, const void* f, void* x,
-                       const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit);
+                       const void* base, void* out, const SweepSync& sync, const int* done, long spin_limit,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Supported (lanes per row, entries per lane) of the one-wave form.
 bool wave_shape_supported(int tb, int k);
 int wave_lds_bytes(int R, bool fp32);

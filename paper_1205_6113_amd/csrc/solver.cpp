@@ -568,12 +568,17 @@ static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vecto
 // SWEEP_UPPER_OUT). x is first filled with the not-yet-solved marker.
 // The triangular-solve kernel of a pack: the one-wave form where the pack has it, else
 // the four-wave workgroup kernel. x must hold the sentinel.
+// ev0 / ev1 (measurement only): events that end up holding the kernel's start and end.
 static void launch_tri(cpc_solver* h, int op, const DevSweepSched& sch, const SweepPackDev& pk, const void* f,
-                       void* x, const void* base, void* out, const int* done) {
-  if (pk.wave.ok)
-    launch_wave_sweep(h->stream, op, pk.wave, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
-  else
+                       void* x, const void* base, void* out, const int* done, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr) {
+  if (pk.wave.ok) {
+    launch_wave_sweep(h->stream, op, pk.wave, h->f32, f, x, base, out, h->sync, done, h->spin_limit, ev0, ev1);
+  } else {
+    if (ev0) HIPCHK(hipEventRecord(ev0, h->stream));
     launch_sweep_packed(h->stream, op, sch.d, pk, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
+    if (ev1) HIPCHK(hipEventRecord(ev1, h->stream));
+  }
 }
 
 static void run_sweep(cpc_solver* h, int op, const DevSweepSched& sch, const SweepPackDev& pk, const void* f,
@@ -2571,6 +2576,15 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
     HIPCHK(hipEventRecord(e, h->stream));
   };
   auto ev_end = ev_begin;
+  // a pair of events for one launch that stamps them itself (null when not timing)
+  auto ev_pair = [&](hipEvent_t& e0, hipEvent_t& e1) {
+    e0 = e1 = nullptr;
+    if (!timing) return;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    evs.push_back(e0);
+    evs.push_back(e1);
+  };
   auto launch_kernel = [&](int kern, int d) {
     Level& L = h->lev[d];
     void* f = d == 0 ? h->pin : L.f;
@@ -2594,9 +2608,11 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
           break;
         }
         launch_fill_sentinel(h->stream, L.lower.d.n, u, f32, nullptr);
-        ev_begin();
-        launch_tri(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr);
-        ev_end();
+        {
+          hipEvent_t e0, e1;
+          ev_pair(e0, e1);
+          launch_tri(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, nullptr, e0, e1);
+        }
         break;
       case CPC_K_BGS:
         if (L.bdense) {
@@ -2612,21 +2628,28 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
           break;
         }
         launch_fill_sentinel(h->stream, L.upper.d.n, u, f32, nullptr);
-        ev_begin();
-        launch_tri(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr);
-        ev_end();
+        {
+          hipEvent_t e0, e1;
+          ev_pair(e0, e1);
+          launch_tri(h, SWEEP_UPPER, L.upper, L.bgs, f, u, nullptr, nullptr, nullptr, e0, e1);
+        }
         break;
       case CPC_K_ILU_L:
         launch_fill_sentinel(h->stream, ilu_lower_sched(h).d.n, h->y, f32, nullptr);
-        ev_begin();
-        launch_tri(h, SWEEP_UNIT_LOWER, ilu_lower_sched(h), h->ilu_l, h->res, h->y, nullptr, nullptr, nullptr);
-        ev_end();
+        {
+          hipEvent_t e0, e1;
+          ev_pair(e0, e1);
+          launch_tri(h, SWEEP_UNIT_LOWER, ilu_lower_sched(h), h->ilu_l, h->res, h->y, nullptr, nullptr, nullptr, e0,
+                     e1);
+        }
         break;
       case CPC_K_ILU_U:
         launch_fill_sentinel(h->stream, ilu_upper_sched(h).d.n, h->w, f32, nullptr);
-        ev_begin();
-        launch_tri(h, SWEEP_UPPER_OUT, ilu_upper_sched(h), h->ilu_u, h->y, h->w, h->u1, h->u2, nullptr);
-        ev_end();
+        {
+          hipEvent_t e0, e1;
+          ev_pair(e0, e1);
+          launch_tri(h, SWEEP_UPPER_OUT, ilu_upper_sched(h), h->ilu_u, h->y, h->w, h->u1, h->u2, nullptr, e0, e1);
+        }
         break;
       case CPC_K_RESIDUAL:
         spmv_or_throw(h, smoothed(L.A, L.nS, f32), 1, u, f32, f, f32, L.r, f32, L.A.tpr, nullptr);
@@ -2656,54 +2679,64 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
     }
   };
   if (kernel == CPC_K_DENSE_GEMV) {
-    // the dense products of every selected level, both directions, captured once as a
-    // graph and replayed reps times between one pair of events (launch gaps kept
-    // small, no per-launch event overhead); one launch per block and direction
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
+    // the dense products of every selected level, both directions (one launch per
+    // block and direction), each launch stamping its own start and end into a pair of
+    // events, so that the mean is that of the kernels, not of the gaps between them
+    std::vector<hipEvent_t> pool;
     try {
-      int count = 0;
       double bytes = 0.0, mbytes = 0.0;
       const double eb = f32 ? 4.0 : 8.0, vb = f32 ? 4.0 : 8.0;
       // the method's share: the forward and backward triangular solves these products
       // evaluate, spread over their launches
       for (int d : levels) mbytes += method_kernel_bytes(h, CPC_K_FGS, d) + method_kernel_bytes(h, CPC_K_BGS, d);
-      HIPCHK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      std::vector<std::pair<int, int>> items;  // (level, block or -1 for the whole level)
       for (int d : levels) {
-        Level& L = h->lev[d];
-        void* f = d == 0 ? h->pin : L.f;
-        void* u = d == 0 ? h->u1 : L.u;
-        auto both = [&](const DenseTriDev& dt, double entries, double rows) {
-          launch_dense_lower(h->stream, dt, f32, f32, f, u, nullptr);
-          launch_dense_lower_t(h->stream, dt, f32, f32, f, u, nullptr);
-          count += 2;
-          bytes += 2.0 * (eb * entries + 2.0 * vb * rows);
-        };
-        if (L.bdense) {
-          const int K = (int)L.bd_start.size() - 1;
-          for (int b = 0; b < K; ++b) {
-            const DenseTriDev dt = bd_block(L, b);
-            const double nb = L.bd_start[b + 1] - L.bd_start[b];
-            both(dt, 0.5 * nb * (nb + 1), nb);
-          }
-        } else {
-          both(L.dtri, L.dense_entries, (double)L.nS);
+        const Level& L = h->lev[d];
+        const int K = L.bdense ? (int)L.bd_start.size() - 1 : 1;
+        for (int b = 0; b < K; ++b) {
+          items.push_back({d, L.bdense ? b : -1});
+          const double nb = L.bdense ? L.bd_start[b + 1] - L.bd_start[b] : (double)L.nS;
+          const double entries = L.bdense ? 0.5 * nb * (nb + 1) : L.dense_entries;
+          bytes += 2.0 * (eb * entries + 2.0 * vb * nb);
         }
       }
-      HIPCHK(hipStreamEndCapture(h->stream, &g));
-      HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-      const float ms = time_ms(h, reps, [&] { HIPCHK(hipGraphLaunch(ge, h->stream)); });
-      (void)hipGraphExecDestroy(ge);
-      (void)hipGraphDestroy(g);
-      if (avg_ms) *avg_ms = ms / count;
+      const int count = 2 * (int)items.size();
+      pool.resize(2 * (size_t)count);
+      for (auto& e : pool) HIPCHK(hipEventCreate(&e));
+      auto pass = [&](bool timed) {
+        int q = 0;
+        for (const auto& it : items) {
+          Level& L = h->lev[it.first];
+          void* f = it.first == 0 ? h->pin : L.f;
+          void* u = it.first == 0 ? h->u1 : L.u;
+          const DenseTriDev dt = it.second >= 0 ? bd_block(L, it.second) : L.dtri;
+          for (int dir = 0; dir < 2; ++dir, ++q) {
+            hipEvent_t e0 = timed ? pool[2 * q] : nullptr, e1 = timed ? pool[2 * q + 1] : nullptr;
+            if (dir == 0) launch_dense_lower(h->stream, dt, f32, f32, f, u, nullptr, e0, e1);
+            else launch_dense_lower_t(h->stream, dt, f32, f32, f, u, nullptr, e0, e1);
+          }
+        }
+      };
+      pass(false);  // warm-up
+      double ms = 0.0;
+      for (int r = 0; r < reps; ++r) {
+        pass(true);
+        HIPCHK(hipEventSynchronize(pool.back()));
+        for (int q = 0; q < count; ++q) {
+          float t = 0.f;
+          HIPCHK(hipEventElapsedTime(&t, pool[2 * q], pool[2 * q + 1]));
+          ms += t;
+        }
+      }
+      for (auto& e : pool) (void)hipEventDestroy(e);
+      pool.clear();
+      if (avg_ms) *avg_ms = ms / ((double)reps * count);
       if (bytes_per_launch) *bytes_per_launch = mbytes / count;
       if (form_bytes_per_launch) *form_bytes_per_launch = bytes / count;
       if (launches) *launches = reps * count;
       HIPCHK(hipGetLastError());
     } catch (const HipError& e) {
-      if (ge) (void)hipGraphExecDestroy(ge);
-      if (g) (void)hipGraphDestroy(g);
-      (void)hipStreamEndCapture(h->stream, &g);
+      for (auto& ev : pool) (void)hipEventDestroy(ev);
       return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
     }
     return CPC_OK;
