@@ -307,6 +307,81 @@ def test_rs_splitting_invariants(seed):
     del rng
 
 
+def _grid(nx, ny, diag, couplings):
+    """Dense matrix on an nx x ny grid: a_ii = diag, a_ij = -w for each (dx, dy, w)."""
+    n = nx * ny
+    a = np.zeros((n, n))
+    for y in range(ny):
+        for x in range(nx):
+            i = x + nx * y
+            a[i, i] = diag
+            for dx, dy, w in couplings:
+                for sx, sy in ((dx, dy), (-dx, -dy)):
+                    if 0 <= x + sx < nx and 0 <= y + sy < ny:
+                        a[i, x + sx + nx * (y + sy)] = -w
+    return a
+
+
+def _rs_2d_matrix(name):
+    five = [(1, 0, 1.0), (0, 1, 1.0)]
+    nine = five + [(1, 1, 1.0), (1, -1, 1.0)]
+    if name == "five_point_3x3":
+        return _grid(3, 3, 4.0, five)
+    if name == "five_point_4x4":
+        return _grid(4, 4, 4.0, five)
+    if name == "nine_point_3x3":
+        return _grid(3, 3, 8.0, nine)
+    if name == "nine_point_5x5":
+        return _grid(5, 5, 8.0, nine)
+    if name == "anisotropic_5x3":
+        return _grid(5, 3, 2.2, [(1, 0, 1.0), (0, 1, 0.1)])
+    cpl = _RS_2D[name]["couplings"]
+    n = 1 + max(max(i, j) for i, j, _ in cpl)
+    a = np.zeros((n, n))
+    for i, j, w in cpl:
+        a[i, j] = a[j, i] = -w
+    np.fill_diagonal(a, 1.0 - a.sum(axis=1))
+    return a
+
+
+_RS_2D = json.load(open(os.path.join(GOLDEN, "rs_2d_handworked.json")))["cases"]
+
+
+@pytest.mark.parametrize("name", sorted(_RS_2D))
+def test_rs_handworked_grids(name):
+    """Classical splitting and interpolation (Section 3.2) on 2-D grids and on small
+    graphs chosen so that a wrong tie-break, lambda counted over S_i instead of S_i^T,
+    or a missing lambda update changes the splitting; against splittings and weights
+    worked by hand (fixture tests/golden/rs_2d_handworked.json, derivations in it)."""
+    g = _RS_2D[name]
+    A = _rs_2d_matrix(name)
+    n, rp, ci, v = dense_to_csr(A)
+    cf, nc = oracle.rs_split(n, rp, ci, v)
+    assert cf.tolist() == g["cf"], name
+    h = oracle.Hierarchy(n, rp, ci, v, max_coarse=1, max_levels=2)
+    assert h.nlev == 2 and h.cf(0).tolist() == g["cf"]
+    prp, pci, pv = h.prolongation(0)
+    if "p_rows" in g:
+        for i in range(n):
+            got = list(zip(pci[prp[i]:prp[i + 1]].tolist(), pv[prp[i]:prp[i + 1]].tolist()))
+            want = [(c, w) for c, w in g["p_rows"][i]]
+            assert [c for c, _ in got] == [c for c, _ in want], (name, i)
+            assert np.allclose([w for _, w in got], [w for _, w in want], rtol=1e-14, atol=0), (name, i)
+    if "p_weight_edge_rows" in g:
+        nx = g["nx"]
+        for i in range(n):
+            if g["cf"][i]:
+                continue
+            y = i // nx
+            want = g["p_weight_middle_row"] if y == 1 else g["p_weight_edge_rows"]
+            for q in range(prp[i], prp[i + 1]):
+                assert abs(pv[q] - want) <= 1e-14 * want, (name, i)
+    if "coarse" in g:
+        crp, cci, cv = h.level(1)
+        m = crp.size - 1
+        assert np.array_equal(gen.csr_to_dense(m, crp, cci, cv), np.array(g["coarse"]))
+
+
 def test_rs_interpolation_preserves_constants_on_zero_row_sum():
     """Classical interpolation reproduces constants where the row sum of A is zero
     and every coupling is strong and negative (a_ii = -sum a_ij)."""
