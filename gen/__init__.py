@@ -18,3 +18,4 @@ from .tpfa import (  # noqa: F401
     scaled_config,
     csr_to_dense,
 )
+from .wide import wide_band  # noqa: F401,E402

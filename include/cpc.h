@@ -290,8 +290,9 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
  * build for it alone) and concatenates them level by level; cpc_solve_batch runs PCG
  * on all systems at once, one HIP-graph replay per iteration, with per-system
  * scalars and stopping, so each system's iterates are those of its own solve.
- *   nsys                      : number of systems (>= 1); every system needs more than
- *                               max_coarse rows when nsys > 1.
+ *   nsys                      : number of systems (>= 1). A system of at most max_coarse
+ *                               rows is its own coarsest level: its V-cycle is the exact
+ *                               solve, as for a one-level hierarchy alone.
  *   n[s], row_ptr[s], col_idx[s], val[s] : host CSR of system s (copied).
  * Vectors of a batch are concatenated in system order: system s occupies entries
  * [offset_s, offset_s + n[s]) (offsets from cpc_batch_info). */

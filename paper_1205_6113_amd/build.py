@@ -83,7 +83,7 @@ def build(verbose: bool = False) -> Path:
     os.replace(tmp, LIB)
     # host-only library of the SETUP code (no GPU needed), used by CPU tests
     tmp = HOST_LIB.with_suffix(".so.tmp")
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", f"-I{INCLUDE}", "-o", str(tmp),
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off", f"-I{INCLUDE}", "-o", str(tmp),
            str(CSRC / "host_setup.cpp"), str(CSRC / "host_check.cpp")]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -109,16 +109,21 @@ int cpch_sweep(int n, const int* rp, const int* ci, const double* v, int forward
 // taken by another row, or never, -5 no pack (a row longer than every shape), -6 the
 // blocks' dependency graph has a cycle.
 int cpch_wave_emulate(int n, const int* rp, const int* ci, const double* v, int forward, int W, int M, int unit,
-                      int ring, const double* f, double* x, int* shape) {
+                      int ring, const double* f, double* x, int* shape, const int* parts, int nparts) {
   HostCsr a = make_csr(n, rp, ci, v);
-  const int stride = cpc::dominant_stride(a);
+  int stride = cpc::dominant_stride(a);
   cpc::WaveSchedule s;
-  if (!cpc::build_wave_schedule(a, forward != 0, W, M, stride, s)) return -6;
+  if (parts && nparts > 0) {  // per-system schedules of a block-diagonal matrix
+    cpc::build_wave_schedule_parts(a, forward != 0, W, M, std::vector<int>(parts, parts + nparts + 1), 4, s);
+    stride = s.stride;
+  } else if (!cpc::build_wave_schedule(a, forward != 0, W, M, stride, s)) {
+    return -6;
+  }
   std::vector<std::pair<int, int>> shapes;
   for (int tb : {1, 2, 4, 8, 16})
     for (int k : {2, 4}) shapes.push_back({tb, k});
   cpc::WavePack w;
-  if (!cpc::build_wave_pack(a, a.v, s, shapes, w)) return -5;
+  if (!cpc::build_wave_pack(a, a.v, s, shapes, w, 3)) return -5;
   const int K = w.k, TB = w.tb, G = 64 / TB;
   shape[0] = TB;
   shape[1] = K;

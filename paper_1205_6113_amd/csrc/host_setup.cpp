@@ -6,6 +6,9 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <tuple>
+#include <thread>
+#include <atomic>
 #include <queue>
 #include <map>
 #include <functional>
@@ -721,16 +724,97 @@ bool build_wave_schedule(const HostCsr& a, bool forward, int W, int M, int strid
   return true;
 }
 
+void build_wave_schedule_parts(const HostCsr& a, bool forward, int W, int M, const std::vector<int>& parts,
+                               int threads, WaveSchedule& s) {
+  const int np = (int)parts.size() - 1;
+  std::vector<WaveSchedule> ps(np);
+  auto one = [&](int p) {
+    const int r0 = parts[p], r1 = parts[p + 1];
+    HostCsr sub;
+    sub.n = sub.ncols = r1 - r0;
+    sub.rp.resize(sub.n + 1);
+    for (int i = r0; i <= r1; ++i) sub.rp[i - r0] = a.rp[i] - a.rp[r0];
+    sub.ci.resize(sub.rp[sub.n]);
+    for (int q = a.rp[r0]; q < a.rp[r1]; ++q) sub.ci[q - a.rp[r0]] = a.ci[q] - r0;
+    const int stride = dominant_stride(sub);
+    // a part whose segmented blocks would depend on each other in a cycle falls back
+    // to contiguous blocks of the same number of rows
+    if (!build_wave_schedule(sub, forward, W, M, stride, ps[p])) build_wave_schedule(sub, forward, W * M, 1, 0, ps[p]);
+  };
+  threads = std::max(1, std::min(threads, np));
+  if (threads == 1) {
+    for (int p = 0; p < np; ++p) one(p);
+  } else {
+    std::atomic<int> next{0};
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t)
+      pool.emplace_back([&] {
+        for (int p = next++; p < np; p = next++) one(p);
+      });
+    for (auto& th : pool) th.join();
+  }
+  if (np == 1) {
+    s = std::move(ps[0]);
+    return;
+  }
+  // merge: each part's blocks keep their order; parts interleave by the fraction of
+  // their blocks already placed
+  std::vector<std::tuple<double, int, int>> key;  // (position, part, local block)
+  for (int p = 0; p < np; ++p)
+    for (int t = 0; t < ps[p].nblk; ++t) key.emplace_back((t + 0.5) / ps[p].nblk, p, t);
+  std::stable_sort(key.begin(), key.end());
+  s = WaveSchedule{};
+  s.forward = forward;
+  s.n = a.n;
+  s.W = W;
+  s.M = M;
+  s.slot.assign(a.n, 0);
+  s.block_of.assign(a.n, 0);
+  s.blk_ptr.push_back(0);
+  s.blk_lvl.push_back(0);
+  s.lvl_ptr.push_back(0);
+  s.rows.reserve(a.n);
+  for (const auto& kt : key) {
+    const int p = std::get<1>(kt), t = std::get<2>(kt);
+    const WaveSchedule& q = ps[p];
+    const int r0 = parts[p];
+    const int tb = (int)s.blk_ptr.size() - 1;
+    for (int m = q.blk_lvl[t]; m < q.blk_lvl[t + 1]; ++m) {
+      for (int k = q.lvl_ptr[m]; k < q.lvl_ptr[m + 1]; ++k) {
+        const int i = q.rows[k] + r0;
+        s.rows.push_back(i);
+        s.slot[i] = q.slot[q.rows[k]];
+        s.block_of[i] = tb;
+      }
+      s.lvl_ptr.push_back((int)s.rows.size());
+    }
+    s.blk_ptr.push_back((int)s.rows.size());
+    s.blk_lvl.push_back((int)s.lvl_ptr.size() - 1);
+    s.R = std::max(s.R, q.blk_ptr[t + 1] - q.blk_ptr[t]);
+  }
+  s.nblk = (int)s.blk_ptr.size() - 1;
+  for (const auto& q : ps) {
+    s.global_depth = std::max(s.global_depth, q.global_depth);
+    s.stride = std::max(s.stride, q.stride);
+  }
+}
+
 bool build_wave_pack(const HostCsr& a, const std::vector<double>& vals, const WaveSchedule& s,
-                     const std::vector<std::pair<int, int>>& shapes, WavePack& w) {
+                     const std::vector<std::pair<int, int>>& shapes, WavePack& w, int threads) {
   const int n = a.n;
   const bool fwd = s.forward;
-  int maxlen = 0;
-  for (int i = 0; i < n; ++i) {
-    int c = 0;
-    for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) c += fwd ? (a.ci[q] < i) : (a.ci[q] > i);
-    maxlen = std::max(maxlen, c);
-  }
+  std::vector<int> part_max(std::max(1, threads), 0);
+  std::atomic<int> slot_next{0};
+  chunked(n, threads, 65536, [&](int64_t lo, int64_t hi) {
+    int m = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+      int c = 0;
+      for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) c += fwd ? (a.ci[q] < i) : (a.ci[q] > i);
+      m = std::max(m, c);
+    }
+    part_max[slot_next++] = m;
+  });
+  const int maxlen = *std::max_element(part_max.begin(), part_max.end());
   const int nlev = (int)s.lvl_ptr.size() - 1;
   int tb = 0, K = 0;
   int64_t best = 0;
@@ -753,37 +837,50 @@ bool build_wave_pack(const HostCsr& a, const std::vector<double>& vals, const Wa
   w.nblk = s.nblk;
   w.R = s.R;
   w.nsteps = best;
+  // first step of every block
   w.blk_step.assign(s.nblk + 1, 0);
-  w.row.assign(S * G, -1);
-  w.slot.assign(S * G, s.R);
-  w.dinv.assign(S * G, 0.0);
-  w.col.assign(S * K * 64, s.R);
-  w.val.assign(S * K * 64, 0.0);
-  size_t st = 0;
   for (int t = 0; t < s.nblk; ++t) {
-    w.blk_step[t] = (int)st;
-    for (int m = s.blk_lvl[t]; m < s.blk_lvl[t + 1]; ++m) {
-      for (int p0 = s.lvl_ptr[m]; p0 < s.lvl_ptr[m + 1]; p0 += G, ++st) {
-        const int p1 = std::min(p0 + G, s.lvl_ptr[m + 1]);
-        for (int p = p0; p < p1; ++p) {
-          const int gi = p - p0, i = s.rows[p];
-          w.row[st * G + gi] = i;
-          w.slot[st * G + gi] = s.slot[i];
-          int e = 0;
-          for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
-            const int j = a.ci[q];
-            if (j == i) w.dinv[st * G + gi] = 1.0 / vals[q];
-            if (!(fwd ? j < i : j > i)) continue;
-            const size_t at = st * K * 64 + (size_t)(e / tb) * 64 + gi * tb + e % tb;
-            w.col[at] = s.block_of[j] == t ? s.slot[j] : -(j + 1);
-            w.val[at] = vals[q];
-            ++e;
+    int64_t c = 0;
+    for (int m = s.blk_lvl[t]; m < s.blk_lvl[t + 1]; ++m) c += (s.lvl_ptr[m + 1] - s.lvl_ptr[m] + G - 1) / G;
+    w.blk_step[t + 1] = w.blk_step[t] + (int)c;
+  }
+  w.row.resize(S * G);
+  w.slot.resize(S * G);
+  w.dinv.resize(S * G);
+  w.col.resize(S * K * 64);
+  w.val.resize(S * K * 64);
+  // blocks fill disjoint step ranges: padding first, then the rows' entries
+  chunked(s.nblk, threads, 4, [&](int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t) {
+      const size_t b0 = (size_t)w.blk_step[t], b1 = (size_t)w.blk_step[t + 1];
+      std::fill(w.row.begin() + b0 * G, w.row.begin() + b1 * G, -1);
+      std::fill(w.slot.begin() + b0 * G, w.slot.begin() + b1 * G, s.R);
+      std::fill(w.dinv.begin() + b0 * G, w.dinv.begin() + b1 * G, 0.0);
+      std::fill(w.col.begin() + b0 * K * 64, w.col.begin() + b1 * K * 64, s.R);
+      std::fill(w.val.begin() + b0 * K * 64, w.val.begin() + b1 * K * 64, 0.0);
+      size_t st = b0;
+      for (int m = s.blk_lvl[t]; m < s.blk_lvl[t + 1]; ++m) {
+        for (int p0 = s.lvl_ptr[m]; p0 < s.lvl_ptr[m + 1]; p0 += G, ++st) {
+          const int p1 = std::min(p0 + G, s.lvl_ptr[m + 1]);
+          for (int p = p0; p < p1; ++p) {
+            const int gi = p - p0, i = s.rows[p];
+            w.row[st * G + gi] = i;
+            w.slot[st * G + gi] = s.slot[i];
+            int e = 0;
+            for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
+              const int j = a.ci[q];
+              if (j == i) w.dinv[st * G + gi] = 1.0 / vals[q];
+              if (!(fwd ? j < i : j > i)) continue;
+              const size_t at = st * K * 64 + (size_t)(e / tb) * 64 + gi * tb + e % tb;
+              w.col[at] = s.block_of[j] == t ? s.slot[j] : -(j + 1);
+              w.val[at] = vals[q];
+              ++e;
+            }
           }
         }
       }
     }
-  }
-  w.blk_step[s.nblk] = (int)st;
+  });
   return true;
 }
 

@@ -6,6 +6,9 @@
 
 #include <cstdint>
 #include <string>
+#include <algorithm>
+#include <memory>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -103,6 +106,15 @@ int dominant_stride(const HostCsr& a);
 // Returns false when the blocks' dependency graph has a cycle.
 bool build_wave_schedule(const HostCsr& a, bool forward, int W, int M, int stride, WaveSchedule& s);
 
+// The same for a block-diagonal matrix whose diagonal blocks are the row ranges
+// [parts[p], parts[p+1]) (the systems of a batch; {0, n} for one system): each part
+// gets its own schedule with its own dominant coupling distance (contiguous blocks
+// where its segmented blocks would form a cycle), built on up to `threads` host
+// threads, and the parts' blocks are merged in an interleaved order (blocks of
+// different parts are independent). Always succeeds.
+void build_wave_schedule_parts(const HostCsr& a, bool forward, int W, int M, const std::vector<int>& parts,
+                               int threads, WaveSchedule& s);
+
 // One-wave form of a triangular solve over a wave schedule (the layout the kernel
 // reads): each level of each block cut into steps of G = 64 / tb rows, a row's
 // dependency entries dealt over its tb lanes (entry e on lane e % tb at position
@@ -110,20 +122,60 @@ bool build_wave_schedule(const HostCsr& a, bool forward, int W, int M, int strid
 // holds zero) and value 0, padding groups with row -1. Columns: the slot of j inside
 // the row's block, -(j + 1) outside. (tb, k) is the shape from `shapes` that holds the
 // longest row in the fewest steps (then the smallest k).
+// fn(lo, hi) over [0, count) cut into contiguous chunks of at least `grain` items, on
+// up to `threads` host threads (fn must not throw).
+template <typename F>
+void chunked(int64_t count, int threads, int64_t grain, F fn) {
+  threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, count / std::max<int64_t>(grain, 1) + 1));
+  if (threads == 1) {
+    fn((int64_t)0, count);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t)
+    pool.emplace_back([&, t] { fn(count * t / threads, count * (t + 1) / threads); });
+  for (auto& th : pool) th.join();
+}
+
+// Allocator whose resize leaves new elements uninitialised: the large pack arrays are
+// then first touched by the threads that fill them (page faults in parallel).
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  using value_type = T;
+  template <typename U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <typename U, typename... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+};
+template <typename T>
+using RawVec = std::vector<T, NoInitAlloc<T>>;
+
 struct WavePack {
   int tb = 0, k = 0, nblk = 0, R = 0;
   int64_t nsteps = 0;
   std::vector<int> blk_step;  // nblk + 1, processing order
-  std::vector<int> row;       // nsteps * (64 / tb)
-  std::vector<int> slot;      // nsteps * (64 / tb), LDS slot of the row
-  std::vector<double> dinv;   // nsteps * (64 / tb), reciprocal diagonal (0 for padding)
-  std::vector<int> col;       // nsteps * k * 64
-  std::vector<double> val;    // nsteps * k * 64
+  RawVec<int> row;            // nsteps * (64 / tb)
+  RawVec<int> slot;           // nsteps * (64 / tb), LDS slot of the row
+  RawVec<double> dinv;        // nsteps * (64 / tb), reciprocal diagonal (0 for padding)
+  RawVec<int> col;            // nsteps * k * 64
+  RawVec<double> val;         // nsteps * k * 64
 };
 
-// Returns false (w untouched) when no shape holds the longest row.
+// Returns false (w untouched) when no shape holds the longest row. Built on up to
+// `threads` host threads (blocks fill disjoint ranges).
 bool build_wave_pack(const HostCsr& a, const std::vector<double>& vals, const WaveSchedule& s,
-                     const std::vector<std::pair<int, int>>& shapes, WavePack& w);
+                     const std::vector<std::pair<int, int>>& shapes, WavePack& w, int threads = 1);
 
 // Block starts used by build_sweep (size nblk + 1, last = n).
 std::vector<int> sweep_block_starts(const HostCsr& a, int R);

@@ -11,6 +11,8 @@
 // result is bit-identical to any sequential evaluation in the same order.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "kernels.hpp"
 
 namespace cpc {
@@ -148,11 +150,11 @@ void launch_spgemm_fill(hipStream_t s, int nrows, const int* xrp, const int* xci
                         const int* yci, const double* yv, const int* crp, int* cci, double* cv, int* overflow) {
   if (nrows <= 0) return;
   const size_t lds = (sizeof(double) * 2 + sizeof(int) * 2) * kCap;
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::atomic<bool> attr_set{false};  // batch setups launch from several host threads
+  if (!attr_set.load()) {
     if (hipFuncSetAttribute((const void*)spgemm_fill_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) ==
         hipSuccess)
-      attr_set = true;
+      attr_set.store(true);
     else
       (void)hipGetLastError();
   }

@@ -13,8 +13,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <thread>
 #include <map>
+#include <set>
 #include <chrono>
+#include <exception>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -60,8 +65,8 @@ T* dalloc(size_t count, std::vector<void*>& owned) {
   return static_cast<T*>(p);
 }
 
-template <typename T>
-T* dupload(const std::vector<T>& h, std::vector<void*>& owned, hipStream_t s) {
+template <typename T, typename A>
+T* dupload(const std::vector<T, A>& h, std::vector<void*>& owned, hipStream_t s) {
   T* d = dalloc<T>(h.size(), owned);
   if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return d;
@@ -139,7 +144,9 @@ struct Level {
   std::vector<void*> sweep_owned;
   int sweep_rows = 0;  // rows the sweeps cover (all rows at depth 0 for ILU(0), else the smoothed ones)
   int sweep_R = 0;     // rows per block requested for them
+  std::vector<int> parts;  // row ranges of the systems among the swept rows (batches; empty: one)
   int wave_M = 0;      // segments per block of the one-wave form (0: chosen by rule)
+  bool wave_off = false;  // the four-wave kernel takes the level's solves (tuner's choice)
   int wave_stride = -1;  // the matrix's dominant coupling distance (-1: not yet measured)
   // block-dense form of the smoother: block forward/backward substitution with explicit
   // inverses of the diagonal blocks of D+L (levels where it beats the sweeps)
@@ -228,26 +235,27 @@ struct cpc_solver {
 namespace cpc {
 
 static void upload_csr(cpc_solver* h, const HostCsr& a, DevCsr& d, bool with_dpos, std::vector<void*>* into = nullptr,
-                       bool with_f32 = true) {
+                       bool with_f32 = true, hipStream_t stream = nullptr) {
   std::vector<void*>& own = into ? *into : h->owned;
+  const hipStream_t st = stream ? stream : h->stream;
   d.n = a.n;
   d.ncols = a.ncols;
   d.nnz = a.nnz();
-  d.rp = dupload(a.rp, own, h->stream);
-  d.ci = dupload(a.ci, own, h->stream);
-  d.v = dupload(a.v, own, h->stream);
+  d.rp = dupload(a.rp, own, st);
+  d.ci = dupload(a.ci, own, st);
+  d.v = dupload(a.v, own, st);
   if (with_dpos) {
     std::vector<int> dp(a.n, -1);
     for (int i = 0; i < a.n; ++i)
       for (int k = a.rp[i]; k < a.rp[i + 1]; ++k)
         if (a.ci[k] == i) dp[i] = k;
-    d.dpos = dupload(dp, own, h->stream);
+    d.dpos = dupload(dp, own, st);
   }
   d.tpr = pick_tpr(a.n ? (double)d.nnz / a.n : 1.0);
   d.steps = pick_steps(a.n ? (double)d.nnz / a.n : 1.0, d.tpr);
   if (h->f32 && with_f32) {
     d.v32 = dalloc<float>((size_t)d.nnz, own);
-    launch_to_f32(h->stream, d.nnz, d.v, d.v32);
+    launch_to_f32(st, d.nnz, d.v, d.v32);
   }
 }
 
@@ -288,21 +296,22 @@ static DenseListDev upload_dense_list(cpc_solver* h, const std::vector<int>& off
 
 // Galerkin product on the GPU: C = X * Y with the canonical order (rap.hip).
 static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncols, HostCsr& C_host, DevCsr& C,
-                       std::string* msg, std::vector<void*>& keep) {
+                       std::string* msg, std::vector<void*>& keep, hipStream_t stream = nullptr) {
+  const hipStream_t hs = stream ? stream : h->stream;
   const int nrows = X.n;
   std::vector<void*> tmp;
   int* counts = dalloc<int>(nrows, tmp);
   int* ovf = dalloc<int>(1, tmp);
   bool ok = true;
   try {
-    HIPCHK(hipMemsetAsync(ovf, 0, sizeof(int), h->stream));
-    launch_spgemm_count(h->stream, nrows, X.rp, X.ci, Y.rp, Y.ci, counts, ovf);
+    HIPCHK(hipMemsetAsync(ovf, 0, sizeof(int), hs));
+    launch_spgemm_count(hs, nrows, X.rp, X.ci, Y.rp, Y.ci, counts, ovf);
     HIPCHK(hipGetLastError());
     std::vector<int> hc(nrows);
     int hovf = 0;
-    HIPCHK(hipMemcpyAsync(hc.data(), counts, sizeof(int) * nrows, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpyAsync(hc.data(), counts, sizeof(int) * nrows, hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, hs));
+    HIPCHK(hipStreamSynchronize(hs));
     if (hovf) {
       if (msg) *msg = "Galerkin product row exceeds " + std::to_string(spgemm_table_capacity()) + " columns";
       ok = false;
@@ -324,17 +333,17 @@ static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncol
         C.n = nrows;
         C.ncols = ncols;
         C.nnz = tot;
-        C.rp = dupload(C_host.rp, keep, h->stream);
+        C.rp = dupload(C_host.rp, keep, hs);
         C.ci = dalloc<int>((size_t)tot, keep);
         C.v = dalloc<double>((size_t)tot, keep);
-        launch_spgemm_fill(h->stream, nrows, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v, ovf);
+        launch_spgemm_fill(hs, nrows, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v, ovf);
         HIPCHK(hipGetLastError());
         C_host.ci.resize(tot);
         C_host.v.resize(tot);
-        HIPCHK(hipMemcpyAsync(C_host.ci.data(), C.ci, sizeof(int) * tot, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(C_host.v.data(), C.v, sizeof(double) * tot, hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
+        HIPCHK(hipMemcpyAsync(C_host.ci.data(), C.ci, sizeof(int) * tot, hipMemcpyDeviceToHost, hs));
+        HIPCHK(hipMemcpyAsync(C_host.v.data(), C.v, sizeof(double) * tot, hipMemcpyDeviceToHost, hs));
+        HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, hs));
+        HIPCHK(hipStreamSynchronize(hs));
         if (hovf) {
           ok = false;
           if (msg) *msg = "Galerkin product table overflow";
@@ -386,12 +395,20 @@ static int sweep_layout(const SweepSchedule& s, int esz, int pcap, SweepDev& sd)
 // Schedule of one triangular solve of `a` (forward: lower, backward: upper) in blocks
 // of at most R rows, uploaded, with levels cut so that their products fit the LDS the
 // block's other arrays leave.
-static SweepSchedule make_sweep(cpc_solver* h, const HostCsr& a, bool forward, int R, DevSweepSched& d) {
+// The four-wave kernel's schedule of one direction with R rows per block, its levels
+// cut to fit the LDS budget (host only; throws HipError when no cut fits).
+struct SweepPlan {
+  SweepSchedule s;
+  SweepDev sd{};
+};
+static SweepPlan plan_sweep(const cpc_solver* h, const HostCsr& a, bool forward, int R) {
   const int esz = (int)esz_of(h);
   const int budget = sweep_lds_budget();
   const int nt = sweep_threads();
-  SweepSchedule s = build_sweep(a, forward, R, 0);
-  SweepDev sd{};
+  SweepPlan pl;
+  SweepSchedule& s = pl.s;
+  SweepDev& sd = pl.sd;
+  s = build_sweep(a, forward, R, 0);
   int room = (budget - 16 - sweep_layout(s, esz, 0, sd)) / 8;
   if (room < nt) throw HipError{hipErrorInvalidValue, "sweep block too large for LDS"};
   int64_t cap = s.max_level_entries;
@@ -409,24 +426,72 @@ static SweepSchedule make_sweep(cpc_solver* h, const HostCsr& a, bool forward, i
   sd.nblk = s.nblk;
   sd.nlev = (int)s.lvl_ptr.size() - 1;
   sd.maxl = s.max_local_levels;
-  sd.blk_row = dupload(s.blk_row, *h->cur_owned, h->stream);
-  sd.blk_beg = dupload(s.blk_beg, *h->cur_owned, h->stream);
-  sd.blk_end = dupload(s.blk_end, *h->cur_owned, h->stream);
-  sd.lvl_ptr = dupload(s.lvl_ptr, *h->cur_owned, h->stream);
   sd.grid = std::min(s.nblk, 1024);
   // four waves per block; a one-wave workgroup (no cross-wave barriers) measured
   // slower even where one block covers the matrix, since a level's entries then take
   // four times as many steps per lane
   sd.nt = h->opt.sweep_threads == 64 ? 64 : 256;
+  return pl;
+}
+
+static void upload_sweep(cpc_solver* h, const SweepPlan& pl, DevSweepSched& d) {
+  SweepDev sd = pl.sd;
+  sd.blk_row = dupload(pl.s.blk_row, *h->cur_owned, h->stream);
+  sd.blk_beg = dupload(pl.s.blk_beg, *h->cur_owned, h->stream);
+  sd.blk_end = dupload(pl.s.blk_end, *h->cur_owned, h->stream);
+  sd.lvl_ptr = dupload(pl.s.lvl_ptr, *h->cur_owned, h->stream);
   d.d = sd;
-  d.global_depth = s.global_depth;
-  return s;
+  d.global_depth = pl.s.global_depth;
+}
+
+// fa() and fb() on two host threads; an exception of either is rethrown after both end.
+template <typename FA, typename FB>
+static void both(FA fa, FB fb) {
+  std::exception_ptr ea, eb;
+  std::thread t([&] {
+    try {
+      fa();
+    } catch (...) {
+      ea = std::current_exception();
+    }
+  });
+  try {
+    fb();
+  } catch (...) {
+    eb = std::current_exception();
+  }
+  t.join();
+  if (ea) std::rethrow_exception(ea);
+  if (eb) std::rethrow_exception(eb);
 }
 
 static void spmv_or_throw(cpc_solver* h, const MatDev& A, int mode, const void* x, bool xf32, const void* f,
                           bool ff32, void* y, bool yf32, int tpr, const int* done) {
   if (!launch_spmv(h->stream, A, mode, x, xf32, f, ff32, y, yf32, tpr, done))
     throw HipError{hipErrorInvalidValue, "unsupported SpMV precision combination"};
+}
+
+// fn(i) for i in [0, count) on up to `threads` host threads (fn must not throw).
+template <typename F>
+static void parallel_for(int count, int threads, F fn) {
+  threads = std::max(1, std::min(threads, count));
+  if (threads == 1) {
+    for (int i = 0; i < count; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t)
+    pool.emplace_back([&] {
+      for (int i = next++; i < count; i = next++) fn(i);
+    });
+  for (auto& th : pool) th.join();
+}
+
+// Host threads for per-system setup work: the machine's, at most 16.
+static int setup_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(hc ? hc : 1u, 16u));
 }
 
 // Upload the one-wave form of a triangular solve (wave_sweep.hip) over a wave
@@ -437,11 +502,13 @@ static WaveDev upload_wave(cpc_solver* h, const HostCsr& a, const std::vector<do
                            const WaveDev* share) {
   WaveDev w{};
   std::vector<std::pair<int, int>> shapes;
+  // up to 64 dependency entries per row: longer rows (wide Galerkin levels) run faster
+  // in the four-wave kernel, which keeps four times as many rows in flight per block
   for (int tb : {1, 2, 4, 8, 16})
     for (int k : {2, 4})
       if (wave_shape_supported(tb, k)) shapes.push_back({tb, k});
   WavePack wp;
-  if (!build_wave_pack(a, vals, s, shapes, wp)) return w;
+  if (!build_wave_pack(a, vals, s, shapes, wp, setup_threads())) return w;
   if (wave_lds_bytes(wp.R, h->f32) > 150 * 1024) return w;
   if (share && share->ok && (share->tb != wp.tb || share->k != wp.k)) share = nullptr;
   w.ok = 1;
@@ -481,87 +548,160 @@ static int wave_segments(int stride, int R) { return stride >= R ? 4 : 1; }
 
 // One-wave forms of the forward and backward solves of `a` (and of the ILU factor's,
 // `lu` non-null) with R rows per block in M segments, into the packs given.
-static void build_wave_forms(cpc_solver* h, const HostCsr& a, int R, int M, int stride, SweepPackDev& lo,
-                             SweepPackDev& up, const std::vector<double>* lu, SweepPackDev* ilo, SweepPackDev* iup) {
-  if (h->opt.sweep_kernel == 1) return;
-  const int W = std::max(1, R / std::max(1, M));
-  WaveSchedule wl, wu;
-  if (!build_wave_schedule(a, true, W, M, stride, wl) || !build_wave_schedule(a, false, W, M, stride, wu)) {
-    // blocks that depend on each other in a cycle: contiguous blocks instead
-    if (!build_wave_schedule(a, true, R, 1, 0, wl) || !build_wave_schedule(a, false, R, 1, 0, wu)) return;
+// Largest over the parts of each part's dominant coupling distance.
+static int parts_stride(const HostCsr& a, const std::vector<int>& parts) {
+  int best = 0;
+  for (size_t p = 0; p + 1 < parts.size(); ++p) {
+    std::map<int, int> count;
+    for (int i = parts[p]; i < parts[p + 1]; ++i)
+      if (a.rp[i] < a.rp[i + 1] && a.ci[a.rp[i]] < i) ++count[i - a.ci[a.rp[i]]];
+    int mode = 0, mc = 0;
+    for (const auto& kv : count)
+      if (kv.second > mc) {
+        mode = kv.first;
+        mc = kv.second;
+      }
+    best = std::max(best, mode);
   }
+  return best;
+}
+
+// One-wave forms of the forward and backward solves of `a` (and of the ILU factor's,
+// `lu` non-null) with R rows per block in M segments, each system of `parts` scheduled
+// on its own (the two directions built on two host threads), into the packs given.
+// Returns true when every form was built; depth_lo / depth_up receive the schedules'
+// numbers of level sets.
+static bool build_wave_forms(cpc_solver* h, const HostCsr& a, int R, int M, const std::vector<int>& parts,
+                             SweepPackDev& lo, SweepPackDev& up, const std::vector<double>* lu, SweepPackDev* ilo,
+                             SweepPackDev* iup, int* depth_lo, int* depth_up) {
+  if (h->opt.sweep_kernel == 1) return false;
+  const int W = std::max(1, R / std::max(1, M));
+  const int threads = std::max(1, setup_threads() / 2);
+  WaveSchedule wl, wu;
+  std::thread tl([&] { build_wave_schedule_parts(a, true, W, M, parts, threads, wl); });
+  build_wave_schedule_parts(a, false, W, M, parts, threads, wu);
+  tl.join();
   lo.wave = upload_wave(h, a, a.v, wl, nullptr);
   up.wave = upload_wave(h, a, a.v, wu, nullptr);
+  bool all = lo.wave.ok && up.wave.ok;
   if (lu && ilo && iup) {
     ilo->wave = upload_wave(h, a, *lu, wl, &lo.wave);
     iup->wave = upload_wave(h, a, *lu, wu, &up.wave);
+    all = all && ilo->wave.ok && iup->wave.ok;
   }
+  if (depth_lo) *depth_lo = wl.global_depth;
+  if (depth_up) *depth_up = wu.global_depth;
+  return all;
 }
 
-// Pack the rows of a triangular solve in its processing order: the dependency entries
-// (left of the diagonal forward, right of it backward) with columns in the row's own
-// block stored block-relative and the others as -(j + 1). share: reuse the row/ptr/col
-// arrays of a pack with the same schedule and direction (values differ).
-static SweepPackDev build_pack(cpc_solver* h, const HostCsr& a, const std::vector<double>& vals,
-                               const SweepSchedule& s, const SweepPackDev* share) {
-  SweepPackDev pk{};
+// The rows of a triangular solve packed in its processing order (host side): the
+// dependency entries (left of the diagonal forward, right of it backward) with columns
+// in the row's own block stored block-relative and the others as -(j + 1).
+struct PackHost {
+  std::vector<int> ptr, col;
+  std::vector<double> diag, v;
+  int tb = 1;
+};
+static PackHost pack_host(const HostCsr& a, const std::vector<double>& vals, const SweepSchedule& s) {
+  PackHost ph;
   const int n = a.n;
   const bool fwd = s.forward;
-  std::vector<int> ptr(n + 1, 0);
-  std::vector<double> diag(n, 1.0);  // reciprocal diagonal
-  for (int p = 0; p < n; ++p) {
-    const int i = s.perm[p];
-    int c = 0;
-    for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
-      const int j = a.ci[q];
-      if (j == i) diag[p] = 1.0 / vals[q];
-      else if (fwd ? j < i : j > i) ++c;
-    }
-    ptr[p + 1] = ptr[p] + c;
-  }
-  const int64_t ne = ptr[n];
-  std::vector<int> col((size_t)std::max<int64_t>(ne, 1), 0);
-  std::vector<double> v((size_t)std::max<int64_t>(ne, 1), 0.0);
-  {
-    std::vector<int> blk_of(n);
-    for (int b = 0; b < s.nblk; ++b)
-      for (int i = s.blk_row[b]; i < s.blk_row[b + 1]; ++i) blk_of[i] = b;
-    for (int p = 0; p < n; ++p) {
+  const int nt = setup_threads();
+  std::vector<int>& ptr = ph.ptr;
+  std::vector<double>& diag = ph.diag;  // reciprocal diagonal
+  ptr.assign(n + 1, 0);
+  diag.assign(n, 1.0);
+  chunked(n, nt, 65536, [&](int64_t p0, int64_t p1) {
+    for (int64_t p = p0; p < p1; ++p) {
       const int i = s.perm[p];
-      const int b = blk_of[i];
-      int w = ptr[p];
+      int c = 0;
       for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
         const int j = a.ci[q];
-        if (j == i || !(fwd ? j < i : j > i)) continue;
-        col[w] = (blk_of[j] == b) ? j - s.blk_row[b] : -(j + 1);
-        v[w] = vals[q];
-        ++w;
+        if (j == i) diag[p] = 1.0 / vals[q];
+        else if (fwd ? j < i : j > i) ++c;
       }
+      ptr[p + 1] = c;
     }
+  });
+  for (int p = 0; p < n; ++p) ptr[p + 1] += ptr[p];
+  const int64_t ne = ptr[n];
+  std::vector<int>& col = ph.col;
+  std::vector<double>& v = ph.v;
+  col.assign((size_t)std::max<int64_t>(ne, 1), 0);
+  v.assign((size_t)std::max<int64_t>(ne, 1), 0.0);
+  {
+    std::vector<int> blk_of(n);
+    chunked(s.nblk, nt, 16, [&](int64_t b0, int64_t b1) {
+      for (int64_t b = b0; b < b1; ++b)
+        for (int i = s.blk_row[b]; i < s.blk_row[b + 1]; ++i) blk_of[i] = (int)b;
+    });
+    chunked(n, nt, 65536, [&](int64_t p0, int64_t p1) {
+      for (int64_t p = p0; p < p1; ++p) {
+        const int i = s.perm[p];
+        const int b = blk_of[i];
+        int w = ptr[p];
+        for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) {
+          const int j = a.ci[q];
+          if (j == i || !(fwd ? j < i : j > i)) continue;
+          col[w] = (blk_of[j] == b) ? j - s.blk_row[b] : -(j + 1);
+          v[w] = vals[q];
+          ++w;
+        }
+      }
+    });
   }
+  // lanes per row in the summing phase: about eight products per lane
+  const double avg = n ? (double)ne / n : 0.0;
+  int t = 1;
+  while (t < 64 && t * 8 < avg) t <<= 1;
+  ph.tb = t;
+  return ph;
+}
+
+// share: reuse the row/ptr/col arrays of a pack with the same schedule and direction
+// (values differ).
+static SweepPackDev upload_pack(cpc_solver* h, const PackHost& ph, const SweepSchedule& s,
+                                const SweepPackDev* share) {
+  SweepPackDev pk{};
   if (share) {
     pk.row = share->row;
     pk.ptr = share->ptr;
     pk.col = share->col;
   } else {
     pk.row = dupload(s.perm, *h->cur_owned, h->stream);
-    pk.ptr = dupload(ptr, *h->cur_owned, h->stream);
-    pk.col = dupload(col, *h->cur_owned, h->stream);
+    pk.ptr = dupload(ph.ptr, *h->cur_owned, h->stream);
+    pk.col = dupload(ph.col, *h->cur_owned, h->stream);
   }
   if (h->f32) {
-    std::vector<float> v32(v.begin(), v.end()), d32(diag.begin(), diag.end());
+    std::vector<float> v32(ph.v.begin(), ph.v.end()), d32(ph.diag.begin(), ph.diag.end());
     pk.val = dupload(v32, *h->cur_owned, h->stream);
     pk.diag = dupload(d32, *h->cur_owned, h->stream);
   } else {
-    pk.val = dupload(v, *h->cur_owned, h->stream);
-    pk.diag = dupload(diag, *h->cur_owned, h->stream);
+    pk.val = dupload(ph.v, *h->cur_owned, h->stream);
+    pk.diag = dupload(ph.diag, *h->cur_owned, h->stream);
   }
-  // lanes per row in the summing phase: about eight products per lane
-  const double avg = n ? (double)ne / n : 0.0;
-  int t = 1;
-  while (t < 64 && t * 8 < avg) t <<= 1;
-  pk.tb = t;
+  pk.tb = ph.tb;
   return pk;
+}
+
+// Schedules and packs of both directions of the four-wave kernel (the host work of the
+// two directions on two threads), and those of a second factor on the same schedules
+// (lu non-null: the ILU(0) values).
+static void build_fourwave(cpc_solver* h, const HostCsr& a, int R, DevSweepSched& lo, DevSweepSched& up,
+                           SweepPackDev& fl, SweepPackDev& fu, const std::vector<double>* lu, SweepPackDev* il,
+                           SweepPackDev* iu) {
+  SweepPlan pl, pu;
+  PackHost hl, hu, hil, hiu;
+  both([&] { pl = plan_sweep(h, a, true, R); hl = pack_host(a, a.v, pl.s); if (lu) hil = pack_host(a, *lu, pl.s); },
+       [&] { pu = plan_sweep(h, a, false, R); hu = pack_host(a, a.v, pu.s); if (lu) hiu = pack_host(a, *lu, pu.s); });
+  upload_sweep(h, pl, lo);
+  upload_sweep(h, pu, up);
+  fl = upload_pack(h, hl, pl.s, nullptr);
+  fu = upload_pack(h, hu, pu.s, nullptr);
+  if (lu && il && iu) {
+    *il = upload_pack(h, hil, pl.s, &fl);
+    *iu = upload_pack(h, hiu, pu.s, &fu);
+  }
 }
 
 // x = T^{-1} f for the triangular factor the pack holds (out = base + x for
@@ -592,16 +732,57 @@ static HostCsr strict_lower(const HostCsr& a) {
   HostCsr t;
   t.n = a.n;
   t.ncols = a.ncols;
-  t.rp.assign(1, 0);
-  for (int i = 0; i < a.n; ++i) {
-    for (int q = a.rp[i]; q < a.rp[i + 1]; ++q)
-      if (a.ci[q] < i) {
-        t.ci.push_back(a.ci[q]);
-        t.v.push_back(a.v[q]);
-      }
-    t.rp.push_back((int)t.ci.size());
-  }
+  t.rp.assign(a.n + 1, 0);
+  const int nt = setup_threads();
+  chunked(a.n, nt, 65536, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int c = 0;
+      for (int q = a.rp[i]; q < a.rp[i + 1]; ++q) c += a.ci[q] < i;
+      t.rp[i + 1] = c;
+    }
+  });
+  for (int i = 0; i < a.n; ++i) t.rp[i + 1] += t.rp[i];
+  t.ci.resize(t.rp[a.n]);
+  t.v.resize(t.rp[a.n]);
+  chunked(a.n, nt, 65536, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int w = t.rp[i];
+      for (int q = a.rp[i]; q < a.rp[i + 1]; ++q)
+        if (a.ci[q] < i) {
+          t.ci[w] = a.ci[q];
+          t.v[w++] = a.v[q];
+        }
+    }
+  });
   return t;
+}
+
+// A matrix of nrows x ncols made of blocks placed at row and column offsets; the
+// blocks' row ranges tile [0, nrows). Blocks are copied on host threads.
+struct PlacedBlock {
+  const HostCsr* m;
+  int row_off, col_off;
+};
+static void place_blocks(std::vector<PlacedBlock> blocks, int nrows, int ncols, HostCsr& out) {
+  std::sort(blocks.begin(), blocks.end(),
+            [](const PlacedBlock& x, const PlacedBlock& y) { return x.row_off < y.row_off; });
+  std::vector<int64_t> nz(blocks.size() + 1, 0);
+  for (size_t k = 0; k < blocks.size(); ++k) nz[k + 1] = nz[k] + blocks[k].m->nnz();
+  out.n = nrows;
+  out.ncols = ncols;
+  out.rp.assign(nrows + 1, 0);
+  out.ci.resize(nz.back());
+  out.v.resize(nz.back());
+  parallel_for((int)blocks.size(), setup_threads(), [&](int k) {
+    const HostCsr& m = *blocks[k].m;
+    const int r0 = blocks[k].row_off, c0 = blocks[k].col_off;
+    const int64_t base = nz[k];
+    for (int i = 0; i < m.n; ++i) out.rp[r0 + i + 1] = (int)(base + m.rp[i + 1]);
+    for (int64_t q = 0; q < (int64_t)m.ci.size(); ++q) {
+      out.ci[base + q] = m.ci[q] + c0;
+      out.v[base + q] = m.v[q];
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -617,12 +798,16 @@ struct SysHier {
   std::vector<double> inv;            // dense inverse of A[L-1]
 };
 
-static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::string* msg) {
+// stream: where its Galerkin products run (null: the handle's stream); the host parts
+// touch only S, so systems of a batch can be built on threads of their own.
+static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::string* msg,
+                          hipStream_t stream = nullptr) {
+  const hipStream_t hs = stream ? stream : h->stream;
   std::vector<void*> tmp;
   int status = CPC_OK;
   try {
     DevCsr Ad;
-    upload_csr(h, S.A[0], Ad, false, &tmp, false);
+    upload_csr(h, S.A[0], Ad, false, &tmp, false, hs);
     for (int d = 0;; ++d) {
       const HostCsr& A = S.A[d];
       if (A.n <= o.max_coarse || d + 1 >= o.max_levels) break;
@@ -633,10 +818,10 @@ static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::
       rs_interpolation(A, o.theta, cf, nc, P);
       HostCsr R = transpose(P);
       DevCsr Pd, Rd, APd, Acd;
-      upload_csr(h, P, Pd, false, &tmp, false);
-      upload_csr(h, R, Rd, false, &tmp, false);
+      upload_csr(h, P, Pd, false, &tmp, false, hs);
+      upload_csr(h, R, Rd, false, &tmp, false, hs);
       HostCsr AP, Ac;
-      if (!gpu_spgemm(h, Ad, Pd, nc, AP, APd, msg, tmp) || !gpu_spgemm(h, Rd, APd, nc, Ac, Acd, msg, tmp)) {
+      if (!gpu_spgemm(h, Ad, Pd, nc, AP, APd, msg, tmp, hs) || !gpu_spgemm(h, Rd, APd, nc, Ac, Acd, msg, tmp, hs)) {
         status = CPC_E_NOMEM;
         break;
       }
@@ -664,8 +849,9 @@ static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::
         status = dense_spd_inverse(Lc, S.inv, msg);
       }
     }
-    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipStreamSynchronize(hs));
   } catch (...) {
+    (void)hipStreamSynchronize(hs);
     for (void* p : tmp) (void)hipFree(p);
     throw;
   }
@@ -869,20 +1055,40 @@ static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int 
   std::vector<void*>* prev = h->cur_owned;
   h->cur_owned = &L.sweep_owned;
   try {
-    const int Rw = std::min(R, sweep_max_rows_per_block());  // the four-wave kernel's blocks
-    SweepSchedule lo = make_sweep(h, sub, true, Rw, L.lower);
-    SweepSchedule up = make_sweep(h, sub, false, Rw, L.upper);
-    L.fgs = build_pack(h, sub, sub.v, lo, nullptr);
-    L.bgs = build_pack(h, sub, sub.v, up, nullptr);
-    if (ilu && !h->iluk) {
-      h->ilu_l = build_pack(h, sub, h->lu_host, lo, &L.fgs);
-      h->ilu_u = build_pack(h, sub, h->lu_host, up, &L.bgs);
-    }
-    if (L.wave_stride < 0) L.wave_stride = dominant_stride(sub);
-    const int M = L.wave_M > 0 ? L.wave_M : wave_segments(L.wave_stride, R);
     const bool with_ilu = ilu && !h->iluk;
-    build_wave_forms(h, sub, R, M, L.wave_stride, L.fgs, L.bgs, with_ilu ? &h->lu_host : nullptr,
+    const std::vector<int> parts =
+        (!L.parts.empty() && L.parts.front() == 0 && L.parts.back() == sub.n) ? L.parts : std::vector<int>{0, sub.n};
+    if (L.wave_stride < 0) L.wave_stride = parts_stride(sub, parts);
+    const int M = L.wave_M > 0 ? L.wave_M : wave_segments(L.wave_stride, R);
+    SweepPackDev fw{}, bw{}, ilw{}, iuw{};
+    int dlo = 0, dup = 0;
+    const bool wave_all =
+        !L.wave_off && build_wave_forms(h, sub, R, M, parts, fw, bw, with_ilu ? &h->lu_host : nullptr,
+                                        with_ilu ? &ilw : nullptr, with_ilu ? &iuw : nullptr, &dlo, &dup);
+    if (wave_all) {
+      // the one-wave forms serve every solve of the level: no four-wave schedules
+      L.lower = DevSweepSched{};
+      L.upper = DevSweepSched{};
+      L.lower.d.n = L.upper.d.n = sub.n;
+      L.lower.global_depth = dlo;
+      L.upper.global_depth = dup;
+      L.fgs = fw;
+      L.bgs = bw;
+      if (with_ilu) {
+        h->ilu_l = ilw;
+        h->ilu_u = iuw;
+      }
+    } else {
+      const int Rw = std::min(R, sweep_max_rows_per_block());  // the four-wave kernel's blocks
+      build_fourwave(h, sub, Rw, L.lower, L.upper, L.fgs, L.bgs, with_ilu ? &h->lu_host : nullptr,
                      with_ilu ? &h->ilu_l : nullptr, with_ilu ? &h->ilu_u : nullptr);
+      L.fgs.wave = fw.wave;
+      L.bgs.wave = bw.wave;
+      if (with_ilu) {
+        h->ilu_l.wave = ilw.wave;
+        h->ilu_u.wave = iuw.wave;
+      }
+    }
   } catch (...) {
     h->cur_owned = prev;
     throw;
@@ -898,14 +1104,25 @@ static void build_iluk_sweeps(cpc_solver* h, int R) {
   std::vector<void*>* prev = h->cur_owned;
   h->cur_owned = &h->owned;
   try {
-    const int Rw = std::min(R, sweep_max_rows_per_block());
-    SweepSchedule lo = make_sweep(h, h->iluF, true, Rw, h->ilu_lower);
-    SweepSchedule up = make_sweep(h, h->iluF, false, Rw, h->ilu_upper);
-    h->ilu_l = build_pack(h, h->iluF, h->iluF.v, lo, nullptr);
-    h->ilu_u = build_pack(h, h->iluF, h->iluF.v, up, nullptr);
-    const int stride = dominant_stride(h->iluF);
-    build_wave_forms(h, h->iluF, R, wave_segments(stride, R), stride, h->ilu_l, h->ilu_u, nullptr, nullptr,
-                     nullptr);
+    const std::vector<int> parts{0, h->iluF.n};
+    const int stride = parts_stride(h->iluF, parts);
+    SweepPackDev lw{}, uw{};
+    int dlo = 0, dup = 0;
+    if (build_wave_forms(h, h->iluF, R, wave_segments(stride, R), parts, lw, uw, nullptr, nullptr, nullptr, &dlo,
+                         &dup)) {
+      h->ilu_lower = DevSweepSched{};
+      h->ilu_upper = DevSweepSched{};
+      h->ilu_lower.d.n = h->ilu_upper.d.n = h->iluF.n;
+      h->ilu_lower.global_depth = dlo;
+      h->ilu_upper.global_depth = dup;
+      h->ilu_l = lw;
+      h->ilu_u = uw;
+    } else {
+      const int Rw = std::min(R, sweep_max_rows_per_block());
+      build_fourwave(h, h->iluF, Rw, h->ilu_lower, h->ilu_upper, h->ilu_l, h->ilu_u, nullptr, nullptr, nullptr);
+      h->ilu_l.wave = lw.wave;
+      h->ilu_u.wave = uw.wave;
+    }
   } catch (...) {
     h->cur_owned = prev;
     throw;
@@ -1173,21 +1390,31 @@ static void tune_sweeps(cpc_solver* h) {
     float best = try_r && !skip_r ? cost() : 0.f;
     // build the sweeps with R rows per block (M segments per block in the one-wave form)
     // in a list of their own; keep them if they are faster, else restore the current ones
-    auto try_build = [&](int R, int M) {
+    auto try_build = [&](int R, int M, bool off) {
       DevSweepSched lo = L.lower, up = L.upper;
       SweepPackDev fg = L.fgs, bg = L.bgs, il = h->ilu_l, iu = h->ilu_u;
       const int oldR = L.sweep_R, oldM = L.wave_M;
+      const bool oldOff = L.wave_off;
       std::vector<void*> old;
       old.swap(L.sweep_owned);
       bool built = true;
       L.wave_M = M;
+      L.wave_off = off;
+      const double tb0 = now_s();
       try {
         build_level_sweeps(h, L, sub, R, ilu);
       } catch (const HipError&) {
         built = false;  // the candidate does not fit the sweep kernel's LDS
         (void)hipGetLastError();
       }
+      const double tb1 = now_s();
       const float t = built ? cost() : 0.f;
+      if (built) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "level %zu: %d-row blocks, %d segments (%s): %.3f ms, built in %.2f s", d, R,
+                      L.fgs.wave.ok ? L.fgs.wave.M : 1, L.fgs.wave.ok ? "one-wave" : "four-wave", t, tb1 - tb0);
+        progress(h, buf);
+      }
       if (built && t < best) {
         best = t;
         HIPCHK(hipStreamSynchronize(h->stream));
@@ -1204,23 +1431,48 @@ static void tune_sweeps(cpc_solver* h) {
         h->ilu_u = iu;
         L.sweep_R = oldR;
         L.wave_M = oldM;
+        L.wave_off = oldOff;
       }
     };
-    // 1024 .. 8192 (16384: one-wave form only), then halving below 1024 for as long as
-    // the smallest one wins (the wide coarse stencils of L1 favour short blocks)
-    for (int R : {1024, 2048, 4096, 8192, 16384, 512, 256}) {
-      if (!try_r || skip_r || R == L.sweep_R || R >= L.sweep_rows) continue;
-      if (R < 1024 && L.sweep_R != 2 * R) continue;
+    if (try_r && !skip_r) {
+      char buf[128];
+      std::snprintf(buf, sizeof buf, "level %zu: %d-row blocks (%s): %.3f ms", d, L.sweep_R,
+                    L.fgs.wave.ok ? "one-wave" : "four-wave", best);
+      progress(h, buf);
+    }
+    // block sizes 256 .. 16384 (above 8192: one-wave form only): 1024 and 4096 first,
+    // then doubling and halving from the better of those for as long as each step
+    // gains (the measured times fall and then rise with the block size, with noise that
+    // a walk from a single start can stop on)
+    std::set<int> tried{L.sweep_R};
+    for (int R : {1024, 4096}) {
+      if (!try_r || skip_r || tried.count(R) || R >= L.sweep_rows) continue;
       if (R > sweep_max_rows_per_block() && !L.fgs.wave.ok) continue;
-      try_build(R, L.wave_M);
+      tried.insert(R);
+      try_build(R, L.wave_M, L.wave_off);
+    }
+    for (int dir = 0; dir < 2 && try_r && !skip_r; ++dir) {
+      for (;;) {
+        const int R = dir == 0 ? L.sweep_R * 2 : L.sweep_R / 2;
+        if (R < 256 || R > 16384 || R >= L.sweep_rows || tried.count(R)) break;
+        if (R > sweep_max_rows_per_block() && !L.fgs.wave.ok) break;
+        tried.insert(R);
+        const int before = L.sweep_R;
+        try_build(R, L.wave_M, L.wave_off);
+        if (L.sweep_R == before) break;
+      }
     }
     // segments per block of the one-wave form at the chosen block size
     if (try_r && !skip_r && L.fgs.wave.ok && L.wave_stride > 0) {
       const int cur = L.fgs.wave.M;
       for (int M : {1, 2, 4})
-        if (M != cur && L.sweep_R / M >= 256 && (M == 1 || L.wave_stride >= L.sweep_R / M)) try_build(L.sweep_R, M);
-      progress(h, "level " + std::to_string(d) + ": one-wave sweeps, " + std::to_string(L.sweep_R) +
-                      "-row blocks in " + std::to_string(L.fgs.wave.M) + " segments");
+        if (M != cur && L.sweep_R / M >= 256 && (M == 1 || L.wave_stride >= L.sweep_R / M))
+          try_build(L.sweep_R, M, false);
+      // the four-wave kernel at that block size (wide coarse rows can favour it)
+      if (L.sweep_R <= sweep_max_rows_per_block()) try_build(L.sweep_R, L.wave_M, true);
+      progress(h, "level " + std::to_string(d) + ": " + (L.wave_off ? "four-wave" : "one-wave") + " sweeps, " +
+                      std::to_string(L.sweep_R) + "-row blocks" +
+                      (L.wave_off ? "" : " in " + std::to_string(L.fgs.wave.M) + " segments"));
     }
     // block-dense form of the Gauss-Seidel factor, blocks of 2048 / 4096 / 8192 rows
     if (h->opt.dense_smoother == 3 && d + 1 < h->lev.size()) {
@@ -1307,25 +1559,26 @@ static void tune_sweeps(cpc_solver* h) {
 // the level vector holds, in this order, the systems that are smoothed at d (still
 // coarsened further) and then the systems whose coarsest level is d; matrices are
 // block diagonal, so the leading smoothed rows couple only among themselves.
-// Depth 0 keeps the callers' system order (every system of a batch has >= 2 levels).
+// Depth 0 keeps the callers' system order.
 static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_options& o, std::string* msg) {
   const int ns = (int)sys.size();
   int D = 0;
   for (auto& S : sys) D = std::max(D, (int)S.A.size());
-  if (ns > 1)
-    for (int s = 0; s < ns; ++s)
-      if (sys[s].A.size() < 2) {
-        if (msg) *msg = "system " + std::to_string(s) + " of the batch has one level (n <= max_coarse)";
-        return CPC_E_ARG;
-      }
+  // Depth 0 keeps the callers' order and smooths every system there: a system that is
+  // its own coarsest level (one level, n <= max_coarse) gets empty rows in P, so no
+  // coarse correction reaches it, and the exact solve A_0^{-1} f of the systems that
+  // bottom out at depth 0 overwrites its rows at the end of the cycle (its V-cycle is
+  // A_0^{-1}, as for a one-level hierarchy alone).
+  const bool mixed0 = D > 1 && std::any_of(sys.begin(), sys.end(), [](const SysHier& S) { return S.A.size() < 2; });
+  auto smoothed_at = [&](int d, int s) { return d + 1 < (int)sys[s].A.size() || (d == 0 && mixed0); };
   std::vector<std::vector<int>> order(D), off(D, std::vector<int>(ns, -1));
   std::vector<int> ntot(D, 0), nS(D, 0);
   for (int d = 0; d < D; ++d) {
     for (int s = 0; s < ns; ++s)
-      if (d + 1 < (int)sys[s].A.size()) order[d].push_back(s);
+      if (smoothed_at(d, s)) order[d].push_back(s);
     const int nsm = (int)order[d].size();
     for (int s = 0; s < ns; ++s)
-      if (d + 1 == (int)sys[s].A.size()) order[d].push_back(s);
+      if (d + 1 == (int)sys[s].A.size() && !smoothed_at(d, s)) order[d].push_back(s);
     int o_ = 0;
     for (int k = 0; k < (int)order[d].size(); ++k) {
       const int s = order[d][k];
@@ -1340,17 +1593,14 @@ static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_o
   for (int s = 0; s < ns; ++s) h->lu_host.insert(h->lu_host.end(), sys[s].lu.begin(), sys[s].lu.end());
   for (int d = 0; d < D; ++d) {
     Level& L = h->lev[d];
+    progress(h, "level " + std::to_string(d) + ": " + std::to_string(ntot[d]) + " rows, " +
+                    std::to_string(order[d].size()) + " systems");
     // block-diagonal matrix of depth d
     HostCsr& A = L.A_host;
-    A.n = A.ncols = ntot[d];
-    A.rp.assign(1, 0);
-    for (int s : order[d]) {
-      const HostCsr& a = sys[s].A[d];
-      const int o_ = off[d][s];
-      const int base = A.rp.back();
-      for (int i = 0; i < a.n; ++i) A.rp.push_back(base + a.rp[i + 1]);
-      for (int c : a.ci) A.ci.push_back(c + o_);
-      A.v.insert(A.v.end(), a.v.begin(), a.v.end());
+    {
+      std::vector<PlacedBlock> blk;
+      for (int s : order[d]) blk.push_back({&sys[s].A[d], off[d][s], off[d][s]});
+      place_blocks(blk, ntot[d], ntot[d], A);
     }
     L.nS = nS[d];
     upload_csr(h, A, L.A, true);
@@ -1358,20 +1608,40 @@ static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_o
     // prolongation from depth d+1 (rows: smoothed systems at d; columns: depth d+1 layout)
     if (d + 1 < D && L.nS > 0) {
       HostCsr& P = L.P_host;
-      P.n = L.nS;
-      P.ncols = ntot[d + 1];
-      P.rp.assign(1, 0);
       L.cf.clear();
+      std::vector<PlacedBlock> pb, rb;
+      std::vector<HostCsr> empty, tr;  // empty rows of one-level systems; per-system P^T
+      empty.reserve(order[d].size());
+      std::vector<int> with_p;
       for (int s : order[d]) {
-        if (d + 1 >= (int)sys[s].A.size()) continue;
-        const HostCsr& p = sys[s].P[d];
-        const int base = P.rp.back();
-        for (int i = 0; i < p.n; ++i) P.rp.push_back(base + p.rp[i + 1]);
-        for (int c : p.ci) P.ci.push_back(c + off[d + 1][s]);
-        P.v.insert(P.v.end(), p.v.begin(), p.v.end());
+        if (!smoothed_at(d, s)) continue;
+        if (d + 1 >= (int)sys[s].A.size()) {  // one-level system at depth 0: empty rows
+          HostCsr e;
+          e.n = sys[s].A[d].n;
+          e.rp.assign(e.n + 1, 0);
+          empty.push_back(std::move(e));
+          L.cf.insert(L.cf.end(), (size_t)sys[s].A[d].n, 0);
+          continue;
+        }
+        with_p.push_back(s);
         L.cf.insert(L.cf.end(), sys[s].cf[d].begin(), sys[s].cf[d].end());
       }
-      HostCsr R = transpose(P);
+      tr.resize(with_p.size());
+      parallel_for((int)with_p.size(), setup_threads(), [&](int k) { tr[k] = transpose(sys[with_p[k]].P[d]); });
+      size_t e = 0;
+      for (int s : order[d]) {
+        if (!smoothed_at(d, s)) continue;
+        if (d + 1 >= (int)sys[s].A.size()) {
+          pb.push_back({&empty[e++], off[d][s], 0});
+          continue;
+        }
+        const size_t k = std::find(with_p.begin(), with_p.end(), s) - with_p.begin();
+        pb.push_back({&sys[s].P[d], off[d][s], off[d + 1][s]});
+        rb.push_back({&tr[k], off[d + 1][s], off[d][s]});
+      }
+      place_blocks(pb, L.nS, ntot[d + 1], P);
+      HostCsr R;
+      place_blocks(rb, ntot[d + 1], L.nS, R);
       upload_csr(h, P, L.P, false);
       upload_csr(h, R, L.R, false);
     }
@@ -1390,18 +1660,23 @@ static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_o
     }
     // sweep schedules and packed rows: the smoothed rows (all rows at depth 0, for ILU(0))
     const int rows = (d == 0) ? ntot[0] : L.nS;
+    L.parts.assign(1, 0);
+    for (int s : order[d])
+      if (off[d][s] + sys[s].A[d].n <= rows) L.parts.push_back(off[d][s] + sys[s].A[d].n);
     if (rows > 0) {
       HostCsr sub = (rows == ntot[d]) ? A : leading_rows(A, rows);
       const int Rb = o.sweep_block_rows > 0 ? std::min(o.sweep_block_rows, sweep_max_rows_per_block())
                                             : choose_block_rows(rows);
       L.sweep_rows = rows;
+      progress(h, "level " + std::to_string(d) + ": sweep forms");
       build_level_sweeps(h, L, sub, Rb, d == 0);
       upload_csr(h, strict_lower(sub), L.Ls, false);
       L.t = valloc(h, rows);
       if (L.nS > 0 && d + 1 < D) {
+        progress(h, "level " + std::to_string(d) + ": dense forms");
         std::vector<int> dn, dv;
         for (int s : order[d])
-          if (d + 1 < (int)sys[s].A.size()) {
+          if (smoothed_at(d, s)) {
             dn.push_back(sys[s].A[d].n);
             dv.push_back(off[d][s]);
           }
@@ -2324,16 +2599,22 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
   h->f32 = (o.precision == CPC_FP32_PRECOND);
   try {
     std::vector<SysHier> sys(nsys);
-    for (int s = 0; s < nsys; ++s) {
+    std::vector<int> sst(nsys, CPC_OK);
+    std::vector<std::string> smsg(nsys);
+    const int nthreads = setup_threads();
+    progress(h.get(), "ILU(0) of " + std::to_string(nsys) + " systems on " + std::to_string(nthreads) +
+                          " host threads");
+    parallel_for(nsys, nthreads, [&](int s) {
       HostCsr A0;
       A0.n = A0.ncols = n[s];
       A0.rp.assign(row_ptr[s], row_ptr[s] + n[s] + 1);
       A0.ci.assign(col_idx[s], col_idx[s] + row_ptr[s][n[s]]);
       A0.v.assign(val[s], val[s] + row_ptr[s][n[s]]);
       sys[s].A.push_back(std::move(A0));
-      if (s % 8 == 0) progress(h.get(), "ILU(0) of system " + std::to_string(s));
-      int st = ilu0_factor(sys[s].A[0], sys[s].lu, &msg);
-      if (st != CPC_OK) return set_err((cpc_status)st, "system " + std::to_string(s) + ": " + msg);
+      sst[s] = ilu0_factor(sys[s].A[0], sys[s].lu, &smsg[s]);
+    });
+    for (int s = 0; s < nsys; ++s) {
+      if (sst[s] != CPC_OK) return set_err((cpc_status)sst[s], "system " + std::to_string(s) + ": " + smsg[s]);
       h->sys_n.push_back(n[s]);
       h->sys_off.push_back(s == 0 ? 0 : h->sys_off[s - 1] + n[s - 1]);
     }
@@ -2344,12 +2625,33 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
       HIPCHK(hipStreamCreate(&h->stream));
       h->own_stream = true;
     }
-    for (int s = 0; s < nsys; ++s) {
-      progress(h.get(), "system " + std::to_string(s) + " of " + std::to_string(nsys) + ": hierarchy (" +
-                            std::to_string(sys[s].A[0].n) + " rows)");
-      int st = build_sys_hier(h.get(), sys[s], o, &msg);
-      if (st != CPC_OK) return set_err((cpc_status)st, "system " + std::to_string(s) + ": " + msg);
-    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    // each system's hierarchy on a host thread: coarsening and interpolation on the host,
+    // Galerkin products on a stream of the thread's own
+    progress(h.get(), "hierarchies of " + std::to_string(nsys) + " systems on " + std::to_string(nthreads) +
+                          " host threads");
+    std::atomic<int> built{0};
+    std::mutex plock;
+    const int dev = h->device;
+    parallel_for(nsys, nthreads, [&](int s) {
+      hipStream_t ts = nullptr;
+      try {
+        HIPCHK(hipSetDevice(dev));
+        HIPCHK(hipStreamCreate(&ts));
+        sst[s] = build_sys_hier(h.get(), sys[s], o, &smsg[s], ts);
+      } catch (const HipError& e) {
+        sst[s] = CPC_E_DEVICE;
+        smsg[s] = e.where + ": " + hipGetErrorString(e.e);
+      }
+      if (ts) (void)hipStreamDestroy(ts);
+      const int k = ++built;
+      if (k % 8 == 0 || k == nsys) {
+        std::lock_guard<std::mutex> lock(plock);
+        progress(h.get(), std::to_string(k) + " of " + std::to_string(nsys) + " hierarchies built");
+      }
+    });
+    for (int s = 0; s < nsys; ++s)
+      if (sst[s] != CPC_OK) return set_err((cpc_status)sst[s], "system " + std::to_string(s) + ": " + smsg[s]);
     progress(h.get(), "assembling the batch levels");
     int st = assemble_levels(h.get(), sys, o, &msg);
     if (st != CPC_OK) return set_err((cpc_status)st, msg);

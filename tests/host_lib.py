@@ -29,7 +29,7 @@ def lib():
         L.cpch_rs_interp.restype = ctypes.c_long
         L.cpch_sweep.argtypes = [I, P, P, P, I, I, I, P, P, P, P, P, P, P, P, P, P]
         L.cpch_dense_inverse.argtypes = [I, P, P, P, P]
-        L.cpch_wave_emulate.argtypes = [I, P, P, P, I, I, I, I, I, P, P, P]
+        L.cpch_wave_emulate.argtypes = [I, P, P, P, I, I, I, I, I, P, P, P, P, I]
         _lib = L
     return _lib
 
@@ -169,13 +169,16 @@ def check_sweep_schedule(n, rp, ci, s, forward, cap=0):
     return s["nwait"]
 
 
-def wave_emulate(n, rp, ci, v, forward, W, f, M=1, unit=False, ring=8):
+def wave_emulate(n, rp, ci, v, forward, W, f, M=1, unit=False, ring=8, parts=None):
     """Sequential emulation of the one-wave sweep kernel on its pack (see
-    cpch_wave_emulate): returns (status, x, (tb, k, nblk, nsteps, R, M, stride))."""
+    cpch_wave_emulate): returns (status, x, (tb, k, nblk, nsteps, R, M, stride)).
+    parts: row boundaries of the diagonal blocks scheduled on their own (a batch)."""
     rp, ci, v = _csr(rp, ci, v)
     f = np.ascontiguousarray(f, np.float64)
     x = np.zeros(n)
     shape = np.zeros(7, np.int32)
+    pa = None if parts is None else np.ascontiguousarray(parts, np.int32)
     st = lib().cpch_wave_emulate(n, _p(rp), _p(ci), _p(v), int(forward), int(W), int(M), int(unit), int(ring),
-                                 _p(f), _p(x), _p(shape))
+                                 _p(f), _p(x), _p(shape), None if pa is None else _p(pa),
+                                 0 if pa is None else len(pa) - 1)
     return st, x, tuple(int(t) for t in shape)

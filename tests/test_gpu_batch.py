@@ -48,13 +48,33 @@ def test_batch_hierarchy_levels_match_single_solves():
         assert info["n"][0] == sum(p.n for p in probs)
 
 
-def test_batch_rejects_one_level_system():
+def test_batch_with_one_level_systems():
+    """Systems of at most max_coarse rows (their own coarsest level) beside multi-level
+    ones, in any position: per-system iteration counts and x as the oracle's solves of
+    each system alone (a one-level system converges in one iteration, B_co = A^{-1})."""
     import paper_1205_6113_amd as cpc
-    from paper_1205_6113_amd import _lib
-    probs = gen.config4(sizes=[4, 10])  # 64 unknowns <= max_coarse
-    with pytest.raises(cpc.CpcError) as e:
-        cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs])
-    assert e.value.status == _lib.CPC_E_ARG
+    probs = gen.config4(sizes=[4, 10, 3, 12, 6])  # 64, 1000, 27, 1728, 216 unknowns
+    refs = []
+    for p in probs:
+        h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
+        refs.append((h.nlev, h.pcg(oracle.PREC_COMBINED, p.b, p.tol, 1000)))
+    assert sorted(nl for nl, _ in refs)[0] == 1 and max(nl for nl, _ in refs) > 1
+    b = torch.as_tensor(np.concatenate([p.b for p in probs]), device="cuda")
+    for prec in ("combined", "amg"):
+        with cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs], prec=prec) as bs:
+            x, it, rel, st = bs.solve(b, tol=1e-8)
+            assert st == 0
+            xs = x.cpu().numpy()
+            for s, (p, (nl, r)) in enumerate(zip(probs, refs)):
+                xo = xs[bs.offsets[s]:bs.offsets[s] + p.n]
+                if prec == "combined":
+                    assert it[s] == r["iters"], (s, it[s], r["iters"])
+                    err = np.linalg.norm(xo - r["x"]) / np.linalg.norm(r["x"])
+                    assert err <= 1e-10, (s, err)
+                if nl == 1:
+                    assert it[s] == 1, (prec, s, it[s])
+                    xd = np.linalg.solve(gen.csr_to_dense(p.n, p.row_ptr, p.col, p.val), p.b)
+                    assert np.linalg.norm(xo - xd) <= 1e-12 * np.linalg.norm(xd)
 
 
 _MID_REFS = {}

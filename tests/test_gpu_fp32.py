@@ -2,8 +2,17 @@
 
 The preconditioner's matrices and vectors are stored in FP32 with FP64 row sums;
 PCG vectors, the outer residuals of Algorithm 2.1, reductions and the coarsest
-solve stay FP64. Bar: true relative residual <= 1e-8; the error against the FP64
-oracle's solution is reported per case."""
+solve stay FP64.
+
+Bars. Operators (S, B and B_co of Algorithm 2.1 applied to one vector): relative
+error <= 1e-6 against the FP64 oracle, i.e. about 17 units of FP32 rounding
+(u = 6.0e-8): every stored entry and every vector handed between kernels is rounded
+once to FP32 and the row sums are FP64, so the error is a small multiple of u (the
+measured errors are 2.7e-9 .. 1.1e-7). Solve: the true relative residual meets the
+requested tolerance, PCG takes at most one more iteration than in FP64, and the
+solution differs from the FP64 oracle's by <= 1e-10 (the preconditioner's FP32
+perturbation changes the search directions by O(u) and the iterate by O(u) times the
+remaining error; measured <= 1.3e-14)."""
 import numpy as np
 import pytest
 import torch
@@ -36,7 +45,8 @@ def test_fp32_preconditioner_reaches_fp64_accuracy(case):
             z = s32.apply(op, torch.as_tensor(r, device="cuda")).cpu().numpy()
             zr = h.apply(which, r)
             err = np.linalg.norm(z - zr) / np.linalg.norm(zr)
-            assert err <= 1e-4, (case, op, err)
+            print(f"[fp32] {case} {op}: operator error {err:.3e}", flush=True)
+            assert err <= 1e-6, (case, op, err)
         x32, it32, rel32, st32 = s32.solve(b, tol=p.tol)
         x64, it64, rel64, st64 = s64.solve(b, tol=p.tol)
     assert st32 == 0 and st64 == 0
@@ -46,5 +56,5 @@ def test_fp32_preconditioner_reaches_fp64_accuracy(case):
     print(f"[fp32] {case}: iters fp32={it32} fp64={it64} oracle={ro['iters']} true relres={tr:.3e} "
           f"x err vs fp64 oracle={err:.3e}")
     assert tr <= p.tol * 1.05
-    assert it32 <= it64 + 3
-    assert err <= 1e-5
+    assert it32 <= it64 + 1
+    assert err <= 1e-10

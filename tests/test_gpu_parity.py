@@ -53,6 +53,9 @@ def small_cases():
         "c2s-workgroup": (gen.scaled_config(2, 0.15), 0, "never", "workgroup"),
         "c2s-tiny-blocks-workgroup": (gen.scaled_config(2, 0.15), 7, "never", "workgroup"),
         "c1-ragged-workgroup": (gen.config1(37, 23), 37, "never", "workgroup"),
+        # rows of up to 120 dependency entries (64 lanes per row in the one-wave kernel)
+        "wide-rows": (gen.wide_band(), 2048, "never", "auto"),
+        "wide-rows-workgroup": (gen.wide_band(), 2048, "never", "workgroup"),
     }
 
 

@@ -110,3 +110,53 @@ def test_ring_depths_and_single_block():
     for ring in (1, 2, 8, 16):
         _check(p.n, p.row_ptr, p.col, p.val, 5, ring=ring)
     _check(p.n, p.row_ptr, p.col, p.val, p.n)
+
+
+def _block_diag(problems):
+    rps, cis, vs, parts, off, nnz = [np.zeros(1, np.int64)], [], [], [0], 0, 0
+    for p in problems:
+        rps.append(np.asarray(p.row_ptr[1:], np.int64) + nnz)
+        cis.append(np.asarray(p.col, np.int64) + off)
+        vs.append(np.asarray(p.val))
+        off += p.n
+        nnz += int(p.row_ptr[-1])
+        parts.append(off)
+    return off, np.concatenate(rps), np.concatenate(cis), np.concatenate(vs), parts
+
+
+@pytest.mark.parametrize("W,M", [(96, 4), (256, 1), (64, 2)])
+def test_batch_parts_own_schedules(W, M):
+    """A batch's block-diagonal level: each system scheduled with its own coupling
+    distance (3-D systems of different plane sizes, a 2-D one, a tiny one), the systems'
+    blocks interleaved in one ticket order; bounds, hand-offs and the solution checked."""
+    probs = [gen.scaled_config(2, 0.15), gen.config1(9, 7), gen.scaled_config(3, 0.12), gen.config1(3, 2),
+             gen.scaled_config(5, 0.15)]
+    n, rp, ci, v, parts = _block_diag(probs)
+    f = np.random.default_rng(W + M).standard_normal(n)
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    a = sp.csr_matrix((v, ci, rp), shape=(n, n))
+    for forward in (True, False):
+        for unit in ((False, True) if forward else (False,)):
+            st, x, shape = host_lib.wave_emulate(n, rp, ci, v, forward, W, f, M=M, unit=unit, parts=parts)
+            assert st == 0, (W, M, forward, unit, st)
+            t = sp.tril(a) if forward else sp.triu(a)
+            if unit:
+                t = t - sp.diags(t.diagonal()) + sp.eye(n)
+            xr = spl.spsolve_triangular(t.tocsr(), f, lower=forward)
+            assert np.linalg.norm(x - xr) / np.linalg.norm(xr) <= 1e-12
+            tb, k, nblk, nsteps, R, m, stride = shape
+            assert R <= W * M
+            assert nblk >= len(probs)  # blocks never span two systems
+
+
+def test_long_rows_have_no_one_wave_pack():
+    """Rows with more than 64 dependency entries get no one-wave pack (status -5): the
+    setup gives such levels to the four-wave kernel."""
+    p = gen.wide_band(3000, 160)
+    st, _, _ = host_lib.wave_emulate(p.n, p.row_ptr, p.col, p.val, True, 256, np.ones(p.n))
+    assert st == -5
+    p = gen.wide_band(3000, 40)
+    rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+    v = np.where(p.col == rows, 1.0, p.val / 160.0)  # bounded unit-lower solve
+    assert _check(p.n, p.row_ptr, p.col, v, 256, dense=False)
