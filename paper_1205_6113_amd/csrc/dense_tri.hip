@@ -25,6 +25,9 @@
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
+#include <map>
+#include <mutex>
+
 #include <algorithm>
 #include <vector>
 
@@ -392,13 +395,30 @@ void launch_transpose(hipStream_t s, int n, const void* X, void* Y, bool fp32) {
   else transpose_kernel<double><<<grid, kNT, 0, s>>>(n, (const double*)X, (double*)Y);
 }
 
-bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int* ci, const double* v, double* M,
-                       double* work, std::string* msg) {
+// One rocBLAS handle per device, made on first use and kept until the process ends (a
+// block-dense level builds thousands of small inverses; a handle per call costs more
+// than their GEMMs).
+static rocblas_handle blas_handle(std::string* msg) {
+  static std::mutex mu;
+  static std::map<int, rocblas_handle> handles;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = handles.find(dev);
+  if (it != handles.end()) return it->second;
   rocblas_handle hb = nullptr;
   if (rocblas_create_handle(&hb) != rocblas_status_success) {
     if (msg) *msg = "rocblas_create_handle failed";
-    return false;
+    return nullptr;
   }
+  handles[dev] = hb;
+  return hb;
+}
+
+bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int* ci, const double* v, double* M,
+                       double* work, std::string* msg) {
+  rocblas_handle hb = blas_handle(msg);
+  if (!hb) return false;
   bool ok = rocblas_set_stream(hb, s) == rocblas_status_success;
   const long ld = dense_ld(n);
   if (ok && hipMemsetAsync(M, 0, sizeof(double) * (size_t)n * ld, s) != hipSuccess) ok = false;
@@ -428,7 +448,6 @@ bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int*
     }
   }
   if (!ok && msg && msg->empty()) *msg = "dense triangular inverse failed";
-  rocblas_destroy_handle(hb);
   return ok;
 }
 

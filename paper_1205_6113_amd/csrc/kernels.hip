@@ -74,11 +74,13 @@ __device__ bool arrive(double part, double* partials, unsigned* counter, double*
 // SpMV family
 
 
+// rid (may be null): row k of the matrix is entry rid[k] of f and y (the rows of one
+// step of the block substitution, which lie in several systems of a batch).
 template <int TPR, int U, typename VT, typename XT, typename FT, typename YT>
 __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const VT* __restrict__ v, const XT* __restrict__ x,
                                                    const FT* __restrict__ f, YT* __restrict__ y, int mode,
-                                                   const int* __restrict__ done) {
+                                                   const int* __restrict__ rid, const int* __restrict__ done) {
   constexpr int RPB = kNT / TPR;
   const int lane = threadIdx.x % TPR;
   const int stride = gridDim.x * RPB;
@@ -87,28 +89,31 @@ __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict_
   // are read before they are needed: the first row's together with the convergence flag,
   // the next row's while this one is summed, so the flag and those reads add no step to
   // the chain of dependent loads (rows bounds, then entries, then x).
-  int b = 0, e = 0;
+  int b = 0, e = 0, o = 0;
   double g = 0.0;
   if (i < n) {
     b = rp[i];
     e = rp[i + 1];
-    g = mode == 1 ? ld(f, i) : (mode == 2 ? ld(y, i) : 0.0);
+    o = rid ? rid[i] : i;
+    g = mode == 1 ? ld(f, o) : (mode == 2 ? ld(y, o) : 0.0);
   }
   if (done && *done) return;
   for (; i < n; i += stride) {
     const double s0 = row_dot<TPR, U>(b + lane, e, ci, v, x);
     const int in = i + stride;
     const double gi = g;
+    const int oi = o;
     if (in < n) {
       b = rp[in];
       e = rp[in + 1];
-      g = mode == 1 ? ld(f, in) : (mode == 2 ? ld(y, in) : 0.0);
+      o = rid ? rid[in] : in;
+      g = mode == 1 ? ld(f, o) : (mode == 2 ? ld(y, o) : 0.0);
     }
     const double s = gsum<TPR>(s0);
     if (lane == 0) {
-      if (mode == 0) st(y, i, s);
-      else if (mode == 1) st(y, i, gi - s);
-      else st(y, i, gi + s);
+      if (mode == 0) st(y, oi, s);
+      else if (mode == 1) st(y, oi, gi - s);
+      else st(y, oi, gi + s);
     }
   }
 }
@@ -335,7 +340,7 @@ static void spmv_typed_u(hipStream_t s, const MatDev& A, int mode, const void* x
   const int grid = grid_for(A.n, rpb);
 #define CPC_SPMV_CALL(T)                                                                                  \
   spmv_kernel<T, U, VT, XT, FT, YT><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const VT*)A.v, (const XT*)x,  \
-                                                         (const FT*)f, (YT*)y, mode, done)
+                                                         (const FT*)f, (YT*)y, mode, A.rid, done)
   CPC_TPR_DISPATCH(tpr, CPC_SPMV_CALL)
 #undef CPC_SPMV_CALL
 }

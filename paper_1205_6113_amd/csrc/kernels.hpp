@@ -73,6 +73,8 @@ struct MatDev {  // CSR on the device; values of type T
   const void* v;
   bool fp32;
   int steps;  // entries per lane a small launch takes at once in a row product: 1, 2 or 4
+  // SpMV only: row k of the matrix is level row rid[k] of f and y (null: row k itself)
+  const int* rid = nullptr;
 };
 
 // ---- launchers (all asynchronous on `s`) -----------------------------------

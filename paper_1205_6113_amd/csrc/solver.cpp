@@ -112,6 +112,29 @@ struct DevCsr {
   }
 };
 
+// Block substitution with explicit inverses of the diagonal blocks of D+L. Blocks never
+// span two systems of a batch: step k of the forward solve takes the k-th block of every
+// system at once, step t of the backward solve the t-th block from each system's end
+// (one system: one block per step).
+struct BlockDense {
+  int B = 0;
+  std::vector<int> start, rows;    // per block, in forward-step order: first row, rows
+  std::vector<long> moff;          // per block: element offset of its inverse
+  std::vector<int> fstep;          // forward step k: blocks [fstep[k], fstep[k+1])
+  std::vector<int> bblk, bstep;    // backward step t: blocks bblk[bstep[t] .. bstep[t+1])
+  std::vector<int> fitem, bitem;   // offsets of each step's row items in the two item lists
+  std::vector<int> frow, brow;     // offsets of each step's rows in Loff / Uoff
+  const int4* items_f = nullptr;   // row items of the forward steps (device)
+  const int4* items_b = nullptr;   // row items of the backward steps (device)
+  DenseTriDev dt{};                // the blocks as systems: n, moff, voff per block; M, MT
+  DevCsr Loff, Uoff;               // entries left / right of the row's block, rows in step order
+  const int* Lrid = nullptr;       // level row of each row of Loff / Uoff (device)
+  const int* Urid = nullptr;
+  double entries = 0.0;            // stored inverse entries (byte model)
+  std::vector<void*> owned;
+  int nblk() const { return (int)start.size(); }
+};
+
 struct DevSweepSched {
   SweepDev d{};
   int global_depth = 0;
@@ -151,14 +174,7 @@ struct Level {
   // block-dense form of the smoother: block forward/backward substitution with explicit
   // inverses of the diagonal blocks of D+L (levels where it beats the sweeps)
   bool bdense = false;
-  int bd_B = 0;
-  std::vector<int> bd_start;     // K + 1 block starts
-  DenseTriDev bd_dt{};           // the diagonal blocks as systems
-  std::vector<int> bd_item_off;  // K + 1 offsets of each block's row items
-  std::vector<long> bd_moff;     // K element offsets of the blocks' inverses
-  DevCsr bd_Loff, bd_Uoff;       // lower / upper entries outside the row's block
-  std::vector<void*> bd_owned;
-  double bd_entries = 0.0;       // stored inverse entries (byte model)
+  BlockDense bd;
 };
 
 }  // namespace cpc
@@ -224,7 +240,7 @@ struct cpc_solver {
       if (L.dense_M) (void)hipFree(L.dense_M);
       if (L.dense_MT) (void)hipFree(L.dense_MT);
       for (void* ptr : L.sweep_owned) (void)hipFree(ptr);
-      for (void* ptr : L.bd_owned) (void)hipFree(ptr);
+      for (void* ptr : L.bd.owned) (void)hipFree(ptr);
       for (void* ptr : L.dense_owned) (void)hipFree(ptr);
     }
     for (void* ptr : owned) (void)hipFree(ptr);
@@ -1134,50 +1150,89 @@ static void build_iluk_sweeps(cpc_solver* h, int R) {
 static const DevSweepSched& ilu_lower_sched(const cpc_solver* h) { return h->iluk ? h->ilu_lower : h->lev[0].lower; }
 static const DevSweepSched& ilu_upper_sched(const cpc_solver* h) { return h->iluk ? h->ilu_upper : h->lev[0].upper; }
 
-// Block-dense form of a level's Gauss-Seidel factor T = D + L with blocks of B rows:
-// the forward solve is, block by block, g_b = f_b - (T entries left of the block) x,
-// x_b = T_bb^{-1} g_b; the backward solve with T^T = D + U runs the blocks in reverse
-// with the entries right of the block and x_b = T_bb^{-T} g_b. Returns false (nothing
-// kept) when it does not fit or a step fails.
+// Block-dense form of a level's Gauss-Seidel factor T = D + L with blocks of B rows
+// (each system of a batch cut on its own): the forward solve is, block by block,
+// g_b = f_b - (T entries left of the block) x, x_b = T_bb^{-1} g_b; the backward solve
+// with T^T = D + U runs each system's blocks in reverse with the entries right of the
+// block and x_b = T_bb^{-T} g_b. Blocks of different systems are independent, so each
+// step takes one block of every system. Returns false (nothing kept) when the inverses
+// do not fit or a step fails.
 static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B) {
   if (B <= 0 || B > kDenseMaxRows) return false;
   const int n = sub.n;
-  std::vector<int> st;
-  for (int r = 0; r < n; r += B) st.push_back(r);
-  st.push_back(n);
-  const int K = (int)st.size() - 1;
+  const std::vector<int> parts =
+      (!L.parts.empty() && L.parts.front() == 0 && L.parts.back() == n) ? L.parts : std::vector<int>{0, n};
+  const int np = (int)parts.size() - 1;
+  BlockDense bd;
+  bd.B = B;
+  std::vector<int> kc(np);
+  int kmax = 0;
+  for (int p = 0; p < np; ++p) {
+    kc[p] = (parts[p + 1] - parts[p] + B - 1) / B;
+    kmax = std::max(kmax, kc[p]);
+  }
+  std::vector<std::vector<int>> id(np);  // block index of the k-th block of part p
+  bd.fstep.push_back(0);
+  for (int k = 0; k < kmax; ++k) {
+    for (int p = 0; p < np; ++p) {
+      if (k >= kc[p]) continue;
+      id[p].push_back(bd.nblk());
+      const int r0 = parts[p] + k * B;
+      bd.start.push_back(r0);
+      bd.rows.push_back(std::min(B, parts[p + 1] - r0));
+    }
+    bd.fstep.push_back(bd.nblk());
+  }
+  bd.bstep.push_back(0);
+  for (int t = 0; t < kmax; ++t) {
+    for (int p = 0; p < np; ++p)
+      if (t < kc[p]) bd.bblk.push_back(id[p][kc[p] - 1 - t]);
+    bd.bstep.push_back((int)bd.bblk.size());
+  }
+  const int K = bd.nblk();
   double bytes = 0.0;
-  for (int b = 0; b < K; ++b) bytes += 16.0 * (st[b + 1] - st[b]) * (double)(st[b + 1] - st[b]);
+  for (int b = 0; b < K; ++b) bytes += 16.0 * bd.rows[b] * (double)bd.rows[b];
   if (bytes > 32e9) return false;
+  // entries outside each row's block, rows in step order (forward: left of the block;
+  // backward: right of it)
   HostCsr lo, up;
-  lo.n = up.n = n;
+  std::vector<int> lrid, urid;
   lo.ncols = up.ncols = sub.ncols;
   lo.rp.assign(1, 0);
   up.rp.assign(1, 0);
-  for (int i = 0; i < n; ++i) {
-    const int b0 = (i / B) * B, b1 = std::min(b0 + B, n);
-    for (int q = sub.rp[i]; q < sub.rp[i + 1]; ++q) {
-      const int j = sub.ci[q];
-      if (j < b0) {
-        lo.ci.push_back(j);
-        lo.v.push_back(sub.v[q]);
-      } else if (j >= b1) {
-        up.ci.push_back(j);
-        up.v.push_back(sub.v[q]);
+  auto add_rows = [&](HostCsr& m, std::vector<int>& rid, int b, bool left) {
+    const int b0 = bd.start[b], b1 = b0 + bd.rows[b];
+    for (int i = b0; i < b1; ++i) {
+      for (int q = sub.rp[i]; q < sub.rp[i + 1]; ++q) {
+        const int j = sub.ci[q];
+        if (left ? j < b0 : j >= b1) {
+          m.ci.push_back(j);
+          m.v.push_back(sub.v[q]);
+        }
       }
+      m.rp.push_back((int)m.ci.size());
+      rid.push_back(i);
     }
-    lo.rp.push_back((int)lo.ci.size());
-    up.rp.push_back((int)up.ci.size());
+  };
+  bd.frow.push_back(0);
+  for (int k = 0; k < kmax; ++k) {
+    for (int b = bd.fstep[k]; b < bd.fstep[k + 1]; ++b) add_rows(lo, lrid, b, true);
+    bd.frow.push_back((int)lrid.size());
   }
-  std::vector<void*> own;
-  std::vector<long> moff(K);
-  std::vector<int> nbs(K);
+  bd.brow.push_back(0);
+  for (int t = 0; t < kmax; ++t) {
+    for (int q = bd.bstep[t]; q < bd.bstep[t + 1]; ++q) add_rows(up, urid, bd.bblk[q], false);
+    bd.brow.push_back((int)urid.size());
+  }
+  lo.n = (int)lrid.size();
+  up.n = (int)urid.size();
+  std::vector<void*>& own = bd.owned;
   long tot = 0, wmax = 1;
+  bd.moff.resize(K);
   for (int b = 0; b < K; ++b) {
-    nbs[b] = st[b + 1] - st[b];
-    moff[b] = tot;
-    tot += (long)nbs[b] * dense_ld(nbs[b]);
-    wmax = std::max(wmax, dense_work_need(nbs[b]));
+    bd.moff[b] = tot;
+    tot += (long)bd.rows[b] * dense_ld(bd.rows[b]);
+    wmax = std::max(wmax, dense_work_need(bd.rows[b]));
   }
   auto drop = [&] {
     (void)hipStreamSynchronize(h->stream);
@@ -1195,7 +1250,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   bool ok = true;
   std::string msg;
   for (int b = 0; ok && b < K; ++b)
-    ok = dense_tri_inverse(h->stream, nbs[b], st[b], L.A.rp, L.A.ci, L.A.v, M64 + moff[b], work, &msg);
+    ok = dense_tri_inverse(h->stream, bd.rows[b], bd.start[b], L.A.rp, L.A.ci, L.A.v, M64 + bd.moff[b], work, &msg);
   ok = ok && hipStreamSynchronize(h->stream) == hipSuccess;
   (void)hipFree(work);
   if (!ok) {
@@ -1221,94 +1276,99 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   own.push_back(MT);
   if (hipMemsetAsync(MT, 0, es * tot, h->stream) != hipSuccess) return drop();  // zero padding columns
   for (int b = 0; b < K; ++b)
-    launch_transpose(h->stream, nbs[b], (const char*)M + es * moff[b], (char*)MT + es * moff[b], h->f32);
-  std::vector<int4> itn;
-  std::vector<int> ioff(1, 0);
-  double ent = 0.0;
-  for (int b = 0; b < K; ++b) {
-    dense_row_items(b, nbs[b], itn);
-    ioff.push_back((int)itn.size());
-    ent += 0.5 * (double)nbs[b] * (nbs[b] + 1);
+    launch_transpose(h->stream, bd.rows[b], (const char*)M + es * bd.moff[b], (char*)MT + es * bd.moff[b], h->f32);
+  // row items of each step, the forward steps' and the backward steps' in lists of their own
+  std::vector<int4> itf, itb;
+  bd.fitem.push_back(0);
+  for (int k = 0; k < kmax; ++k) {
+    for (int b = bd.fstep[k]; b < bd.fstep[k + 1]; ++b) dense_row_items(b, bd.rows[b], itf);
+    bd.fitem.push_back((int)itf.size());
   }
+  bd.bitem.push_back(0);
+  for (int t = 0; t < kmax; ++t) {
+    for (int q = bd.bstep[t]; q < bd.bstep[t + 1]; ++q) dense_row_items(bd.bblk[q], bd.rows[bd.bblk[q]], itb);
+    bd.bitem.push_back((int)itb.size());
+  }
+  for (int b = 0; b < K; ++b) bd.entries += 0.5 * (double)bd.rows[b] * (bd.rows[b] + 1);
   try {
-    upload_csr(h, lo, L.bd_Loff, false, &own);
-    upload_csr(h, up, L.bd_Uoff, false, &own);
-    // one block's off-block product is a small launch that ends with its longest row:
+    upload_csr(h, lo, bd.Loff, false, &own);
+    upload_csr(h, up, bd.Uoff, false, &own);
+    bd.Lrid = dupload(lrid, own, h->stream);
+    bd.Urid = dupload(urid, own, h->stream);
+    // a step's off-block product is a small launch that ends with its longest row:
     // lanes enough for that row to take a single batch of four entries per lane
     for (auto* m : {&lo, &up}) {
       int longest = 0;
       for (int i = 0; i < m->n; ++i) longest = std::max(longest, m->rp[i + 1] - m->rp[i]);
-      DevCsr& d = m == &lo ? L.bd_Loff : L.bd_Uoff;
+      DevCsr& d = m == &lo ? bd.Loff : bd.Uoff;
       d.tpr = 1;
       while (d.tpr < 64 && 4 * d.tpr < longest) d.tpr <<= 1;
       d.steps = 4;
     }
-    DenseTriDev& dt = L.bd_dt;
+    DenseTriDev& dt = bd.dt;
     dt = DenseTriDev{};
-    dt.n = dupload(nbs, own, h->stream);
-    dt.moff = dupload(moff, own, h->stream);
-    std::vector<int> voff(st.begin(), st.end() - 1);
-    dt.voff = dupload(voff, own, h->stream);
+    dt.n = dupload(bd.rows, own, h->stream);
+    dt.moff = dupload(bd.moff, own, h->stream);
+    dt.voff = dupload(bd.start, own, h->stream);
     dt.M = M;
     dt.MT = MT;
-    dt.nitem_n = (int)itn.size();
-    dt.item_n = dupload(itn, own, h->stream);
+    bd.items_f = dupload(itf, own, h->stream);
+    bd.items_b = dupload(itb, own, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError&) {
-    L.bd_dt = DenseTriDev{};
     return drop();
   }
-  L.bd_B = B;
-  L.bd_start = st;
-  L.bd_item_off = ioff;
-  L.bd_moff = moff;
-  L.bd_entries = ent;
-  L.bd_owned.swap(own);
+  L.bd = std::move(bd);
   return true;
 }
 
 static void free_blockdense(cpc_solver* h, Level& L) {
   HIPCHK(hipStreamSynchronize(h->stream));
-  for (void* p : L.bd_owned) (void)hipFree(p);
-  L.bd_owned.clear();
-  L.bd_dt = DenseTriDev{};
-  L.bd_start.clear();
-  L.bd_item_off.clear();
-  L.bd_moff.clear();
-  L.bd_B = 0;
-  L.bd_entries = 0.0;
+  for (void* p : L.bd.owned) (void)hipFree(p);
+  L.bd = BlockDense{};
   L.bdense = false;
 }
 
-// The block-dense form's launch over diagonal block b.
-static DenseTriDev bd_block(const Level& L, int b) {
-  if (b < 0 || (size_t)b + 1 >= L.bd_start.size() || L.bd_moff.size() + 1 != L.bd_start.size() ||
-      L.bd_item_off.size() != L.bd_start.size())
-    throw HipError{hipErrorInvalidValue, "block-dense form: inconsistent block tables"};
-  DenseTriDev dt = L.bd_dt;
-  dt.item_n += L.bd_item_off[b];
-  dt.nitem_n = L.bd_item_off[b + 1] - L.bd_item_off[b];
-  dt.one_n = L.bd_start[b + 1] - L.bd_start[b];
-  dt.one_voff = L.bd_start[b];
-  dt.one_moff = L.bd_moff[b];
+// The row-product launch of step t of the block-dense form (forward, or backward with
+// the transposed inverses): the blocks of the step as systems, or a single block.
+static DenseTriDev bd_step(const Level& L, bool upper, int t) {
+  const BlockDense& bd = L.bd;
+  const std::vector<int>& step = upper ? bd.bstep : bd.fstep;
+  const std::vector<int>& item = upper ? bd.bitem : bd.fitem;
+  if (t < 0 || (size_t)t + 1 >= step.size() || item.size() != step.size())
+    throw HipError{hipErrorInvalidValue, "block-dense form: inconsistent step tables"};
+  DenseTriDev dt = bd.dt;
+  dt.item_n = (upper ? bd.items_b : bd.items_f) + item[t];
+  dt.nitem_n = item[t + 1] - item[t];
+  dt.one_n = 0;
+  if (step[t + 1] - step[t] == 1) {  // one block: its rows and offsets need no table reads
+    const int b = upper ? bd.bblk[step[t]] : step[t];
+    dt.one_n = bd.rows[b];
+    dt.one_voff = bd.start[b];
+    dt.one_moff = bd.moff[b];
+  }
   return dt;
+}
+
+static int bd_steps(const Level& L, bool upper) {
+  return (int)(upper ? L.bd.bstep.size() : L.bd.fstep.size()) - 1;
 }
 
 // x = T^{-1} f (upper = false) or x = T^{-T} f (upper = true) through the block-dense
 // form; g is a scratch vector of the level.
 static void bdense_solve(cpc_solver* h, Level& L, bool upper, const void* f, void* x, void* g, const int* done) {
   const bool f32 = h->f32;
-  const size_t es = esz_of(h);
-  const int K = (int)L.bd_start.size() - 1;
-  const DevCsr& off = upper ? L.bd_Uoff : L.bd_Loff;
-  for (int t = 0; t < K; ++t) {
-    const int b = upper ? K - 1 - t : t;
-    const int r0 = L.bd_start[b], nb = L.bd_start[b + 1] - r0;
+  const BlockDense& bd = L.bd;
+  const DevCsr& off = upper ? bd.Uoff : bd.Loff;
+  const std::vector<int>& rows = upper ? bd.brow : bd.frow;
+  const int T = bd_steps(L, upper);
+  for (int t = 0; t < T; ++t) {
     MatDev m = off.mat(f32);
-    m.n = nb;
-    m.rp = off.rp + r0;
-    spmv_or_throw(h, m, 1, x, f32, (const char*)f + es * r0, f32, (char*)g + es * r0, f32, off.tpr, done);
-    const DenseTriDev dt = bd_block(L, b);
+    m.n = rows[t + 1] - rows[t];
+    m.rp = off.rp + rows[t];
+    m.rid = (upper ? bd.Urid : bd.Lrid) + rows[t];
+    spmv_or_throw(h, m, 1, x, f32, f, f32, g, f32, off.tpr, done);
+    const DenseTriDev dt = bd_step(L, upper, t);
     if (upper) launch_dense_lower_t(h->stream, dt, f32, f32, g, x, done);
     else launch_dense_lower(h->stream, dt, f32, f32, g, x, done);
   }
@@ -1353,7 +1413,7 @@ static void tune_sweeps(cpc_solver* h) {
         }
       });
     };
-    const bool try_r = L.sweep_rows <= 2000000 && !(L.dense_smooth && !ilu);
+    const bool try_r = L.sweep_rows <= 8000000 && !(L.dense_smooth && !ilu);
     const bool bd_ok = L.sweep_rows > 8192 && d + 1 < h->lev.size() && h->opt.dense_smoother == 0;
     auto gs_cost = [&] {
       return time_ms(h, 3, [&] {
@@ -1483,30 +1543,12 @@ static void tune_sweeps(cpc_solver* h) {
         h->opt.dense_smoother != 2) {
       float gbest = gs_cost();
       const bool was_dense = L.dense_smooth;
-      // block sizes from the middle out; 1024 and 8192 only where the model
-      // t(B) = a / B + c B fitted to the 2048 and 4096 timings predicts a gain
-      for (int B : {4096, 2048, 8192, 1024}) {
-        if (B >= L.sweep_rows) continue;
-        if (L.bdense && L.bd_B == B) continue;  // kept from the quick look
-        if ((B == 8192 || B == 1024) && bd_time.count(2048) && bd_time.count(4096)) {
-          const double t2 = bd_time[2048], t4 = bd_time[4096];
-          const double c = (2.0 * t4 - t2) / (2.0 * 4096.0 - 2048.0);  // from t2 = a/2048 + 2048c, t4 = a/4096 + 4096c
-          const double a = (t2 - 2048.0 * c) * 2048.0;
-          const double pred = a / B + c * B;
-          if (!(pred < 0.97 * gbest)) continue;
-        }
-        // the current best block-dense form (if any) is set aside while B is tried
+      // block substitution with B-row blocks; kept if faster than the best so far (the
+      // current block-dense form, if any, is set aside meanwhile)
+      auto try_bd = [&](int B) {
         Level keep;
         keep.bdense = L.bdense;
-        keep.bd_B = L.bd_B;
-        keep.bd_start.swap(L.bd_start);
-        keep.bd_dt = L.bd_dt;
-        keep.bd_item_off.swap(L.bd_item_off);
-        keep.bd_moff.swap(L.bd_moff);
-        keep.bd_Loff = L.bd_Loff;
-        keep.bd_Uoff = L.bd_Uoff;
-        keep.bd_owned.swap(L.bd_owned);
-        keep.bd_entries = L.bd_entries;
+        std::swap(keep.bd, L.bd);
         L.bdense = false;
         bool better = false;
         progress(h, "level " + std::to_string(d) + ": block substitution with " + std::to_string(B) + "-row blocks");
@@ -1521,23 +1563,32 @@ static void tune_sweeps(cpc_solver* h) {
         }
         if (better) {
           HIPCHK(hipStreamSynchronize(h->stream));
-          for (void* p : keep.bd_owned) (void)hipFree(p);
+          for (void* p : keep.bd.owned) (void)hipFree(p);
         } else {
           free_blockdense(h, L);
           L.bdense = keep.bdense;
-          L.bd_B = keep.bd_B;
-          L.bd_start.swap(keep.bd_start);
-          L.bd_dt = keep.bd_dt;
-          L.bd_item_off.swap(keep.bd_item_off);
-          L.bd_moff.swap(keep.bd_moff);
-          L.bd_Loff = keep.bd_Loff;
-          L.bd_Uoff = keep.bd_Uoff;
-          L.bd_owned.swap(keep.bd_owned);
-          L.bd_entries = keep.bd_entries;
+          std::swap(keep.bd, L.bd);
         }
+      };
+      // block sizes from the middle out; 1024 and 8192 only where the model
+      // t(B) = a / B + c B fitted to the 2048 and 4096 timings predicts a gain
+      for (int B : {4096, 2048, 8192, 1024}) {
+        if (B >= L.sweep_rows) continue;
+        if (L.bdense && L.bd.B == B) continue;  // kept from the quick look
+        if ((B == 8192 || B == 1024) && bd_time.count(2048) && bd_time.count(4096)) {
+          const double t2 = bd_time[2048], t4 = bd_time[4096];
+          const double c = (2.0 * t4 - t2) / (2.0 * 4096.0 - 2048.0);  // from t2 = a/2048 + 2048c, t4 = a/4096 + 4096c
+          const double a = (t2 - 2048.0 * c) * 2048.0;
+          const double pred = a / B + c * B;
+          if (!(pred < 0.97 * gbest)) continue;
+        }
+        try_bd(B);
       }
+      // in a batch (many independent systems per step) small blocks can keep winning:
+      // halve while the smallest size tried is the best
+      for (int B = 512; B >= 256 && L.bdense && L.bd.B == 2 * B && bd_time.count(2 * B); B /= 2) try_bd(B);
       progress(h, "level " + std::to_string(d) + ": " +
-                      (L.bdense ? "block-dense, " + std::to_string(L.bd_B) + "-row blocks"
+                      (L.bdense ? "block-dense, " + std::to_string(L.bd.B) + "-row blocks"
                                 : (L.dense_smooth ? std::string("explicit inverse") : "sweeps, " +
                                    std::to_string(L.sweep_R) + "-row blocks")));
       if (L.bdense && was_dense) {  // the block form replaces the whole-level inverse
@@ -1982,7 +2033,7 @@ static double level_smooth_bytes(const cpc_solver* h, size_t d) {
   const double nz = (double)L.nnzS, n = L.nS, half = 0.5 * (nz - n);
   const double eb = h->f32 ? 4.0 : 8.0;
   double one;
-  if (L.bdense) one = eb * L.bd_entries + (double)L.bd_Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
+  if (L.bdense) one = eb * L.bd.entries + (double)L.bd.Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
   else if (L.dense_smooth) one = eb * L.dense_entries + 2.0 * vb * n;
   else one = vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;
   return 2.0 * one + half * mb + 4.0 * n + 3.0 * vb * n;
@@ -1999,7 +2050,7 @@ static double vcycle_bytes(const cpc_solver* h) {
       const double p = (double)L.P.nnz;
       const double half = 0.5 * (nz - n);
       const double eb = h->f32 ? 4.0 : 8.0;  // explicit inverse entry
-      const double bdb = eb * L.bd_entries + (double)L.bd_Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
+      const double bdb = eb * L.bd.entries + (double)L.bd.Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
       if (L.bdense) b += bdb;                                     // block-dense T^{-1} f
       else if (L.dense_smooth) b += eb * L.dense_entries + 2.0 * vb * n;    // T^{-1} f
       else b += vb * n + (half + n) * mb + 4.0 * n + 2.0 * vb * n;  // marker fill + forward GS from zero
@@ -2031,7 +2082,7 @@ static double kernel_bytes(const cpc_solver* h, int kernel, int d) {
     case CPC_K_FGS:
     case CPC_K_BGS:
       if (L.bdense)
-        return (h->f32 ? 4.0 : 8.0) * L.bd_entries + (double)L.bd_Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
+        return (h->f32 ? 4.0 : 8.0) * L.bd.entries + (double)L.bd.Loff.nnz * mb + 4.0 * n + 3.0 * vb * n;
       if (L.dense_smooth) return (h->f32 ? 4.0 : 8.0) * L.dense_entries + 2.0 * vb * n;
       return (half + n) * mb + 4.0 * n + 2.0 * vb * n;
     case CPC_K_ILU_L: return half * mb + 4.0 * n + 2.0 * vb * n;
@@ -2745,7 +2796,7 @@ cpc_status cpc_smoother_kind(cpc_handle h, int32_t level, int32_t* kind, int32_t
   if (block_rows) *block_rows = L.sweep_R;
   if (L.nS <= 0 || level + 1 == (int32_t)h->lev.size()) *kind = -1;
   else *kind = L.dense_smooth ? 1 : (L.bdense ? 2 : 0);
-  if (block_rows && L.bdense) *block_rows = L.bd_B;
+  if (block_rows && L.bdense) *block_rows = L.bd.B;
   return CPC_OK;
 }
 
@@ -2991,32 +3042,42 @@ cpc_status cpc_time_kernel(cpc_handle h, int32_t kernel, int32_t level, int32_t 
       // the method's share: the forward and backward triangular solves these products
       // evaluate, spread over their launches
       for (int d : levels) mbytes += method_kernel_bytes(h, CPC_K_FGS, d) + method_kernel_bytes(h, CPC_K_BGS, d);
-      std::vector<std::pair<int, int>> items;  // (level, block or -1 for the whole level)
+      struct Item {
+        int level, dir, step;  // step of the block-dense form, or -1 for a whole-level inverse
+      };
+      std::vector<Item> items;
       for (int d : levels) {
         const Level& L = h->lev[d];
-        const int K = L.bdense ? (int)L.bd_start.size() - 1 : 1;
-        for (int b = 0; b < K; ++b) {
-          items.push_back({d, L.bdense ? b : -1});
-          const double nb = L.bdense ? L.bd_start[b + 1] - L.bd_start[b] : (double)L.nS;
-          const double entries = L.bdense ? 0.5 * nb * (nb + 1) : L.dense_entries;
-          bytes += 2.0 * (eb * entries + 2.0 * vb * nb);
+        for (int dir = 0; dir < 2; ++dir) {
+          const int T = L.bdense ? bd_steps(L, dir == 1) : 1;
+          for (int t = 0; t < T; ++t) {
+            items.push_back({d, dir, L.bdense ? t : -1});
+            if (!L.bdense) {
+              bytes += eb * L.dense_entries + 2.0 * vb * L.nS;
+              continue;
+            }
+            const std::vector<int>& step = dir == 1 ? L.bd.bstep : L.bd.fstep;
+            for (int q = step[t]; q < step[t + 1]; ++q) {
+              const double nb = L.bd.rows[dir == 1 ? L.bd.bblk[q] : q];
+              bytes += eb * 0.5 * nb * (nb + 1) + 2.0 * vb * nb;
+            }
+          }
         }
       }
-      const int count = 2 * (int)items.size();
+      const int count = (int)items.size();
       pool.resize(2 * (size_t)count);
       for (auto& e : pool) HIPCHK(hipEventCreate(&e));
       auto pass = [&](bool timed) {
         int q = 0;
         for (const auto& it : items) {
-          Level& L = h->lev[it.first];
-          void* f = it.first == 0 ? h->pin : L.f;
-          void* u = it.first == 0 ? h->u1 : L.u;
-          const DenseTriDev dt = it.second >= 0 ? bd_block(L, it.second) : L.dtri;
-          for (int dir = 0; dir < 2; ++dir, ++q) {
-            hipEvent_t e0 = timed ? pool[2 * q] : nullptr, e1 = timed ? pool[2 * q + 1] : nullptr;
-            if (dir == 0) launch_dense_lower(h->stream, dt, f32, f32, f, u, nullptr, e0, e1);
-            else launch_dense_lower_t(h->stream, dt, f32, f32, f, u, nullptr, e0, e1);
-          }
+          Level& L = h->lev[it.level];
+          void* f = it.level == 0 ? h->pin : L.f;
+          void* u = it.level == 0 ? h->u1 : L.u;
+          const DenseTriDev dt = it.step >= 0 ? bd_step(L, it.dir == 1, it.step) : L.dtri;
+          hipEvent_t e0 = timed ? pool[2 * q] : nullptr, e1 = timed ? pool[2 * q + 1] : nullptr;
+          ++q;
+          if (it.dir == 0) launch_dense_lower(h->stream, dt, f32, f32, f, u, nullptr, e0, e1);
+          else launch_dense_lower_t(h->stream, dt, f32, f32, f, u, nullptr, e0, e1);
         }
       };
       pass(false);  // warm-up
