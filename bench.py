@@ -76,6 +76,51 @@ def cpu_baseline(p, iters_gpu):
     return h, r, setup_s, solve_s, np
 
 
+def chain_latency(dev, reps):
+    """Dependent-step latencies of the one-wave sweep kernel on a chain (tridiagonal
+    matrix, one row per level set): with the whole chain in one block every step is an
+    in-block step (t_step); with two-row blocks every second step waits for another
+    workgroup's store (t_hop, the cross-workgroup hand-off beyond an in-block step)."""
+    import numpy as np
+    import paper_1205_6113_amd as cpc
+    n = 8192  # the largest one-block sweep with a forced block size
+    rp = np.concatenate([[0], np.cumsum([2] + [3] * (n - 2) + [2])]).astype(np.int32)
+    ci, v = [], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                ci.append(j)
+                v.append(2.5 if j == i else -1.0)
+    ci = np.array(ci, np.int32)
+    v = np.array(v)
+    ms = {}
+    for R in (n, 2):
+        with cpc.Solver(n, rp, ci, v, device=dev, sweep_block_rows=R, dense_smoother="never") as s:
+            ms[R] = s.time_kernel("fgs", level=0, reps=reps)["avg_ms"]
+    t_step = 1000.0 * ms[n] / n
+    t_hop = 2.0 * 1000.0 * ms[2] / n - 2.0 * t_step
+    return {"t_step_us": round(t_step, 4), "t_hop_us": round(t_hop, 4), "chain_rows": n,
+            "one_block_ms": round(ms[n], 4), "two_row_blocks_ms": round(ms[2], 4)}
+
+
+def sweep_roofs(solver, info, lat, reps):
+    """Both roofs of every level smoothed by level-scheduled sweeps: the HBM floor (the
+    forward sweep's method bytes at 8 TB/s) and the latency floor (dependency depth times
+    the in-block step latency; depth times step plus hand-off if every level crossed a
+    workgroup), beside the measured forward sweep."""
+    rows = []
+    for d in range(info["nlev"] - 1):
+        if info["smoother"][d] != "sweep":
+            continue
+        tk = solver.time_kernel("fgs", level=d, reps=reps)
+        depth = info["depth"][d]
+        rows.append({"level": d, "rows": info["n"][d], "depth": depth, "measured_ms": round(tk["avg_ms"], 4),
+                     "method_bytes": tk["bytes"], "hbm_floor_ms": round(tk["bytes"] / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
+                     "latency_floor_ms": round(depth * lat["t_step_us"] / 1000.0, 4),
+                     "all_hops_ms": round(depth * (lat["t_step_us"] + lat["t_hop_us"]) / 1000.0, 4)})
+    return rows
+
+
 def bench_batch(args):
     """Batch of 64 independent TPFA systems (edges 32..96) in one batched solve, against
     the same 64 systems solved one after the other with single-system handles."""
@@ -383,6 +428,10 @@ def main():
                 "form_bytes_per_launch": fd["form_bytes_per_launch"], "launches_timed": fd["launches_timed"]}
     log(f"roofline {dom}: {fd['avg_launch_us']:.2f} us/launch, {fd['method_bytes_per_launch'] / 1e6:.3f} MB "
         f"method bytes/launch -> {achieved:.1f} GB/s")
+    # the sweeps' two roofs (HBM bytes and dependency latency)
+    lat = chain_latency(dev, args.roofline_reps)
+    sroofs = sweep_roofs(solver, info, lat, args.roofline_reps)
+    log(f"sweep latency: {lat}; levels: {sroofs}")
     # after the timed launches, so that the copy's write-backs do not land on them
     if args.copy_calibration > 0:
         nbytes = args.copy_calibration * (1 << 20)
@@ -445,6 +494,7 @@ def main():
                    "precision": args.precision},
         "roofline": roofline,
         "families": fam,
+        "sweep_roofs": {"latency": lat, "levels": sroofs},
     }
     if compare:
         out["config"]["compare"] = compare
