@@ -183,6 +183,7 @@ __global__ __launch_bounds__(kNT) void bdense_kernel(DenseListDev dl, const void
   if (done && *done) return;
   const int blk = blockIdx.x;
   const int ent = dl.blk_entry[blk];
+  if (masked(dl.mask, ent)) return;  // a system that has stopped
   const int n0 = dl.n[ent];
   const int off = dl.off[ent];
   const double* inv = dl.inv + dl.inv_off[ent];

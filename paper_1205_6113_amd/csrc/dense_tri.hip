@@ -218,6 +218,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   int n, a0, b0, na, nb, voff;
   long moff;
   if (dt.one_n > 0) {  // item k: rows 4k.. and the mirrored group m-1-k, if it lies below
+    if (masked(dt.mask, dt.one_sys)) return;
     n = dt.one_n;
     voff = dt.one_voff;
     moff = dt.one_moff;
@@ -229,6 +230,7 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   } else {
     const int4 iv = dt.item_n[blockIdx.x];
     const int s = iv.x;
+    if (masked(dt.mask, s)) return;  // a block of a system that has stopped
     n = dt.n[s];
     a0 = iv.y;
     b0 = iv.z;

@@ -755,6 +755,7 @@ void build_wave_schedule_parts(const HostCsr& a, bool forward, int W, int M, con
   }
   if (np == 1) {
     s = std::move(ps[0]);
+    s.blk_part.assign(s.nblk, 0);
     return;
   }
   // merge: each part's blocks keep their order; parts interleave by the fraction of
@@ -790,6 +791,7 @@ void build_wave_schedule_parts(const HostCsr& a, bool forward, int W, int M, con
     }
     s.blk_ptr.push_back((int)s.rows.size());
     s.blk_lvl.push_back((int)s.lvl_ptr.size() - 1);
+    s.blk_part.push_back(p);
     s.R = std::max(s.R, q.blk_ptr[t + 1] - q.blk_ptr[t]);
   }
   s.nblk = (int)s.blk_ptr.size() - 1;

@@ -98,6 +98,7 @@ struct WaveSchedule {
   std::vector<int> lvl_ptr;   // level boundaries within `rows`
   std::vector<int> slot;      // [n] LDS slot of each row within its block
   std::vector<int> block_of;  // [n] processing index of each row's block
+  std::vector<int> blk_part;  // nblk: part (system) of block t (build_wave_schedule_parts)
 };
 
 // Longest lower coupling i - j (j < i) that most rows share (0 for a diagonal matrix).

@@ -80,7 +80,8 @@ template <int TPR, int U, typename VT, typename XT, typename FT, typename YT>
 __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const VT* __restrict__ v, const XT* __restrict__ x,
                                                    const FT* __restrict__ f, YT* __restrict__ y, int mode,
-                                                   const int* __restrict__ rid, const int* __restrict__ done) {
+                                                   const int* __restrict__ rid, SysMask mask,
+                                                   const int* __restrict__ done) {
   constexpr int RPB = kNT / TPR;
   const int lane = threadIdx.x % TPR;
   const int stride = gridDim.x * RPB;
@@ -99,7 +100,8 @@ __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict_
   }
   if (done && *done) return;
   for (; i < n; i += stride) {
-    const double s0 = row_dot<TPR, U>(b + lane, e, ci, v, x);
+    const bool skip = masked(mask, o);  // a row of a system that has stopped
+    const double s0 = row_dot<TPR, U>(b + lane, skip ? b : e, ci, v, x);
     const int in = i + stride;
     const double gi = g;
     const int oi = o;
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(kNT) void spmv_kernel(int n, const int* __restrict_
       g = mode == 1 ? ld(f, o) : (mode == 2 ? ld(y, o) : 0.0);
     }
     const double s = gsum<TPR>(s0);
-    if (lane == 0) {
+    if (lane == 0 && !skip) {
       if (mode == 0) st(y, oi, s);
       else if (mode == 1) st(y, oi, gi - s);
       else st(y, oi, gi + s);
@@ -340,7 +342,7 @@ static void spmv_typed_u(hipStream_t s, const MatDev& A, int mode, const void* x
   const int grid = grid_for(A.n, rpb);
 #define CPC_SPMV_CALL(T)                                                                                  \
   spmv_kernel<T, U, VT, XT, FT, YT><<<grid, kNT, 0, s>>>(A.n, A.rp, A.ci, (const VT*)A.v, (const XT*)x,  \
-                                                         (const FT*)f, (YT*)y, mode, A.rid, done)
+                                                         (const FT*)f, (YT*)y, mode, A.rid, A.mask, done)
   CPC_TPR_DISPATCH(tpr, CPC_SPMV_CALL)
 #undef CPC_SPMV_CALL
 }

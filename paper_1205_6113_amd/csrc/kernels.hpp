@@ -31,6 +31,20 @@ struct PcgState {
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_MAXIT = 2, DONE_BREAKDOWN = 3, DONE_ZERO_RHS = 4 };
 
+// Per-system mask of a batched solve: unit k of a launch (a row, a block, a system of a
+// dense list) belongs to system of[k] (-1: to none alone), and the launch skips units
+// whose system has stopped (done[s] != 0). Null done: no mask. Units are masked only where
+// no unit of a running system waits on them (blocks never span two systems).
+struct SysMask {
+  const int* of = nullptr;
+  const int* done = nullptr;
+};
+__device__ __forceinline__ bool masked(const SysMask& m, int k) {
+  if (!m.done || !m.of) return false;
+  const int s = m.of[k];
+  return s >= 0 && m.done[s] != 0;
+}
+
 // Device counters shared by every persistent sweep launch (self-resetting).
 struct SweepSync {
   unsigned* ticket;  // [1]
@@ -56,6 +70,7 @@ struct SweepDev {
   int off_xs, off_rows, off_ptr, off_meta;  // byte offsets of the LDS arrays (products start at 0)
   int grid;              // workgroups launched
   int nt;                // threads per workgroup: 64 or 256
+  SysMask mask{};        // by block (blocks within one system only)
 };
 
 enum SweepOp {
@@ -75,6 +90,7 @@ struct MatDev {  // CSR on the device; values of type T
   int steps;  // entries per lane a small launch takes at once in a row product: 1, 2 or 4
   // SpMV only: row k of the matrix is level row rid[k] of f and y (null: row k itself)
   const int* rid = nullptr;
+  SysMask mask{};  // SpMV only: by level row (the output index)
 };
 
 // ---- launchers (all asynchronous on `s`) -----------------------------------
@@ -125,6 +141,7 @@ struct DenseListDev {
   const int* off;         // [entries] offset of its segment in the level vector
   const long* inv_off;    // [entries] offset of its row-major inverse in inv
   const double* inv;      // concatenated inverses (FP64)
+  SysMask mask{};         // by entry
 };
 
 void launch_bspmv_pq(hipStream_t s, const BatchDev& bd, const MatDev& A, const double* p, double* q, int tpr);
@@ -156,6 +173,7 @@ struct WaveDev {
   const int* row;       // [nsteps][G] row of each group, -1 for none
   const int* slot;      // [nsteps][G] LDS slot of the group's row within its block
   const void* dinv;     // [nsteps][G] reciprocal diagonal of the group's row
+  SysMask mask{};       // by ticket (processing position of the block)
 };
 
 struct SweepPackDev {
@@ -193,6 +211,8 @@ struct DenseTriDev {
   int one_n;
   int one_voff;
   long one_moff;
+  int one_sys;     // the system index (of mask) of a one_n launch
+  SysMask mask{};  // by system index of the list (a block of the block-dense form)
 };
 // Row stride of a stored n x n inverse: n rounded up to a multiple of 4 elements, so
 // that every row starts 16-byte aligned (the padding columns hold zeros), and 8 more

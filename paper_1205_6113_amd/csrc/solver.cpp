@@ -168,6 +168,8 @@ struct Level {
   int sweep_rows = 0;  // rows the sweeps cover (all rows at depth 0 for ILU(0), else the smoothed ones)
   int sweep_R = 0;     // rows per block requested for them
   std::vector<int> parts;  // row ranges of the systems among the swept rows (batches; empty: one)
+  std::vector<int> part_sys;  // batch system of each part (batches only)
+  const int* row_sys = nullptr;  // [rows] batch system of each row of the level (batches only)
   int wave_M = 0;      // segments per block of the one-wave form (0: chosen by rule)
   bool wave_off = false;  // the four-wave kernel takes the level's solves (tuner's choice)
   int wave_stride = -1;  // the matrix's dominant coupling distance (-1: not yet measured)
@@ -183,6 +185,9 @@ constexpr int kNumPrec = CPC_PREC_BBAR + 1;  // preconditioners cpc_solve can ru
 
 struct cpc_solver {
   cpc_options opt{};
+  // batched solves: the per-system stop flags the preconditioner's kernels skip stopped
+  // systems by (set while a batched solve enqueues its work; null otherwise)
+  const int* mask_done = nullptr;
   int device = 0;  // the GPU the handle was set up on (current device at setup)
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -514,8 +519,10 @@ static int setup_threads() {
 // schedule; share: a form over the same schedule and pattern whose step, row, slot and
 // column arrays are reused (values differ). Not built (ok = 0) when no supported shape
 // holds the longest row (more than 64 dependency entries).
+// part_sys (batches): the batch system of each part of the schedule, for the per-system
+// mask of the blocks.
 static WaveDev upload_wave(cpc_solver* h, const HostCsr& a, const std::vector<double>& vals, const WaveSchedule& s,
-                           const WaveDev* share) {
+                           const WaveDev* share, const std::vector<int>* part_sys = nullptr) {
   WaveDev w{};
   std::vector<std::pair<int, int>> shapes;
   // up to 64 dependency entries per row: longer rows (wide Galerkin levels) run faster
@@ -541,7 +548,18 @@ static WaveDev upload_wave(cpc_solver* h, const HostCsr& a, const std::vector<do
     w.col = share->col;
     w.row = share->row;
     w.slot = share->slot;
+    w.mask = share->mask;
   } else {
+    if (part_sys && (int)s.blk_part.size() == s.nblk) {
+      std::vector<int> bs(s.nblk);
+      bool okp = true;
+      for (int t = 0; t < s.nblk; ++t) {
+        const int p = s.blk_part[t];
+        okp = okp && p >= 0 && p < (int)part_sys->size();
+        bs[t] = okp ? (*part_sys)[p] : -1;
+      }
+      if (okp) w.mask.of = dupload(bs, *h->cur_owned, h->stream);
+    }
     w.blk_step = dupload(wp.blk_step, *h->cur_owned, h->stream);
     w.col = dupload(wp.col, *h->cur_owned, h->stream);
     w.row = dupload(wp.row, *h->cur_owned, h->stream);
@@ -589,7 +607,8 @@ static int parts_stride(const HostCsr& a, const std::vector<int>& parts) {
 // numbers of level sets.
 static bool build_wave_forms(cpc_solver* h, const HostCsr& a, int R, int M, const std::vector<int>& parts,
                              SweepPackDev& lo, SweepPackDev& up, const std::vector<double>* lu, SweepPackDev* ilo,
-                             SweepPackDev* iup, int* depth_lo, int* depth_up) {
+                             SweepPackDev* iup, int* depth_lo, int* depth_up,
+                             const std::vector<int>* part_sys = nullptr) {
   if (h->opt.sweep_kernel == 1) return false;
   const int W = std::max(1, R / std::max(1, M));
   const int threads = std::max(1, setup_threads() / 2);
@@ -597,8 +616,8 @@ static bool build_wave_forms(cpc_solver* h, const HostCsr& a, int R, int M, cons
   std::thread tl([&] { build_wave_schedule_parts(a, true, W, M, parts, threads, wl); });
   build_wave_schedule_parts(a, false, W, M, parts, threads, wu);
   tl.join();
-  lo.wave = upload_wave(h, a, a.v, wl, nullptr);
-  up.wave = upload_wave(h, a, a.v, wu, nullptr);
+  lo.wave = upload_wave(h, a, a.v, wl, nullptr, part_sys);
+  up.wave = upload_wave(h, a, a.v, wu, nullptr, part_sys);
   bool all = lo.wave.ok && up.wave.ok;
   if (lu && ilo && iup) {
     ilo->wave = upload_wave(h, a, *lu, wl, &lo.wave);
@@ -720,6 +739,29 @@ static void build_fourwave(cpc_solver* h, const HostCsr& a, int R, DevSweepSched
   }
 }
 
+// The per-system mask of a batched solve over a launch's unit map (no mask outside a
+// batched solve or without a map).
+static SysMask mask_of(const cpc_solver* h, const int* of) {
+  SysMask m;
+  if (h->mask_done && of) {
+    m.of = of;
+    m.done = h->mask_done;
+  }
+  return m;
+}
+static MatDev masked_rows(const cpc_solver* h, MatDev m, const int* row_sys) {
+  m.mask = mask_of(h, row_sys);
+  return m;
+}
+static DenseTriDev dmask(const cpc_solver* h, DenseTriDev dt) {
+  dt.mask = mask_of(h, dt.mask.of);
+  return dt;
+}
+static DenseListDev lmask(const cpc_solver* h, DenseListDev dl) {
+  dl.mask = mask_of(h, dl.mask.of);
+  return dl;
+}
+
 // x = T^{-1} f for the triangular factor the pack holds (out = base + x for
 // SWEEP_UPPER_OUT). x is first filled with the not-yet-solved marker.
 // The triangular-solve kernel of a pack: the one-wave form where the pack has it, else
@@ -729,7 +771,9 @@ static void launch_tri(cpc_solver* h, int op, const DevSweepSched& sch, const Sw
                        void* x, const void* base, void* out, const int* done, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr) {
   if (pk.wave.ok) {
-    launch_wave_sweep(h->stream, op, pk.wave, h->f32, f, x, base, out, h->sync, done, h->spin_limit, ev0, ev1);
+    WaveDev w = pk.wave;
+    w.mask = mask_of(h, w.mask.of);
+    launch_wave_sweep(h->stream, op, w, h->f32, f, x, base, out, h->sync, done, h->spin_limit, ev0, ev1);
   } else {
     if (ev0) HIPCHK(hipEventRecord(ev0, h->stream));
     launch_sweep_packed(h->stream, op, sch.d, pk, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
@@ -964,7 +1008,9 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
     dt.one_n = ns[0];
     dt.one_voff = voffs[0];
     dt.one_moff = moff[0];
+    dt.one_sys = 0;
   }
+  if (h->batch && L.part_sys.size() == ns.size()) dt.mask.of = dupload(L.part_sys, h->owned, h->stream);
   dt.nitem_t = (int)itt.size();
   dt.item_t = dupload(itt, h->owned, h->stream);
   dt.nred = (int)red.size();
@@ -1078,9 +1124,11 @@ static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int 
     const int M = L.wave_M > 0 ? L.wave_M : wave_segments(L.wave_stride, R);
     SweepPackDev fw{}, bw{}, ilw{}, iuw{};
     int dlo = 0, dup = 0;
+    const std::vector<int>* psys =
+        (h->batch && L.part_sys.size() + 1 == parts.size() && parts.size() > 1) ? &L.part_sys : nullptr;
     const bool wave_all =
         !L.wave_off && build_wave_forms(h, sub, R, M, parts, fw, bw, with_ilu ? &h->lu_host : nullptr,
-                                        with_ilu ? &ilw : nullptr, with_ilu ? &iuw : nullptr, &dlo, &dup);
+                                        with_ilu ? &ilw : nullptr, with_ilu ? &iuw : nullptr, &dlo, &dup, psys);
     if (wave_all) {
       // the one-wave forms serve every solve of the level: no four-wave schedules
       L.lower = DevSweepSched{};
@@ -1172,11 +1220,14 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
     kmax = std::max(kmax, kc[p]);
   }
   std::vector<std::vector<int>> id(np);  // block index of the k-th block of part p
+  const bool with_sys = h->batch && (int)L.part_sys.size() == np;
+  std::vector<int> blk_sys;  // batch system of each block (per-system mask)
   bd.fstep.push_back(0);
   for (int k = 0; k < kmax; ++k) {
     for (int p = 0; p < np; ++p) {
       if (k >= kc[p]) continue;
       id[p].push_back(bd.nblk());
+      if (with_sys) blk_sys.push_back(L.part_sys[p]);
       const int r0 = parts[p] + k * B;
       bd.start.push_back(r0);
       bd.rows.push_back(std::min(B, parts[p + 1] - r0));
@@ -1314,6 +1365,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
     dt.MT = MT;
     bd.items_f = dupload(itf, own, h->stream);
     bd.items_b = dupload(itb, own, h->stream);
+    if (with_sys) dt.mask.of = dupload(blk_sys, own, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError&) {
     return drop();
@@ -1346,6 +1398,7 @@ static DenseTriDev bd_step(const Level& L, bool upper, int t) {
     dt.one_n = bd.rows[b];
     dt.one_voff = bd.start[b];
     dt.one_moff = bd.moff[b];
+    dt.one_sys = b;
   }
   return dt;
 }
@@ -1367,8 +1420,9 @@ static void bdense_solve(cpc_solver* h, Level& L, bool upper, const void* f, voi
     m.n = rows[t + 1] - rows[t];
     m.rp = off.rp + rows[t];
     m.rid = (upper ? bd.Urid : bd.Lrid) + rows[t];
+    m.mask = mask_of(h, L.row_sys);
     spmv_or_throw(h, m, 1, x, f32, f, f32, g, f32, off.tpr, done);
-    const DenseTriDev dt = bd_step(L, upper, t);
+    const DenseTriDev dt = dmask(h, bd_step(L, upper, t));
     if (upper) launch_dense_lower_t(h->stream, dt, f32, f32, g, x, done);
     else launch_dense_lower(h->stream, dt, f32, f32, g, x, done);
   }
@@ -1698,22 +1752,35 @@ static int assemble_levels(cpc_solver* h, std::vector<SysHier>& sys, const cpc_o
     }
     // exact solves of the systems that bottom out here
     {
-      std::vector<int> doff, dn;
+      std::vector<int> doff, dn, dsys;
       std::vector<const std::vector<double>*> invs;
       for (int s : order[d])
         if (d + 1 == (int)sys[s].A.size()) {
           doff.push_back(off[d][s]);
           dn.push_back(sys[s].A[d].n);
+          dsys.push_back(s);
           invs.push_back(&sys[s].inv);
         }
       L.dense = upload_dense_list(h, doff, dn, invs);
       L.dense_n = dn;
+      if (h->batch && !dsys.empty()) L.dense.mask.of = dupload(dsys, h->owned, h->stream);
+    }
+    // batch system of every row of the level (per-system masks of the batched solve)
+    if (h->batch) {
+      std::vector<int> rs(ntot[d], -1);
+      for (int s : order[d])
+        std::fill(rs.begin() + off[d][s], rs.begin() + off[d][s] + sys[s].A[d].n, s);
+      L.row_sys = dupload(rs, h->owned, h->stream);
     }
     // sweep schedules and packed rows: the smoothed rows (all rows at depth 0, for ILU(0))
     const int rows = (d == 0) ? ntot[0] : L.nS;
     L.parts.assign(1, 0);
+    L.part_sys.clear();
     for (int s : order[d])
-      if (off[d][s] + sys[s].A[d].n <= rows) L.parts.push_back(off[d][s] + sys[s].A[d].n);
+      if (off[d][s] + sys[s].A[d].n <= rows) {
+        L.parts.push_back(off[d][s] + sys[s].A[d].n);
+        L.part_sys.push_back(s);
+      }
     if (rows > 0) {
       HostCsr sub = (rows == ntot[d]) ? A : leading_rows(A, rows);
       const int Rb = o.sweep_block_rows > 0 ? std::min(o.sweep_block_rows, sweep_max_rows_per_block())
@@ -1833,27 +1900,27 @@ static void vcycle(cpc_solver* h, int d, const void* f, void* u, const int* done
   const bool f32 = h->f32;
   if (L.nS > 0 && d + 1 < (int)h->lev.size()) {
     Level& C = h->lev[d + 1];
-    const MatDev A = smoothed(L.A, L.nS, f32);
+    const MatDev A = masked_rows(h, smoothed(L.A, L.nS, f32), L.row_sys);
     // (1) pre-smoothing from zero: u = (D+L)^{-1} f
-    if (L.dense_smooth) launch_dense_lower(h->stream, L.dtri, f32, f32, f, u, done);
+    if (L.dense_smooth) launch_dense_lower(h->stream, dmask(h, L.dtri), f32, f32, f, u, done);
     else if (L.bdense) bdense_solve(h, L, false, f, u, L.r, done);
     else run_sweep(h, SWEEP_LOWER, L.lower, L.fgs, f, u, nullptr, nullptr, done);
     // (2a) f_c = R (f - A u)
     spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);
-    spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
+    spmv_or_throw(h, masked_rows(h, L.R.mat(f32), C.row_sys), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
     // (2b) coarse correction
     vcycle(h, d + 1, C.f, C.u, done);
     // (2c) u += P e
-    spmv_or_throw(h, L.P.mat(f32), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);
+    spmv_or_throw(h, masked_rows(h, L.P.mat(f32), L.row_sys), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);
     // (3) post-smoothing, one backward Gauss-Seidel sweep (S_l^T): the new u solves
     //     (D+U) u = f - L u_old, the strict lower part taken at the old values
-    spmv_or_throw(h, L.Ls.mat(f32), 1, u, f32, f, f32, L.t, f32, L.Ls.tpr, done);
-    if (L.dense_smooth) launch_dense_lower_t(h->stream, L.dtri, f32, f32, L.t, u, done);  // (D+U)^{-1} = T^{-T}
+    spmv_or_throw(h, masked_rows(h, L.Ls.mat(f32), L.row_sys), 1, u, f32, f, f32, L.t, f32, L.Ls.tpr, done);
+    if (L.dense_smooth) launch_dense_lower_t(h->stream, dmask(h, L.dtri), f32, f32, L.t, u, done);  // T^{-T}
     else if (L.bdense) bdense_solve(h, L, true, L.t, u, L.r, done);
     else run_sweep(h, SWEEP_UPPER, L.upper, L.bgs, L.t, u, nullptr, nullptr, done);
   }
   // systems whose coarsest level is this one: e = A_0^{-1} f (FP64 inverse)
-  if (L.dense.nblk > 0) launch_bdense(h->stream, L.dense, f, u, f32, done);
+  if (L.dense.nblk > 0) launch_bdense(h->stream, lmask(h, L.dense), f, u, f32, done);
 }
 
 // z = (LU)^{-1} f (out = nullptr) or out = base + (LU)^{-1} f
@@ -1875,22 +1942,24 @@ static void vcycle_ilu_top(cpc_solver* h, const void* f, void* u, const int* don
     return;
   }
   Level& C = h->lev[1];
-  const MatDev A = smoothed(L.A, L.nS, f32);
+  const MatDev A = masked_rows(h, smoothed(L.A, L.nS, f32), L.row_sys);
+  const MatDev R = masked_rows(h, L.R.mat(f32), C.row_sys), P = masked_rows(h, L.P.mat(f32), L.row_sys);
   ilu_apply(h, f, u, nullptr, nullptr, done);                                           // (1)
   spmv_or_throw(h, A, 1, u, f32, f, f32, L.r, f32, L.A.tpr, done);                       // (2a)
-  spmv_or_throw(h, L.R.mat(f32), 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
+  spmv_or_throw(h, R, 0, L.r, f32, nullptr, f32, C.f, f32, L.R.tpr, done);
   vcycle(h, 1, C.f, C.u, done);                                                         // (2b)
-  spmv_or_throw(h, L.P.mat(f32), 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);     // (2c)
+  spmv_or_throw(h, P, 2, C.u, f32, nullptr, f32, u, f32, L.P.tpr, done);                 // (2c)
   spmv_or_throw(h, A, 1, u, f32, f, f32, L.t, f32, L.A.tpr, done);                       // (3)
   ilu_apply(h, L.t, L.r, nullptr, nullptr, done);
   launch_vec(h->stream, 1, L.nS, L.r, f32, nullptr, false, u, f32, done);
-  if (L.dense.nblk > 0) launch_bdense(h->stream, L.dense, f, u, f32, done);
+  if (L.dense.nblk > 0) launch_bdense(h->stream, lmask(h, L.dense), f, u, f32, done);
 }
 
 // res = r - A u with FP64 A and FP64 r (outer residual of Algorithm 2.1)
 static void outer_residual(cpc_solver* h, const double* r, const void* u, void* res, const int* done) {
   Level& L = h->lev[0];
-  spmv_or_throw(h, L.A.mat(false), 1, u, h->f32, r, false, res, h->f32, L.A.tpr, done);
+  spmv_or_throw(h, masked_rows(h, L.A.mat(false), L.row_sys), 1, u, h->f32, r, false, res, h->f32, L.A.tpr,
+                done);
 }
 
 static void apply_op(cpc_solver* h, int op, const double* r, double* z, const int* done) {
@@ -2367,6 +2436,12 @@ static cpc_status run_solve_batch(cpc_solver* h, int prec, const double* b, doub
   if (maxit < 0 || !(tol >= 0.0)) return set_err(CPC_E_ARG, "maxit must be >= 0 and tol >= 0");
   const double t0 = now_s();
   const int ns = h->nsys;
+  // the preconditioner's launches of this solve skip systems that have stopped
+  struct MaskScope {
+    cpc_solver* h;
+    ~MaskScope() { h->mask_done = nullptr; }
+  } mask_scope{h};
+  h->mask_done = h->bd.done;
   try {
     HIPCHK(hipMemcpyAsync(h->btol, &tol, sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(h->bmaxit, &maxit, sizeof(int), hipMemcpyHostToDevice, h->stream));

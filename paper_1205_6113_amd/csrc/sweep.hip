@@ -96,6 +96,7 @@ __global__ __launch_bounds__(NT) void tri_sweep_kernel(SweepDev sw, SweepPackDev
     __syncthreads();
     if (t >= sw.nblk) break;
     const int b = FWD ? t : sw.nblk - 1 - t;
+    if (masked(sw.mask, b)) continue;  // a block of a system that has stopped
     const int r0 = sw.blk_row[b], r1 = sw.blk_row[b + 1];
     const int nb = r1 - r0;
     const int lb = sw.blk_beg[b];

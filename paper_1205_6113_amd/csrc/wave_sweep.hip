@@ -73,6 +73,7 @@ __global__ __launch_bounds__(64) void tri_wave_kernel(WaveDev w, const XT* __res
     if (lane == 0) t = (int)atomicAdd(sy.ticket, 1u);
     t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
     if (t >= w.nblk) break;
+    if (masked(w.mask, t)) continue;  // a block of a system that has stopped
     const int s0 = w.blk_step[t], s1 = w.blk_step[t + 1];
 
     // entry data, row and diagonal of step s (clamped to the block's last step: past
