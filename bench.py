@@ -133,7 +133,8 @@ def bench_batch(args):
     log(f"workload c4: {len(probs)} systems, {n_tot} unknowns in all")
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    bs = cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs], device=dev, verbose=True)
+    bs = cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs], device=dev, verbose=True,
+                         tune=not args.rules)
     setup_s = time.perf_counter() - t0
     log(f"batch setup {setup_s:.1f}s")
     b = torch.as_tensor(np.concatenate([p.b for p in probs]), device=dev)
@@ -151,7 +152,7 @@ def bench_batch(args):
     # the same systems one by one (setups untimed): every 4th system, times 4
     seq_ms, errs = 0.0, []
     offs = bs.offsets
-    sample = list(range(0, len(probs), 4))
+    sample = [] if args.no_sequential else list(range(0, len(probs), 4))
     for k in sample:
         p = probs[k]
         log(f"single system {k}: n={p.n}")
@@ -166,8 +167,11 @@ def bench_batch(args):
         xb = x[offs[k]:offs[k] + p.n]
         errs.append(float(torch.linalg.norm(xb - x1) / torch.linalg.norm(x1)))
         s1.close()
-    seq_ms *= len(probs) / len(sample)
-    log(f"sequential: {seq_ms:.1f} ms for the {len(probs)} single-system solves (from {len(sample)} of them)")
+    if sample:
+        seq_ms *= len(probs) / len(sample)
+        log(f"sequential: {seq_ms:.1f} ms for the {len(probs)} single-system solves (from {len(sample)} of them)")
+    else:
+        seq_ms = None
     # method bytes: each system's own iterations (the per-iteration figure of the batch
     # is the sum over systems, so weight it by the systems' share of the unknowns); the
     # forms' bytes: the batched preconditioner runs over every system until the last stops
@@ -201,10 +205,11 @@ def bench_batch(args):
                    "systems": len(probs), "unknowns": n_tot, "setup_s": round(setup_s, 3),
                    "solves_per_s": round(len(probs) / (ms_batch / 1000.0), 2),
                    "iters_min": int(its.min()), "iters_max": int(its.max()), "iters_mean": float(its.mean()),
-                   "relres_max": float(rels.max()), "sequential_ms": round(seq_ms, 3),
-                   "sequential_sample": f"every 4th system ({len(sample)}), scaled by {len(probs) / len(sample):g}",
-                   "speedup_vs_sequential": round(seq_ms / ms_batch, 3),
-                   "x_relerr_batch_vs_single_max": max(errs),
+                   "relres_max": float(rels.max()), "sequential_ms": round(seq_ms, 3) if seq_ms else None,
+                   "sequential_sample": (f"every 4th system ({len(sample)}), scaled by {len(probs) / len(sample):g}"
+                                         if sample else None),
+                   "speedup_vs_sequential": round(seq_ms / ms_batch, 3) if seq_ms else None,
+                   "x_relerr_batch_vs_single_max": max(errs) if errs else None,
                    "method_bytes_per_batch_solve": method_batch, "form_bytes_per_batch_solve": form_batch,
                    "oracle_sample": oerr},
     }
@@ -337,6 +342,8 @@ def main():
                     help="copy MB megabytes device to device once (a plain copy of known size for "
                          "calibrating memory counters)")
     ap.add_argument("--rules", action="store_true", help="rule-based setup instead of the timing tuner")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="c4: skip the single-system solves the batch is compared with (profiling runs)")
     ap.add_argument("--verbose", action="store_true", help="print setup progress")
     ap.add_argument("--table", action="store_true",
                     help="instead of the benchmark line, the Table 5.2 comparison of preconditioners")

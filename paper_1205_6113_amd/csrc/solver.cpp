@@ -1346,15 +1346,24 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
     upload_csr(h, up, bd.Uoff, false, &own);
     bd.Lrid = dupload(lrid, own, h->stream);
     bd.Urid = dupload(urid, own, h->stream);
-    // a step's off-block product is a small launch that ends with its longest row:
-    // lanes enough for that row to take a single batch of four entries per lane
+    // a step's off-block product over one block is a small launch that ends with its
+    // longest row: lanes enough for that row to take a single batch of four entries per
+    // lane. Steps over many blocks (batches) have rows enough to keep the GPU busy: lanes
+    // by the average row, as for any large SpMV.
     for (auto* m : {&lo, &up}) {
       int longest = 0;
       for (int i = 0; i < m->n; ++i) longest = std::max(longest, m->rp[i + 1] - m->rp[i]);
       DevCsr& d = m == &lo ? bd.Loff : bd.Uoff;
-      d.tpr = 1;
-      while (d.tpr < 64 && 4 * d.tpr < longest) d.tpr <<= 1;
-      d.steps = 4;
+      const double rows_per_step = kmax > 0 ? (double)m->n / kmax : 0.0;
+      if (rows_per_step > 16384.0) {
+        const double avg = m->n ? (double)m->rp[m->n] / m->n : 1.0;
+        d.tpr = pick_tpr(avg);
+        d.steps = pick_steps(avg, d.tpr);
+      } else {
+        d.tpr = 1;
+        while (d.tpr < 64 && 4 * d.tpr < longest) d.tpr <<= 1;
+        d.steps = 4;
+      }
     }
     DenseTriDev& dt = bd.dt;
     dt = DenseTriDev{};
