@@ -169,6 +169,23 @@ cpc_status cpc_apply_op(cpc_handle h, int32_t op, const double* r_dev, double* z
  * 3.2); device FP64 vectors of length n_l. CPC_E_ARG for a level out of range. */
 cpc_status cpc_spmv(cpc_handle h, int32_t level, const double* x_dev, double* y_dev);
 
+/* C = X Y, the sparse product the SETUP's Galerkin products are made of (Section 3.2:
+ * A_{l+1} = P_l^T (A_l P_l) as two such products), on the current device with the
+ * same kernels: entry (i, j) of C accumulates the rounded products x_ik y_kj from 0.0
+ * in the column order of row i of X, without fused multiply-adds, so the result is
+ * bit-identical to a sequential evaluation in that order; the columns of each row of
+ * C come out sorted. Rows with more distinct columns than the kernels' LDS table
+ * (4096) take the wide-row path (a dense accumulator in device memory).
+ * Host CSR in (X: nrows x ninner, Y: ninner x ncols; sorted or unsorted columns, no
+ * duplicates within a row) and out: crp (nrows + 1 entries) and *nnz are written on
+ * every call; cci and cv (at least *nnz entries each) only when both are non-null, so
+ * a first call with null arrays sizes them. CPC_E_ARG on bad sizes or indices,
+ * CPC_E_NOMEM when C exceeds 2^31 entries or device memory, CPC_E_DEVICE on a device
+ * error. Exposed for tests and tools. */
+cpc_status cpc_spgemm(int32_t nrows, int32_t ninner, int32_t ncols, const int32_t* xrp, const int32_t* xci,
+                      const double* xv, const int32_t* yrp, const int32_t* yci, const double* yv, int32_t* crp,
+                      int32_t* cci, double* cv, int64_t* nnz);
+
 /* Description of the AMG hierarchy the SETUP built (Section 3.2: classical
  * coarsening, Galerkin coarse matrices, coarsest level solved exactly). Caller host
  * arrays hold at least max_levels entries: *nlev = number of levels; n_l[l], nnz_l[l]

@@ -5,4 +5,4 @@ in include/cpc.h); this package is its Python binding.
 """
 from ._lib import (CPC_E_ARG, CPC_E_BREAKDOWN, CPC_E_DEVICE, CPC_E_MAXIT, CPC_E_NOMEM,  # noqa: F401
                    CPC_E_NOT_SPD, CPC_OK, CpcError, LIB_PATH, load)
-from .solver import BatchSolver, Solver, options, setup_status  # noqa: F401
+from .solver import BatchSolver, Solver, options, setup_status, spgemm  # noqa: F401

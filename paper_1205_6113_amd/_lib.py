@@ -25,7 +25,8 @@ EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "c
            "cpc_hierarchy_info", "cpc_get_level", "cpc_get_prolongation", "cpc_get_ilu", "cpc_get_stats",
            "cpc_neg_outer_on_pattern", "cpc_time_kernel", "cpc_destroy", "cpc_last_error", "cpc_tpfa_pattern",
            "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values", "cpc_setup_batch",
-           "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind", "cpc_get_ilu_factor", "cpc_solve_noalloc")
+           "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind", "cpc_get_ilu_factor", "cpc_solve_noalloc",
+           "cpc_spgemm")
 KERNEL = {"spmv_pq": 0, "fgs": 1, "bgs": 2, "ilu_l": 3, "ilu_u": 4, "residual": 5, "restrict": 6, "prolong": 7,
           "vcycle": 8, "precond": 9, "iteration": 10, "dense_gemv": 11, "sweep": 12}
 
@@ -81,6 +82,8 @@ def load():
     lib.cpc_apply_op.restype = I32
     lib.cpc_spmv.argtypes = [P, I32, P, P]
     lib.cpc_spmv.restype = I32
+    lib.cpc_spgemm.argtypes = [I32, I32, I32, P, P, P, P, P, P, P, P, P, ctypes.POINTER(ctypes.c_int64)]
+    lib.cpc_spgemm.restype = I32
     lib.cpc_hierarchy_info.argtypes = [P, ctypes.POINTER(I32), P, P, P]
     lib.cpc_hierarchy_info.restype = I32
     lib.cpc_smoother_kind.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]

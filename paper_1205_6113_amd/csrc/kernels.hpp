@@ -275,13 +275,23 @@ void launch_neg_outer(hipStream_t s, const MatDev& A, const double* lam, const d
 void launch_to_f32(hipStream_t s, int64_t n, const double* a, float* y);
 
 // Galerkin product C = X * Y with the canonical accumulation order (see rap.hip).
-// Symbolic: counts[i] = distinct columns of row i; returns false on a row with more
-// distinct columns than the kernel's table holds (overflow flag set).
+// Symbolic: counts[i] = distinct columns of row i, or -1 for a row with more distinct
+// columns than the LDS table holds (a wide row; the flag `wide` is then set). Numeric:
+// rows with at least spgemm_table_capacity() entries in crp are left to the wide-row
+// kernels; a mismatch with crp sets `overflow`.
 void launch_spgemm_count(hipStream_t s, int nrows, const int* xrp, const int* xci, const int* yrp, const int* yci,
-                         int* counts, int* overflow);
+                         int* counts, int* wide);
 void launch_spgemm_fill(hipStream_t s, int nrows, const int* xrp, const int* xci, const double* xv, const int* yrp,
                         const int* yci, const double* yv, const int* crp, int* cci, double* cv, int* overflow);
 int spgemm_table_capacity();
+// Wide rows (the listed rows; nwg workgroups, each with an ncols-entry slice of mark
+// and acc in device memory, mark zeroed before each of the two calls): the same
+// canonical order with a dense accumulator, entries written in increasing column.
+void launch_spgemm_count_wide(hipStream_t s, int nlist, const int* rows, const int* xrp, const int* xci,
+                              const int* yrp, const int* yci, int ncols, int* mark, int nwg, int* counts);
+void launch_spgemm_fill_wide(hipStream_t s, int nlist, const int* rows, const int* xrp, const int* xci,
+                             const double* xv, const int* yrp, const int* yci, const double* yv, int ncols, int* mark,
+                             double* acc, int nwg, const int* crp, int* cci, double* cv, int* overflow);
 
 // Two-point-flux matrix values and log-permeability gradient (tpfa.hip).
 void launch_tpfa_values(hipStream_t s, int nx, int ny, int nz, double kz, int dirichlet, const double* logk,

@@ -333,10 +333,26 @@ static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncol
     HIPCHK(hipMemcpyAsync(hc.data(), counts, sizeof(int) * nrows, hipMemcpyDeviceToHost, hs));
     HIPCHK(hipMemcpyAsync(&hovf, ovf, sizeof(int), hipMemcpyDeviceToHost, hs));
     HIPCHK(hipStreamSynchronize(hs));
-    if (hovf) {
-      if (msg) *msg = "Galerkin product row exceeds " + std::to_string(spgemm_table_capacity()) + " columns";
-      ok = false;
-    } else {
+    // rows wider than the LDS table: counted (and later filled) with a dense accumulator
+    // slice of ncols entries per workgroup, at most 64 workgroups and 1 GiB
+    std::vector<int> wide;
+    for (int i = 0; hovf && i < nrows; ++i)
+      if (hc[i] < 0) wide.push_back(i);
+    int nwg = 0;
+    int* wrows = nullptr;
+    int* mark = nullptr;
+    if (!wide.empty()) {
+      nwg = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)wide.size(), 64,
+                                                          (int64_t)(1LL << 30) / (12LL * std::max(ncols, 1))}));
+      wrows = dupload(wide, tmp, hs);
+      mark = dalloc<int>((size_t)nwg * std::max(ncols, 1), tmp);
+      HIPCHK(hipMemsetAsync(mark, 0, sizeof(int) * (size_t)nwg * std::max(ncols, 1), hs));
+      launch_spgemm_count_wide(hs, (int)wide.size(), wrows, X.rp, X.ci, Y.rp, Y.ci, ncols, mark, nwg, counts);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hc.data(), counts, sizeof(int) * nrows, hipMemcpyDeviceToHost, hs));
+      HIPCHK(hipStreamSynchronize(hs));
+    }
+    {
       C_host.n = nrows;
       C_host.ncols = ncols;
       C_host.rp.assign(nrows + 1, 0);
@@ -357,7 +373,14 @@ static bool gpu_spgemm(cpc_solver* h, const DevCsr& X, const DevCsr& Y, int ncol
         C.rp = dupload(C_host.rp, keep, hs);
         C.ci = dalloc<int>((size_t)tot, keep);
         C.v = dalloc<double>((size_t)tot, keep);
+        HIPCHK(hipMemsetAsync(ovf, 0, sizeof(int), hs));
         launch_spgemm_fill(hs, nrows, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, C.rp, C.ci, C.v, ovf);
+        if (!wide.empty()) {
+          double* acc = dalloc<double>((size_t)nwg * std::max(ncols, 1), tmp);
+          HIPCHK(hipMemsetAsync(mark, 0, sizeof(int) * (size_t)nwg * std::max(ncols, 1), hs));
+          launch_spgemm_fill_wide(hs, (int)wide.size(), wrows, X.rp, X.ci, X.v, Y.rp, Y.ci, Y.v, ncols, mark, acc,
+                                  nwg, C.rp, C.ci, C.v, ovf);
+        }
         HIPCHK(hipGetLastError());
         C_host.ci.resize(tot);
         C_host.v.resize(tot);
@@ -2854,6 +2877,67 @@ cpc_status cpc_apply_op(cpc_handle h, int32_t op, const double* r_dev, double* z
     }
   } catch (const HipError& e) {
     return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  }
+  return CPC_OK;
+}
+
+cpc_status cpc_spgemm(int32_t nrows, int32_t ninner, int32_t ncols, const int32_t* xrp, const int32_t* xci,
+                      const double* xv, const int32_t* yrp, const int32_t* yci, const double* yv, int32_t* crp,
+                      int32_t* cci, double* cv, int64_t* nnz) {
+  if (nrows < 0 || ninner < 0 || ncols < 0 || !xrp || !yrp || !crp || !nnz)
+    return set_err(CPC_E_ARG, "cpc_spgemm: bad sizes or null arrays");
+  auto csr_ok = [](int n, int m, const int32_t* rp, const int32_t* ci, const double* v) {
+    if (rp[0] != 0) return false;
+    for (int i = 0; i < n; ++i)
+      if (rp[i + 1] < rp[i]) return false;
+    if (rp[n] > 0 && (!ci || !v)) return false;
+    for (int q = 0; q < rp[n]; ++q)
+      if (ci[q] < 0 || ci[q] >= m) return false;
+    return true;
+  };
+  if (!csr_ok(nrows, ninner, xrp, xci, xv) || !csr_ok(ninner, ncols, yrp, yci, yv))
+    return set_err(CPC_E_ARG, "cpc_spgemm: malformed CSR input");
+  try {
+    cpc_solver t;
+    HIPCHK(hipStreamCreate(&t.stream));
+    t.own_stream = true;
+    HostCsr X, Y, C;
+    X.n = nrows;
+    X.ncols = ninner;
+    X.rp.assign(xrp, xrp + nrows + 1);
+    X.ci.assign(xci, xci + xrp[nrows]);
+    X.v.assign(xv, xv + xrp[nrows]);
+    Y.n = ninner;
+    Y.ncols = ncols;
+    Y.rp.assign(yrp, yrp + ninner + 1);
+    Y.ci.assign(yci, yci + yrp[ninner]);
+    Y.v.assign(yv, yv + yrp[ninner]);
+    std::vector<void*> keep;
+    DevCsr Xd, Yd, Cd;
+    std::string msg;
+    bool ok = false;
+    try {
+      upload_csr(&t, X, Xd, false, &keep, false);
+      upload_csr(&t, Y, Yd, false, &keep, false);
+      ok = gpu_spgemm(&t, Xd, Yd, ncols, C, Cd, &msg, keep);
+      HIPCHK(hipStreamSynchronize(t.stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(t.stream);
+      for (void* p : keep) (void)hipFree(p);
+      throw;
+    }
+    for (void* p : keep) (void)hipFree(p);
+    if (!ok) return set_err(CPC_E_NOMEM, "cpc_spgemm: " + msg);
+    std::copy(C.rp.begin(), C.rp.end(), crp);
+    *nnz = C.rp[nrows];
+    if (cci && cv) {
+      std::copy(C.ci.begin(), C.ci.end(), cci);
+      std::copy(C.v.begin(), C.v.end(), cv);
+    }
+  } catch (const HipError& e) {
+    return set_err(CPC_E_DEVICE, e.where + ": " + hipGetErrorString(e.e));
+  } catch (const std::bad_alloc&) {
+    return set_err(CPC_E_NOMEM, "host allocation failed");
   }
   return CPC_OK;
 }

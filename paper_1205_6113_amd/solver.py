@@ -306,6 +306,25 @@ class BatchSolver:
         return Solver.stats(self)
 
 
+def spgemm(x, y, ncols: int):
+    """C = X Y on the GPU with the Galerkin products' canonical order (cpc_spgemm).
+    x, y: (row_ptr, col, val) host CSR triples (X: nrows x len(y row_ptr) - 1).
+    Returns (row_ptr, col, val) of C, columns sorted within each row."""
+    lib = load()
+    xrp, xci, xv = _host(x[0], np.int32), _host(x[1], np.int32), _host(x[2], np.float64)
+    yrp, yci, yv = _host(y[0], np.int32), _host(y[1], np.int32), _host(y[2], np.float64)
+    nrows, ninner = xrp.size - 1, yrp.size - 1
+    crp = np.empty(nrows + 1, np.int32)
+    nnz = ctypes.c_int64(0)
+    check(lib.cpc_spgemm(nrows, ninner, int(ncols), _ptr(xrp), _ptr(xci), _ptr(xv), _ptr(yrp), _ptr(yci), _ptr(yv),
+                         _ptr(crp), None, None, ctypes.byref(nnz)))
+    cci = np.empty(max(nnz.value, 1), np.int32)
+    cv = np.empty(max(nnz.value, 1), np.float64)
+    check(lib.cpc_spgemm(nrows, ninner, int(ncols), _ptr(xrp), _ptr(xci), _ptr(xv), _ptr(yrp), _ptr(yci), _ptr(yv),
+                         _ptr(crp), _ptr(cci), _ptr(cv), ctypes.byref(nnz)))
+    return crp, cci[:nnz.value], cv[:nnz.value]
+
+
 def setup_status(n, row_ptr, col, val, **opts) -> tuple[int, str]:
     """Run cpc_setup and return (status, message) without raising (host-side checks)."""
     lib = load()
