@@ -119,3 +119,28 @@ def test_batch_mid_size_systems_every_smoother_form(forms):
             xo = xs[bs.offsets[s]:bs.offsets[s] + p.n]
             err = np.linalg.norm(xo - r["x"]) / np.linalg.norm(r["x"])
             assert err <= 1e-10, (forms, s, err)
+
+
+def test_batch_fp32_preconditioner():
+    """The batch with the FP32 preconditioner (FP64 PCG): every system reaches the
+    tolerance on its true residual, takes at most one iteration more than the FP64
+    oracle, and its solution lies within 1e-10 of the oracle's (the bars of the
+    single-system FP32 test)."""
+    import paper_1205_6113_amd as cpc
+    probs, refs = _mid_batch()
+    b = torch.as_tensor(np.concatenate([p.b for p in probs]), device="cuda")
+    with cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs], precision="fp32") as bs:
+        x, it, rel, st = bs.solve(b, tol=1e-8)
+        assert st == 0
+        xs = x.cpu().numpy()
+        for s, p in enumerate(probs):
+            r = refs[s]
+            xo = xs[bs.offsets[s]:bs.offsets[s] + p.n]
+            rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
+            ax = np.zeros(p.n)
+            np.add.at(ax, rows, p.val * xo[p.col])
+            tr = np.linalg.norm(p.b - ax) / np.linalg.norm(p.b)
+            err = np.linalg.norm(xo - r["x"]) / np.linalg.norm(r["x"])
+            print(f"[fp32 batch] system {s}: iters {it[s]} (oracle {r['iters']}), true relres {tr:.2e}, "
+                  f"x err {err:.2e}", flush=True)
+            assert tr <= 1e-8 * 1.05 and it[s] <= r["iters"] + 1 and err <= 1e-10, (s, tr, it[s], err)
