@@ -108,6 +108,19 @@ int cpch_sweep(int n, const int* rp, const int* ci, const double* v, int forward
 // of another block read before that block wrote it, -4 a row written twice, into a slot
 // taken by another row, or never, -5 no pack (a row longer than every shape), -6 the
 // blocks' dependency graph has a cycle.
+// Block starts of the four-wave sweep schedule with R rows per block, no block spanning
+// two of the parts (parts: nparts + 1 boundaries, or null). Writes at most cap starts
+// (the last one = n) and returns their number.
+int cpch_block_starts(int n, const int* rp, const int* ci, const double* v, int R, const int* parts, int nparts,
+                      int* out, int cap) {
+  HostCsr a = make_csr(n, rp, ci, v);
+  std::vector<int> pv;
+  if (parts && nparts > 0) pv.assign(parts, parts + nparts + 1);
+  const std::vector<int> st = cpc::sweep_block_starts(a, R, pv.empty() ? nullptr : &pv);
+  for (int i = 0; i < (int)st.size() && i < cap; ++i) out[i] = st[i];
+  return (int)st.size();
+}
+
 int cpch_wave_emulate(int n, const int* rp, const int* ci, const double* v, int forward, int W, int M, int unit,
                       int ring, const double* f, double* x, int* shape, const int* parts, int nparts) {
   HostCsr a = make_csr(n, rp, ci, v);

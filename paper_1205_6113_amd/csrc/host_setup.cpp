@@ -445,34 +445,43 @@ int lower_depth(const HostCsr& a) {
   return depth;
 }
 
-std::vector<int> sweep_block_starts(const HostCsr& a, int R) {
+std::vector<int> sweep_block_starts(const HostCsr& a, int R, const std::vector<int>* parts) {
   const int n = a.n;
+  if (n <= 0) return {0, 0};
   R = std::max(1, std::min(R, n));
+  const bool use_parts = parts && parts->size() >= 2 && parts->front() == 0 && parts->back() == n;
+  const std::vector<int> pr = use_parts ? *parts : std::vector<int>{0, n};
   std::vector<int> starts{0};
-  while (starts.back() + R < n) {
-    const int s0 = starts.back();
-    int cut = s0 + R;
-    // prefer a row with no coupling to its predecessor
-    for (int i = s0 + R; i > s0 + R / 2; --i) {
-      bool coupled = false;
-      for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < i; ++p) coupled |= (a.ci[p] == i - 1);
-      if (!coupled) {
-        cut = i;
-        break;
+  for (size_t q = 0; q + 1 < pr.size(); ++q) {
+    const int end = pr[q + 1];
+    if (end <= starts.back()) continue;
+    while (starts.back() + R < end) {
+      const int s0 = starts.back();
+      int cut = s0 + R;
+      // prefer a row with no coupling to its predecessor
+      for (int i = s0 + R; i > s0 + R / 2; --i) {
+        bool coupled = false;
+        for (int p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < i; ++p) coupled |= (a.ci[p] == i - 1);
+        if (!coupled) {
+          cut = i;
+          break;
+        }
       }
+      starts.push_back(cut);
     }
-    starts.push_back(cut);
+    starts.push_back(end);
   }
-  starts.push_back(n);
+  if (starts.back() != n) starts.push_back(n);
   return starts;
 }
 
-SweepSchedule build_sweep(const HostCsr& a, bool forward, int R, int64_t max_entries) {
+SweepSchedule build_sweep(const HostCsr& a, bool forward, int R, int64_t max_entries,
+                          const std::vector<int>* parts) {
   SweepSchedule s;
   const int n = a.n;
   s.n = n;
   s.forward = forward;
-  s.blk_row = sweep_block_starts(a, R);
+  s.blk_row = sweep_block_starts(a, R, parts);
   s.nblk = (int)s.blk_row.size() - 1;
   s.R = 0;
   for (int b = 0; b < s.nblk; ++b) s.R = std::max(s.R, s.blk_row[b + 1] - s.blk_row[b]);

@@ -75,8 +75,10 @@ struct SweepSchedule {
 // level whose rows hold more dependency entries (entries left of the diagonal for the
 // forward direction, right of it for the backward one) is cut into consecutive levels
 // of at most max_entries entries each; a single row longer than that forms a level of
-// its own.
-SweepSchedule build_sweep(const HostCsr& a, bool forward, int R, int64_t max_entries = 0);
+// its own. parts (optional, {0, ..., n}): row ranges that no block may span (the
+// systems of a batch); every part boundary is a block boundary.
+SweepSchedule build_sweep(const HostCsr& a, bool forward, int R, int64_t max_entries = 0,
+                          const std::vector<int>* parts = nullptr);
 
 // Schedule of the one-wave triangular-solve kernel. Rows are cut into blocks that are
 // unions of up to M segments of W rows spaced `stride` rows apart: row i lies in the
@@ -179,7 +181,7 @@ bool build_wave_pack(const HostCsr& a, const std::vector<double>& vals, const Wa
                      const std::vector<std::pair<int, int>>& shapes, WavePack& w, int threads = 1);
 
 // Block starts used by build_sweep (size nblk + 1, last = n).
-std::vector<int> sweep_block_starts(const HostCsr& a, int R);
+std::vector<int> sweep_block_starts(const HostCsr& a, int R, const std::vector<int>* parts = nullptr);
 
 // Depth of the lower-triangular dependency graph (number of level sets).
 int lower_depth(const HostCsr& a);

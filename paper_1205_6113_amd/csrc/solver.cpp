@@ -445,21 +445,22 @@ struct SweepPlan {
   SweepSchedule s;
   SweepDev sd{};
 };
-static SweepPlan plan_sweep(const cpc_solver* h, const HostCsr& a, bool forward, int R) {
+static SweepPlan plan_sweep(const cpc_solver* h, const HostCsr& a, bool forward, int R,
+                            const std::vector<int>* parts = nullptr) {
   const int esz = (int)esz_of(h);
   const int budget = sweep_lds_budget();
   const int nt = sweep_threads();
   SweepPlan pl;
   SweepSchedule& s = pl.s;
   SweepDev& sd = pl.sd;
-  s = build_sweep(a, forward, R, 0);
+  s = build_sweep(a, forward, R, 0, parts);
   int room = (budget - 16 - sweep_layout(s, esz, 0, sd)) / 8;
   if (room < nt) throw HipError{hipErrorInvalidValue, "sweep block too large for LDS"};
   int64_t cap = s.max_level_entries;
   for (int tries = 0; cap > room; ++tries) {
     // cutting levels adds levels to the level table: leave some slack and retry
     cap = std::max<int64_t>(nt, (int64_t)(0.9 * room));
-    s = build_sweep(a, forward, R, cap);
+    s = build_sweep(a, forward, R, cap, parts);
     room = (budget - 16 - sweep_layout(s, esz, 0, sd)) / 8;
     if (room < nt || tries > 6) throw HipError{hipErrorInvalidValue, "sweep levels do not fit LDS"};
   }
@@ -478,8 +479,21 @@ static SweepPlan plan_sweep(const cpc_solver* h, const HostCsr& a, bool forward,
   return pl;
 }
 
-static void upload_sweep(cpc_solver* h, const SweepPlan& pl, DevSweepSched& d) {
+// parts / part_sys (batches): the system of each block, for the per-system mask (blocks
+// then never span two systems).
+static void upload_sweep(cpc_solver* h, const SweepPlan& pl, DevSweepSched& d, const std::vector<int>* parts = nullptr,
+                         const std::vector<int>* part_sys = nullptr) {
   SweepDev sd = pl.sd;
+  if (parts && part_sys && part_sys->size() + 1 == parts->size()) {
+    std::vector<int> bs(pl.s.nblk, -1);
+    size_t q = 0;
+    for (int b = 0; b < pl.s.nblk; ++b) {
+      const int r0 = pl.s.blk_row[b], r1 = pl.s.blk_row[b + 1];
+      while (q + 1 < parts->size() && (*parts)[q + 1] <= r0) ++q;
+      if (q + 1 < parts->size() && r1 <= (*parts)[q + 1]) bs[b] = (*part_sys)[q];
+    }
+    sd.mask.of = dupload(bs, *h->cur_owned, h->stream);
+  }
   sd.blk_row = dupload(pl.s.blk_row, *h->cur_owned, h->stream);
   sd.blk_beg = dupload(pl.s.blk_beg, *h->cur_owned, h->stream);
   sd.blk_end = dupload(pl.s.blk_end, *h->cur_owned, h->stream);
@@ -747,13 +761,22 @@ static SweepPackDev upload_pack(cpc_solver* h, const PackHost& ph, const SweepSc
 // (lu non-null: the ILU(0) values).
 static void build_fourwave(cpc_solver* h, const HostCsr& a, int R, DevSweepSched& lo, DevSweepSched& up,
                            SweepPackDev& fl, SweepPackDev& fu, const std::vector<double>* lu, SweepPackDev* il,
-                           SweepPackDev* iu) {
+                           SweepPackDev* iu, const std::vector<int>* parts = nullptr,
+                           const std::vector<int>* part_sys = nullptr) {
   SweepPlan pl, pu;
   PackHost hl, hu, hil, hiu;
-  both([&] { pl = plan_sweep(h, a, true, R); hl = pack_host(a, a.v, pl.s); if (lu) hil = pack_host(a, *lu, pl.s); },
-       [&] { pu = plan_sweep(h, a, false, R); hu = pack_host(a, a.v, pu.s); if (lu) hiu = pack_host(a, *lu, pu.s); });
-  upload_sweep(h, pl, lo);
-  upload_sweep(h, pu, up);
+  both([&] {
+         pl = plan_sweep(h, a, true, R, parts);
+         hl = pack_host(a, a.v, pl.s);
+         if (lu) hil = pack_host(a, *lu, pl.s);
+       },
+       [&] {
+         pu = plan_sweep(h, a, false, R, parts);
+         hu = pack_host(a, a.v, pu.s);
+         if (lu) hiu = pack_host(a, *lu, pu.s);
+       });
+  upload_sweep(h, pl, lo, parts, part_sys);
+  upload_sweep(h, pu, up, parts, part_sys);
   fl = upload_pack(h, hl, pl.s, nullptr);
   fu = upload_pack(h, hu, pu.s, nullptr);
   if (lu && il && iu) {
@@ -798,8 +821,10 @@ static void launch_tri(cpc_solver* h, int op, const DevSweepSched& sch, const Sw
     w.mask = mask_of(h, w.mask.of);
     launch_wave_sweep(h->stream, op, w, h->f32, f, x, base, out, h->sync, done, h->spin_limit, ev0, ev1);
   } else {
+    SweepDev sd = sch.d;
+    sd.mask = mask_of(h, sd.mask.of);
     if (ev0) HIPCHK(hipEventRecord(ev0, h->stream));
-    launch_sweep_packed(h->stream, op, sch.d, pk, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
+    launch_sweep_packed(h->stream, op, sd, pk, h->f32, f, x, base, out, h->sync, done, h->spin_limit);
     if (ev1) HIPCHK(hipEventRecord(ev1, h->stream));
   }
 }
@@ -1168,7 +1193,8 @@ static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int 
     } else {
       const int Rw = std::min(R, sweep_max_rows_per_block());  // the four-wave kernel's blocks
       build_fourwave(h, sub, Rw, L.lower, L.upper, L.fgs, L.bgs, with_ilu ? &h->lu_host : nullptr,
-                     with_ilu ? &h->ilu_l : nullptr, with_ilu ? &h->ilu_u : nullptr);
+                     with_ilu ? &h->ilu_l : nullptr, with_ilu ? &h->ilu_u : nullptr, h->batch ? &parts : nullptr,
+                     psys);
       L.fgs.wave = fw.wave;
       L.bgs.wave = bw.wave;
       if (with_ilu) {

@@ -30,6 +30,7 @@ def lib():
         L.cpch_sweep.argtypes = [I, P, P, P, I, I, I, P, P, P, P, P, P, P, P, P, P]
         L.cpch_dense_inverse.argtypes = [I, P, P, P, P]
         L.cpch_wave_emulate.argtypes = [I, P, P, P, I, I, I, I, I, P, P, P, P, I]
+        L.cpch_block_starts.argtypes = [I, P, P, P, I, P, I, P, I]
         _lib = L
     return _lib
 
@@ -182,3 +183,13 @@ def wave_emulate(n, rp, ci, v, forward, W, f, M=1, unit=False, ring=8, parts=Non
                                  _p(f), _p(x), _p(shape), None if pa is None else _p(pa),
                                  0 if pa is None else len(pa) - 1)
     return st, x, tuple(int(t) for t in shape)
+
+
+def block_starts(n, rp, ci, v, R, parts=None):
+    """Block starts of the four-wave sweep schedule (cpch_block_starts)."""
+    rp, ci, v = _csr(rp, ci, v)
+    out = np.zeros(n + 2, np.int32)
+    pa = None if parts is None else np.ascontiguousarray(parts, np.int32)
+    k = lib().cpch_block_starts(n, _p(rp), _p(ci), _p(v), int(R), None if pa is None else _p(pa),
+                                0 if pa is None else len(pa) - 1, _p(out), out.size)
+    return out[:k]

@@ -160,3 +160,17 @@ def test_long_rows_have_no_one_wave_pack():
     rows = np.repeat(np.arange(p.n), np.diff(p.row_ptr))
     v = np.where(p.col == rows, 1.0, p.val / 160.0)  # bounded unit-lower solve
     assert _check(p.n, p.row_ptr, p.col, v, 256, dense=False)
+
+
+def test_four_wave_blocks_never_span_systems():
+    """With a batch's system boundaries given, every boundary is a block start and no
+    block is longer than R (the per-system masks rely on it); without them, the starts
+    are those of the plain rule."""
+    probs = [gen.scaled_config(2, 0.15), gen.config1(9, 7), gen.scaled_config(3, 0.12), gen.config1(3, 2)]
+    n, rp, ci, v, parts = _block_diag(probs)
+    for R in (7, 256, 2048):
+        st = host_lib.block_starts(n, rp, ci, v, R, parts)
+        assert st[0] == 0 and st[-1] == n and np.all(np.diff(st) > 0) and np.all(np.diff(st) <= R)
+        assert set(parts) <= set(st.tolist())
+        plain = host_lib.block_starts(n, rp, ci, v, R)
+        assert plain[0] == 0 and plain[-1] == n and np.all(np.diff(plain) <= R)
