@@ -171,7 +171,6 @@ struct Level {
   std::vector<int> part_sys;  // batch system of each part (batches only)
   const int* row_sys = nullptr;  // [rows] batch system of each row of the level (batches only)
   int wave_M = 0;      // segments per block of the one-wave form (0: chosen by rule)
-  bool wave_off = false;  // the four-wave kernel takes the level's solves (tuner's choice)
   int wave_stride = -1;  // the matrix's dominant coupling distance (-1: not yet measured)
   // block-dense form of the smoother: block forward/backward substitution with explicit
   // inverses of the diagonal blocks of D+L (levels where it beats the sweeps)
@@ -621,19 +620,21 @@ static int wave_segments(int stride, int R) { return stride >= R ? 4 : 1; }
 // `lu` non-null) with R rows per block in M segments, into the packs given.
 // Largest over the parts of each part's dominant coupling distance.
 static int parts_stride(const HostCsr& a, const std::vector<int>& parts) {
-  int best = 0;
-  for (size_t p = 0; p + 1 < parts.size(); ++p) {
+  const int np = (int)parts.size() - 1;
+  std::vector<int> mode(std::max(np, 0), 0);
+  parallel_for(np, setup_threads(), [&](int p) {
     std::map<int, int> count;
     for (int i = parts[p]; i < parts[p + 1]; ++i)
       if (a.rp[i] < a.rp[i + 1] && a.ci[a.rp[i]] < i) ++count[i - a.ci[a.rp[i]]];
-    int mode = 0, mc = 0;
+    int mc = 0;
     for (const auto& kv : count)
       if (kv.second > mc) {
-        mode = kv.first;
+        mode[p] = kv.first;
         mc = kv.second;
       }
-    best = std::max(best, mode);
-  }
+  });
+  int best = 0;
+  for (int m : mode) best = std::max(best, m);
   return best;
 }
 
@@ -972,6 +973,7 @@ static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::
 // row products address one system's inverse with 32-bit byte offsets, which holds up to
 // 16384 rows (2 GiB in FP64); diagonal blocks of the block form obey the same limit.
 static constexpr int kDenseMaxRows = 16384;
+static constexpr double kBlockDenseMaxBytes = 32e9;  // the block form's inverses and transposes
 static constexpr double kDenseMaxBytes = 64e9;
 static constexpr int kDenseTransRows = 16384;
 
@@ -1175,7 +1177,7 @@ static void build_level_sweeps(cpc_solver* h, Level& L, const HostCsr& sub, int 
     const std::vector<int>* psys =
         (h->batch && L.part_sys.size() + 1 == parts.size() && parts.size() > 1) ? &L.part_sys : nullptr;
     const bool wave_all =
-        !L.wave_off && build_wave_forms(h, sub, R, M, parts, fw, bw, with_ilu ? &h->lu_host : nullptr,
+        build_wave_forms(h, sub, R, M, parts, fw, bw, with_ilu ? &h->lu_host : nullptr,
                                         with_ilu ? &ilw : nullptr, with_ilu ? &iuw : nullptr, &dlo, &dup, psys);
     if (wave_all) {
       // the one-wave forms serve every solve of the level: no four-wave schedules
@@ -1292,7 +1294,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   const int K = bd.nblk();
   double bytes = 0.0;
   for (int b = 0; b < K; ++b) bytes += 16.0 * bd.rows[b] * (double)bd.rows[b];
-  if (bytes > 32e9) return false;
+  if (bytes > kBlockDenseMaxBytes) return false;
   // entries outside each row's block, rows in step order (forward: left of the block;
   // backward: right of it)
   HostCsr lo, up;
@@ -1541,18 +1543,22 @@ static void tune_sweeps(cpc_solver* h) {
         }
       });
     };
-    // quick look: where block substitution with 4096-row blocks already beats the sweeps
-    // by half, tuning the sweeps' block size cannot change the outcome and is skipped
-    // (the block form stays as the candidate to beat)
+    // quick look: where block substitution already beats the sweeps by half, tuning the
+    // sweeps' block size cannot change the outcome and is skipped (the block form stays
+    // as the candidate to beat). Blocks of 4096 rows, or of 2048 / 1024 where the larger
+    // inverses would not fit the form's memory bound (batch levels of a million rows).
     std::map<int, float> bd_time;  // measured block-substitution candidates
     bool skip_r = false;
-    if (try_r && bd_ok && !L.dense_smooth && 4096 < L.sweep_rows) {
+    int qB = 4096;
+    while (qB > 1024 && 16.0 * (double)L.sweep_rows * qB > kBlockDenseMaxBytes) qB /= 2;
+    if (try_r && bd_ok && !L.dense_smooth && qB < L.sweep_rows &&
+        16.0 * (double)L.sweep_rows * qB <= kBlockDenseMaxBytes) {
       const float ts = gs_cost();
-      progress(h, "level " + std::to_string(d) + ": block substitution with 4096-row blocks");
-      if (build_blockdense(h, L, sub, 4096)) {
+      progress(h, "level " + std::to_string(d) + ": block substitution with " + std::to_string(qB) + "-row blocks");
+      if (build_blockdense(h, L, sub, qB)) {
         L.bdense = true;
         const float tb = gs_cost();
-        bd_time[4096] = tb;
+        bd_time[qB] = tb;
         if (tb * 1.5f < ts) skip_r = true;
         else free_blockdense(h, L);
       }
@@ -1562,16 +1568,14 @@ static void tune_sweeps(cpc_solver* h) {
     float best = try_r && !skip_r ? cost() : 0.f;
     // build the sweeps with R rows per block (M segments per block in the one-wave form)
     // in a list of their own; keep them if they are faster, else restore the current ones
-    auto try_build = [&](int R, int M, bool off) {
+    auto try_build = [&](int R, int M) {
       DevSweepSched lo = L.lower, up = L.upper;
       SweepPackDev fg = L.fgs, bg = L.bgs, il = h->ilu_l, iu = h->ilu_u;
       const int oldR = L.sweep_R, oldM = L.wave_M;
-      const bool oldOff = L.wave_off;
       std::vector<void*> old;
       old.swap(L.sweep_owned);
       bool built = true;
       L.wave_M = M;
-      L.wave_off = off;
       const double tb0 = now_s();
       try {
         build_level_sweeps(h, L, sub, R, ilu);
@@ -1603,7 +1607,6 @@ static void tune_sweeps(cpc_solver* h) {
         h->ilu_u = iu;
         L.sweep_R = oldR;
         L.wave_M = oldM;
-        L.wave_off = oldOff;
       }
     };
     if (try_r && !skip_r) {
@@ -1621,7 +1624,7 @@ static void tune_sweeps(cpc_solver* h) {
       if (!try_r || skip_r || tried.count(R) || R >= L.sweep_rows) continue;
       if (R > sweep_max_rows_per_block() && !L.fgs.wave.ok) continue;
       tried.insert(R);
-      try_build(R, L.wave_M, L.wave_off);
+      try_build(R, L.wave_M);
     }
     for (int dir = 0; dir < 2 && try_r && !skip_r; ++dir) {
       for (;;) {
@@ -1630,7 +1633,7 @@ static void tune_sweeps(cpc_solver* h) {
         if (R > sweep_max_rows_per_block() && !L.fgs.wave.ok) break;
         tried.insert(R);
         const int before = L.sweep_R;
-        try_build(R, L.wave_M, L.wave_off);
+        try_build(R, L.wave_M);
         if (L.sweep_R == before) break;
       }
     }
@@ -1639,12 +1642,9 @@ static void tune_sweeps(cpc_solver* h) {
       const int cur = L.fgs.wave.M;
       for (int M : {1, 2, 4})
         if (M != cur && L.sweep_R / M >= 256 && (M == 1 || L.wave_stride >= L.sweep_R / M))
-          try_build(L.sweep_R, M, false);
-      // the four-wave kernel at that block size (wide coarse rows can favour it)
-      if (L.sweep_R <= sweep_max_rows_per_block()) try_build(L.sweep_R, L.wave_M, true);
-      progress(h, "level " + std::to_string(d) + ": " + (L.wave_off ? "four-wave" : "one-wave") + " sweeps, " +
-                      std::to_string(L.sweep_R) + "-row blocks" +
-                      (L.wave_off ? "" : " in " + std::to_string(L.fgs.wave.M) + " segments"));
+          try_build(L.sweep_R, M);
+      progress(h, "level " + std::to_string(d) + ": one-wave sweeps, " + std::to_string(L.sweep_R) +
+                      "-row blocks in " + std::to_string(L.fgs.wave.M) + " segments");
     }
     // block-dense form of the Gauss-Seidel factor, blocks of 2048 / 4096 / 8192 rows
     if (h->opt.dense_smoother == 3 && d + 1 < h->lev.size()) {
