@@ -26,7 +26,6 @@
 #include <rocblas/rocblas.h>
 
 #include <map>
-#include <mutex>
 
 #include <algorithm>
 #include <vector>
@@ -397,15 +396,14 @@ void launch_transpose(hipStream_t s, int n, const void* X, void* Y, bool fp32) {
   else transpose_kernel<double><<<grid, kNT, 0, s>>>(n, (const double*)X, (double*)Y);
 }
 
-// One rocBLAS handle per device, made on first use and kept until the process ends (a
-// block-dense level builds thousands of small inverses; a handle per call costs more
-// than their GEMMs).
+// One rocBLAS handle per host thread and device, made on first use and kept until the
+// process ends (a block-dense level builds thousands of small inverses; a handle per
+// call costs more than their GEMMs). Per thread, so that setups running on several
+// threads never share a handle's stream.
 static rocblas_handle blas_handle(std::string* msg) {
-  static std::mutex mu;
-  static std::map<int, rocblas_handle> handles;
+  static thread_local std::map<int, rocblas_handle> handles;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lock(mu);
   auto it = handles.find(dev);
   if (it != handles.end()) return it->second;
   rocblas_handle hb = nullptr;

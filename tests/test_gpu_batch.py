@@ -144,3 +144,28 @@ def test_batch_fp32_preconditioner():
             print(f"[fp32 batch] system {s}: iters {it[s]} (oracle {r['iters']}), true relres {tr:.2e}, "
                   f"x err {err:.2e}", flush=True)
             assert tr <= 1e-8 * 1.05 and it[s] <= r["iters"] + 1 and err <= 1e-10, (s, tr, it[s], err)
+
+
+def test_batch_zero_rhs_system_stops_at_once():
+    """A system with b = 0 stops before the first iteration (x = 0, no iterations) and is
+    masked out of every preconditioner launch; the others converge as when solved
+    alone."""
+    import paper_1205_6113_amd as cpc
+    probs = gen.config4(sizes=[10, 12, 9])
+    zero = 1
+    bs_all = [p.b.copy() for p in probs]
+    bs_all[zero][:] = 0.0
+    b = torch.as_tensor(np.concatenate(bs_all), device="cuda")
+    with cpc.BatchSolver([(p.n, p.row_ptr, p.col, p.val) for p in probs]) as bsv:
+        x0 = torch.full_like(b, 7.0)  # overwritten: the solve starts from x = 0
+        x, it, rel, st = bsv.solve(b, x=x0, tol=1e-8)
+        assert st == 0
+        xs = x.cpu().numpy()
+        for s, p in enumerate(probs):
+            xo = xs[bsv.offsets[s]:bsv.offsets[s] + p.n]
+            if s == zero:
+                assert it[s] == 0 and np.all(xo == 0.0), (it[s], np.abs(xo).max())
+                continue
+            r = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val).pcg(oracle.PREC_COMBINED, p.b, 1e-8, 1000)
+            assert it[s] == r["iters"], (s, it[s], r["iters"])
+            assert np.linalg.norm(xo - r["x"]) <= 1e-10 * np.linalg.norm(r["x"]), s
