@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C-ABI) with the oracle, on the GPU.
 
-Floating-point bar (the benchmark spec): relative solution error <= 1e-10 in FP64 at a
+Floating-point bar: relative solution error <= 1e-10 in FP64 at a
 fixed iteration count; iteration counts equal (a difference of one is accepted
 only when the oracle's stopping residual lies within 1e-12 relative of the
 tolerance). Integer/structure results (C/F splitting, patterns) and the Galerkin
