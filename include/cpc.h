@@ -317,10 +317,13 @@ cpc_status cpc_setup_batch(int32_t nsys, const int32_t* n, const int32_t* const*
                            const int32_t* const* col_idx, const double* const* val, const cpc_options* opt,
                            void* hip_stream, cpc_handle* out);
 
-/* PCG on every system of a batch handle from x = 0 with the handle's preconditioner.
- * b_dev, x_dev: concatenated device FP64 vectors. iters[nsys], relres[nsys]: host
- * outputs per system (may be NULL). Returns CPC_OK when every system converged,
- * CPC_E_MAXIT when one did not, CPC_E_BREAKDOWN on a breakdown. */
+/* PCG (Algorithm 2.1's preconditioner in each iteration) on every system of a batch
+ * handle from x = 0 with the handle's preconditioner. b_dev, x_dev: concatenated device
+ * FP64 vectors. iters[nsys], relres[nsys]: host outputs per system (may be NULL). A
+ * system stops on its own (tolerance, iteration cap, breakdown or b = 0): its x is kept
+ * and the rest of the solve skips it, the preconditioner's launches included. Returns
+ * CPC_OK when every system converged (or had b = 0), CPC_E_MAXIT when one did not,
+ * CPC_E_BREAKDOWN on a breakdown in any system (the others still converge). */
 cpc_status cpc_solve_batch(cpc_handle h, const double* b_dev, double* x_dev, double tol, int32_t maxit,
                            int32_t* iters, double* relres);
 
