@@ -18,4 +18,4 @@ from .tpfa import (  # noqa: F401
     scaled_config,
     csr_to_dense,
 )
-from .wide import wide_band  # noqa: F401,E402
+from .wide import hub_chain, wide_band  # noqa: F401,E402

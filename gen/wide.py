@@ -41,3 +41,48 @@ def wide_band(n: int = 12000, band: int = 160, density: float = 0.6, shift: floa
     return Problem(name=f"chain-{n}-band{band}-{density}", n=n, row_ptr=rp.astype(np.int32), col=cols.astype(np.int32),
                    val=np.ascontiguousarray(val), b=b, tol=1e-8, dims=(n, 1, 1), logk=np.zeros((1, 1, n)),
                    kz_ratio=1.0, dirichlet_x=False)
+
+
+def hub_chain(nc: int = 8400, seed: int = 3) -> Problem:
+    """A chain of nc unknowns, every one weakly coupled to a hub (unknown 0) that is
+    itself strongly coupled to an anchor (unknown 1); chain unknown i is 2 + i.
+
+    With numpy.random.default_rng(seed): chain couplings uniform on [0.5, 1.5), hub
+    couplings uniform on [0.05, 0.1), then diagonal shifts uniform on [0.01, 0.1) added
+    to the negated row sums; anchor coupling 100. The hub row holds every chain unknown,
+    so the Galerkin products of the hub's row (and, one level down, of the coarse hub)
+    have more than nc / 2 distinct columns: a well column seen by a whole reservoir
+    layer. Nothing here solves anything."""
+    rng = np.random.default_rng(seed)
+    n = nc + 2
+    cw = rng.uniform(0.5, 1.5, nc - 1)
+    hw = rng.uniform(0.05, 0.1, nc)
+    rows, cols, w = [], [], []
+    for i in range(nc - 1):
+        rows.append(2 + i)
+        cols.append(3 + i)
+        w.append(cw[i])
+    for i in range(nc):
+        rows.append(0)
+        cols.append(2 + i)
+        w.append(hw[i])
+    rows.append(0)
+    cols.append(1)
+    w.append(100.0)
+    rows, cols, w = np.array(rows), np.array(cols), np.array(w)
+    r = np.concatenate([rows, cols])
+    c = np.concatenate([cols, rows])
+    v = -np.concatenate([w, w])
+    rs = np.bincount(r, weights=-v, minlength=n)
+    diag = rs + rng.uniform(0.01, 0.1, n)
+    r = np.concatenate([r, np.arange(n)])
+    c = np.concatenate([c, np.arange(n)])
+    v = np.concatenate([v, diag])
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(r, minlength=n), out=rp[1:])
+    b = np.random.default_rng(seed + 100).standard_normal(n)
+    return Problem(name=f"hub-chain-{nc}", n=n, row_ptr=rp.astype(np.int32), col=c.astype(np.int32),
+                   val=np.ascontiguousarray(v), b=b, tol=1e-8, dims=(n, 1, 1), logk=np.zeros((1, 1, n)),
+                   kz_ratio=1.0, dirichlet_x=False)

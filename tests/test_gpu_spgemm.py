@@ -87,3 +87,33 @@ def test_wide_rows_beside_narrow_ones():
             xr.append(sorted(rng.choice(ninner, 8, replace=False).tolist()))
     lens = check(csr(xr, ninner, rng), y, ncols)
     assert (lens >= CAP).sum() >= 72 and (lens == CAP - 1).sum() >= 1
+
+
+def test_hierarchy_with_wide_galerkin_rows():
+    """A chain whose every unknown couples to one hub (a well column seen by a whole
+    layer): the hub's rows of A P and of the coarse matrix hold more columns than the
+    LDS table, so the setup's Galerkin products take the wide-row path. The hierarchy
+    (C/F splitting, P, every A_l) is bit-identical to the oracle's and PCG matches it."""
+    import gen
+    import oracle
+    import torch
+    import paper_1205_6113_amd as cpc
+    p = gen.hub_chain()
+    h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
+    rp1, _, _ = h.level(1)
+    assert np.diff(rp1).max() > CAP
+    ro = h.pcg(oracle.PREC_COMBINED, p.b, p.tol, 1000)
+    with cpc.Solver(p.n, p.row_ptr, p.col, p.val) as s:
+        assert s.hierarchy()["nlev"] == h.nlev
+        for d in range(h.nlev):
+            rp, ci, v = s.level(d)
+            orp, oci, ov = h.level(d)
+            assert np.array_equal(rp, orp) and np.array_equal(ci, oci) and np.array_equal(v, ov), d
+            if d + 1 < h.nlev:
+                prp, pci, pv, cf = s.prolongation(d)
+                q = h.prolongation(d)
+                assert np.array_equal(cf, h.cf(d)) and np.array_equal(prp, q[0]) and np.array_equal(pci, q[1])
+                assert np.array_equal(pv, q[2]), d
+        x, it, rel, st = s.solve(torch.as_tensor(p.b, device="cuda"), tol=p.tol)
+        assert st == 0 and it == ro["iters"], (it, ro["iters"])
+        assert np.linalg.norm(x.cpu().numpy() - ro["x"]) <= 1e-10 * np.linalg.norm(ro["x"])
