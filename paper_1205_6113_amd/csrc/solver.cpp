@@ -973,7 +973,31 @@ static int build_sys_hier(cpc_solver* h, SysHier& S, const cpc_options& o, std::
 // row products address one system's inverse with 32-bit byte offsets, which holds up to
 // 16384 rows (2 GiB in FP64); diagonal blocks of the block form obey the same limit.
 static constexpr int kDenseMaxRows = 16384;
-static constexpr double kBlockDenseMaxBytes = 32e9;  // the block form's inverses and transposes
+// Device memory one level's block form (inverses and their transposes) may take: at
+// most 96 GB and 60 % of what is free when it is built (a level of 1.4 M rows in
+// 4096-row blocks on an MI355X's 288 GB; later levels see what earlier ones left).
+static double blockdense_cap() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 32e9;
+  }
+  return std::min(96e9, 0.6 * (double)free_b);
+}
+
+// Bytes of the block form with B-row blocks over the row ranges `parts` (each cut on
+// its own, the last block of a range short): 8 per inverse entry, inverse and
+// transpose. One forward plus one backward solve reads all of them once, so at the
+// HBM peak of 8 TB/s that pair takes at least bytes / 8e12 seconds.
+static double blockdense_bytes(const std::vector<int>& parts, int B) {
+  double bytes = 0.0;
+  for (size_t p = 0; p + 1 < parts.size(); ++p) {
+    const double s = parts[p + 1] - parts[p];
+    const double full = std::floor(s / B), tail = s - full * B;
+    bytes += 16.0 * (full * B * (double)B + tail * tail);
+  }
+  return bytes;
+}
 static constexpr double kDenseMaxBytes = 64e9;
 static constexpr int kDenseTransRows = 16384;
 
@@ -1294,7 +1318,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   const int K = bd.nblk();
   double bytes = 0.0;
   for (int b = 0; b < K; ++b) bytes += 16.0 * bd.rows[b] * (double)bd.rows[b];
-  if (bytes > kBlockDenseMaxBytes) return false;
+  if (bytes > blockdense_cap()) return false;
   // entries outside each row's block, rows in step order (forward: left of the block;
   // backward: right of it)
   HostCsr lo, up;
@@ -1549,11 +1573,22 @@ static void tune_sweeps(cpc_solver* h) {
     // inverses would not fit the form's memory bound (batch levels of a million rows).
     std::map<int, float> bd_time;  // measured block-substitution candidates
     bool skip_r = false;
+    const std::vector<int> lparts = (!L.parts.empty() && L.parts.front() == 0 && L.parts.back() == L.sweep_rows)
+                                        ? L.parts
+                                        : std::vector<int>{0, L.sweep_rows};
+    // lower bound (ms) of one forward + backward block solve: its inverses read at the HBM peak
+    auto bd_floor = [&](int B) { return (float)(blockdense_bytes(lparts, B) / 8e12 * 1e3); };
     int qB = 4096;
-    while (qB > 1024 && 16.0 * (double)L.sweep_rows * qB > kBlockDenseMaxBytes) qB /= 2;
-    if (try_r && bd_ok && !L.dense_smooth && qB < L.sweep_rows &&
-        16.0 * (double)L.sweep_rows * qB <= kBlockDenseMaxBytes) {
-      const float ts = gs_cost();
+    const double cap = blockdense_cap();
+    float ts = 0.f;
+    if (try_r && bd_ok && !L.dense_smooth) {
+      ts = gs_cost();
+      // the look decides only when the form is 1.5x ahead: a block size whose inverses
+      // alone take longer to read than ts / 1.5 cannot do that
+      while (qB > 1024 && (blockdense_bytes(lparts, qB) > cap || 1.5f * bd_floor(qB) >= ts)) qB /= 2;
+    }
+    if (try_r && bd_ok && !L.dense_smooth && qB < L.sweep_rows && blockdense_bytes(lparts, qB) <= cap &&
+        1.5f * bd_floor(qB) < ts) {
       progress(h, "level " + std::to_string(d) + ": block substitution with " + std::to_string(qB) + "-row blocks");
       if (build_blockdense(h, L, sub, qB)) {
         L.bdense = true;
@@ -1687,6 +1722,8 @@ static void tune_sweeps(cpc_solver* h) {
       for (int B : {4096, 2048, 8192, 1024}) {
         if (B >= L.sweep_rows) continue;
         if (L.bdense && L.bd.B == B) continue;  // kept from the quick look
+        if (!(bd_floor(B) < gbest)) continue;   // reading its inverses alone takes longer
+        if (bd_time.count(B) && !(bd_time[B] < gbest)) continue;  // timed in the quick look
         if ((B == 8192 || B == 1024) && bd_time.count(2048) && bd_time.count(4096)) {
           const double t2 = bd_time[2048], t4 = bd_time[4096];
           const double c = (2.0 * t4 - t2) / (2.0 * 4096.0 - 2048.0);  // from t2 = a/2048 + 2048c, t4 = a/4096 + 4096c
