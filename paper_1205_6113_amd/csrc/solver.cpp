@@ -1650,7 +1650,7 @@ static void tune_sweeps(cpc_solver* h) {
                     L.fgs.wave.ok ? "one-wave" : "four-wave", best);
       progress(h, buf);
     }
-    // block sizes 256 .. 16384 (above 8192: one-wave form only): 1024 and 4096 first,
+    // block sizes 64 .. 16384 (below 256 and above 8192: one-wave form only): 1024 and 4096 first,
     // then doubling and halving from the better of those for as long as each step
     // gains (the measured times fall and then rise with the block size, with noise that
     // a walk from a single start can stop on)
@@ -1664,8 +1664,8 @@ static void tune_sweeps(cpc_solver* h) {
     for (int dir = 0; dir < 2 && try_r && !skip_r; ++dir) {
       for (;;) {
         const int R = dir == 0 ? L.sweep_R * 2 : L.sweep_R / 2;
-        if (R < 256 || R > 16384 || R >= L.sweep_rows || tried.count(R)) break;
-        if (R > sweep_max_rows_per_block() && !L.fgs.wave.ok) break;
+        if (R < 64 || R > 16384 || R >= L.sweep_rows || tried.count(R)) break;
+        if ((R > sweep_max_rows_per_block() || R < 256) && !L.fgs.wave.ok) break;
         tried.insert(R);
         const int before = L.sweep_R;
         try_build(R, L.wave_M);
