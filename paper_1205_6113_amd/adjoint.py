@@ -74,14 +74,22 @@ class TpfaGrid:
 
 class _TpfaSolveFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, logk, b, grid: TpfaGrid, tol: float, maxit: int, opts: dict):
-        val = grid.values(logk)
-        torch.cuda.current_stream(logk.device).synchronize()
-        solver = Solver(grid.n, grid.row_ptr, grid.col, val.cpu().numpy(), device=logk.device, **opts)
-        x, it, rel, st = solver.solve(b.detach().contiguous(), tol=tol, maxit=maxit)
+    def forward(ctx, logk, b, grid: TpfaGrid, tol: float, maxit: int, opts: dict, setup):
+        if setup is not None:
+            # the caller's preconditioner, built for a nearby log k; PCG runs on A(log k)
+            x, it, rel, st = setup.solve(logk.detach(), b.detach().contiguous(), tol=tol, maxit=maxit)
+            solver = None
+        else:
+            val = grid.values(logk)
+            torch.cuda.current_stream(logk.device).synchronize()
+            solver = Solver(grid.n, grid.row_ptr, grid.col, val.cpu().numpy(), device=logk.device, **opts)
+            x, it, rel, st = solver.solve(b.detach().contiguous(), tol=tol, maxit=maxit)
         if st != _lib.CPC_OK:
+            if solver is not None:
+                solver.close()
             raise _lib.CpcError(st, f"forward solve did not converge (iters {it}, relres {rel:.3e})")
         ctx.solver = solver
+        ctx.setup = setup
         ctx.grid = grid
         ctx.tol = tol
         ctx.maxit = maxit
@@ -92,25 +100,39 @@ class _TpfaSolveFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gx):
         logk, x = ctx.saved_tensors
-        solver = ctx.solver
-        lam, it, rel, st = solver.solve(gx.detach().contiguous(), tol=ctx.tol, maxit=ctx.maxit)
+        if ctx.setup is not None:
+            lam, it, rel, st = ctx.setup.solve(logk, gx.detach().contiguous(), tol=ctx.tol, maxit=ctx.maxit)
+        else:
+            lam, it, rel, st = ctx.solver.solve(gx.detach().contiguous(), tol=ctx.tol, maxit=ctx.maxit)
+            ctx.solver.close()
         if st != _lib.CPC_OK:
             raise _lib.CpcError(st, f"adjoint solve did not converge (iters {it}, relres {rel:.3e})")
         grad_logk = ctx.grid.logk_grad(logk, lam, x) if ctx.needs_input_grad[0] else None
         grad_b = lam if ctx.needs_input_grad[1] else None
-        solver.close()
-        return grad_logk, grad_b, None, None, None, None
+        return grad_logk, grad_b, None, None, None, None, None
 
 
 def tpfa_solve(logk: torch.Tensor, b: torch.Tensor, grid: TpfaGrid, tol: float = 1e-10, maxit: int = 10000,
-               **opts) -> torch.Tensor:
-    """x = A(log k)^{-1} b, differentiable with respect to log k and b."""
-    return _TpfaSolveFn.apply(logk, b, grid, tol, maxit, opts)
+               setup: "FrozenPreconditionerSolve | None" = None, **opts) -> torch.Tensor:
+    """x = A(log k)^{-1} b, differentiable with respect to log k and b.
+
+    Without `setup` every call builds the preconditioner for A(log k) (cpc_setup) and
+    frees it after the backward pass. With `setup`, a FrozenPreconditionerSolve built
+    for a nearby log k0 on the same grid, the forward and the adjoint PCG run on
+    A(log k) with the preconditioner of A(log k0): no setup per call. The solution and
+    the gradient are those of A(log k) to the tolerance; only the iteration count
+    depends on how far log k is from log k0.
+    """
+    if setup is not None and setup.grid is not grid:
+        raise ValueError("setup was built on another grid")
+    return _TpfaSolveFn.apply(logk, b, grid, tol, maxit, opts, setup)
 
 
 class FrozenPreconditionerSolve:
     """Solves with matrices A(log k') near A(log k) while keeping the preconditioner
-    built for A(log k) (cpc_set_operator_values): for finite-difference checks."""
+    built for A(log k) (cpc_set_operator_values): for finite-difference checks, and as
+    the `setup` of tpfa_solve, so that a sequence of differentiable solves at nearby
+    log k (an optimisation loop) sets up once."""
 
     def __init__(self, logk: torch.Tensor, grid: TpfaGrid, **opts):
         self.grid = grid

@@ -1,5 +1,7 @@
 """Differentiable solve (adjoint) on the GPU against the oracle gradient and central
 finite differences."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -86,6 +88,58 @@ def test_gradient_matches_oracle_and_fd(scale):
         g_fd = (vals[0] - vals[1]) / 2e-3
         assert abs(g_fd - g_b[c]) <= 1e-6 * max(abs(g_b[c]), 1e-3 * np.abs(g_b).max())
     fz.close()
+
+
+def test_gradient_with_reused_setup():
+    """A sequence of differentiable solves at log k0 + small steps, all with the
+    preconditioner set up once at log k0: each loss and gradient equals that of a fresh
+    setup at its own log k (the oracle's at the last step) to the solve tolerance."""
+    adj = _mods()
+    p = _problem(0.25)
+    dev = torch.device("cuda")
+    nx, ny, nz = p.dims
+    grid = adj.TpfaGrid(nx, ny, nz, p.kz_ratio, p.dirichlet_x)
+    lk0 = torch.as_tensor(p.logk.ravel(), device=dev)
+    b = torch.as_tensor(p.b, device=dev)
+    loss_fn = _loss_fn(p, dev)
+    fz = adj.FrozenPreconditionerSolve(lk0, grid)
+    rng = np.random.default_rng(11)
+    try:
+        for step in range(3):
+            dlk = torch.as_tensor(0.02 * (step + 1) * rng.standard_normal(p.n), device=dev)
+            lk_r = (lk0 + dlk).requires_grad_(True)
+            L_r = loss_fn(adj.tpfa_solve(lk_r, b, grid, tol=1e-12, setup=fz))
+            L_r.backward()
+            lk_f = (lk0 + dlk).requires_grad_(True)
+            L_f = loss_fn(adj.tpfa_solve(lk_f, b, grid, tol=1e-12))
+            L_f.backward()
+            assert abs(L_r.item() - L_f.item()) <= 1e-9 * abs(L_f.item())
+            gr, gf = lk_r.grad.cpu().numpy(), lk_f.grad.cpu().numpy()
+            assert np.linalg.norm(gr - gf) <= 1e-8 * np.linalg.norm(gf), step
+        # the last step against the oracle's gradient at that log k (matrix from the generator)
+        lk = (lk0 + dlk).cpu().numpy().reshape(p.logk.shape)
+        rp, ci, val, keep = gen.tpfa_system(lk, p.kz_ratio, p.dirichlet_x)
+        assert np.array_equal(rp, p.row_ptr) and np.array_equal(ci, p.col)
+        q = dataclasses.replace(p, logk=lk, val=val)
+        ref = oracle.misfit_gradient(q, oracle.Hierarchy(q.n, q.row_ptr, q.col, q.val), tol=1e-12)
+        assert abs(L_r.item() - ref["loss"]) <= 1e-9 * abs(ref["loss"])
+        assert np.linalg.norm(gr - ref["grad_logk"]) <= 1e-8 * np.linalg.norm(ref["grad_logk"])
+    finally:
+        fz.close()
+
+
+def test_reused_setup_rejects_another_grid():
+    adj = _mods()
+    dev = torch.device("cuda")
+    g1 = adj.TpfaGrid(4, 4, 2)
+    g2 = adj.TpfaGrid(4, 4, 2)
+    lk = torch.zeros(g1.n, device=dev, dtype=torch.float64)
+    fz = adj.FrozenPreconditionerSolve(lk, g1)
+    try:
+        with pytest.raises(ValueError):
+            adj.tpfa_solve(lk, torch.ones(g1.n, device=dev, dtype=torch.float64), g2, setup=fz)
+    finally:
+        fz.close()
 
 
 def test_two_cell_closed_form():
