@@ -35,6 +35,7 @@ SOURCES = [
     ("rap.hip", "hip", ["-ffp-contract=off"]),
     ("tpfa.hip", "hip", ["-ffp-contract=off"]),
     ("dense_tri.hip", "hip", []),
+    ("dense_gemm.hip", "hip", []),
     ("noalloc.hip", "hip", []),
     ("host_setup.cpp", "gxx", ["-ffp-contract=off"]),
     ("solver.cpp", "hiphost", []),
@@ -76,7 +77,7 @@ def build(verbose: bool = False) -> Path:
         msg = "\n".join(f"--- {n}\n{t}" for n, t in failed)
         raise RuntimeError(f"build failed:\n{msg}")
     tmp = LIB.with_suffix(".so.tmp")
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", str(tmp), *map(str, objs), "-lrocblas"]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", str(tmp), *map(str, objs)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -13,8 +13,9 @@
 // row-major array; the 128 x 128 diagonal blocks are inverted in place by
 // substitution in LDS; then, for spans of 128, 256, 512, ... rows, each pair of
 // adjacent inverted spans [a, a+s) and [a+s, b) gets its off-diagonal block
-// B <- -C^{-1} B A^{-1} from two matrix products (library GEMMs), where A^{-1}, C^{-1}
-// are the inverted diagonal spans. The result is T^{-1}, lower triangular.
+// B <- -C^{-1} B A^{-1} from two matrix products (FP64 on the matrix cores,
+// dense_gemm.hip), where A^{-1}, C^{-1} are the inverted diagonal spans. The result is
+// T^{-1}, lower triangular.
 //
 // Products: y = T^{-1} f by one workgroup per eight rows, four from each end of the
 // system (coalesced row reads, the vector from L2). y = T^{-T} g: on smaller systems from a stored transpose, row by row like the
@@ -23,9 +24,6 @@
 // (deterministic), which reads each stored entry once without a second copy.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
-
-#include <map>
 
 #include <algorithm>
 #include <vector>
@@ -396,56 +394,30 @@ void launch_transpose(hipStream_t s, int n, const void* X, void* Y, bool fp32) {
   else transpose_kernel<double><<<grid, kNT, 0, s>>>(n, (const double*)X, (double*)Y);
 }
 
-// One rocBLAS handle per host thread and device, made on first use and kept until the
-// process ends (a block-dense level builds thousands of small inverses; a handle per
-// call costs more than their GEMMs). Per thread, so that setups running on several
-// threads never share a handle's stream.
-static rocblas_handle blas_handle(std::string* msg) {
-  static thread_local std::map<int, rocblas_handle> handles;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  auto it = handles.find(dev);
-  if (it != handles.end()) return it->second;
-  rocblas_handle hb = nullptr;
-  if (rocblas_create_handle(&hb) != rocblas_status_success) {
-    if (msg) *msg = "rocblas_create_handle failed";
-    return nullptr;
-  }
-  handles[dev] = hb;
-  return hb;
-}
-
 bool dense_tri_inverse(hipStream_t s, int n, int voff, const int* rp, const int* ci, const double* v, double* M,
                        double* work, std::string* msg) {
-  rocblas_handle hb = blas_handle(msg);
-  if (!hb) return false;
-  bool ok = rocblas_set_stream(hb, s) == rocblas_status_success;
   const long ld = dense_ld(n);
-  if (ok && hipMemsetAsync(M, 0, sizeof(double) * (size_t)n * ld, s) != hipSuccess) ok = false;
+  bool ok = hipMemsetAsync(M, 0, sizeof(double) * (size_t)n * ld, s) == hipSuccess;
   if (ok) {
     scatter_lower_kernel<<<std::min((n + kNT - 1) / kNT, 1024), kNT, 0, s>>>(n, voff, rp, ci, v, M);
     leaf_inverse_kernel<<<(n + kLeaf - 1) / kLeaf, kLeaf, 0, s>>>(n, M);
     ok = hipGetLastError() == hipSuccess;
   }
-  // merge inverted spans: rows/columns [a, a+sp) (A) and [a+sp, e) (C), off-diagonal
-  // block B = M[a+sp:e, a:a+sp]; row-major X is column-major X^T, so the row-major
-  // product W = B A^{-1} is the column-major W^T = A^{-T} B^T
-  const double one = 1.0, zero = 0.0, mone = -1.0;
+  // merge inverted spans, all pairs of one span length in one launch per product: pair z
+  // starts at row a = 2 sp z; A = rows/columns [a, a+sp), C = [a+sp, e), off-diagonal
+  // block B = M[a+sp:e, a:a+sp]; W = B A^{-1} into work (pair z at z sp^2, row stride
+  // sp), then B = -C^{-1} W. Only the last pair can be shorter (e = n).
   for (int sp = kLeaf; ok && sp < n; sp *= 2) {
-    for (int a = 0; ok && a + sp < n; a += 2 * sp) {
-      const int e = std::min(a + 2 * sp, n);
-      const int m1 = sp, m2 = e - a - sp;
-      double* Ai = M + a * ld + a;
-      double* B = M + (a + sp) * ld + a;
-      double* Ci = M + (a + sp) * ld + a + sp;
-      // W (m2 x m1, row-major, ld m1) = B A^{-1}
-      ok = rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m1, m2, m1, &one, Ai, (int)ld, B, (int)ld, &zero,
-                         work, m1) == rocblas_status_success;
-      // B = -C^{-1} W
-      if (ok)
-        ok = rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m1, m2, m2, &mone, work, m1, Ci, (int)ld,
-                           &zero, B, (int)ld) == rocblas_status_success;
-    }
+    const int nm = (n - sp + 2 * sp - 1) / (2 * sp);  // pairs: a + sp < n
+    const int a_last = (nm - 1) * 2 * sp;
+    const int m2_last = std::min(a_last + 2 * sp, n) - a_last - sp;
+    const int m2 = nm > 1 ? sp : m2_last;
+    const long stride = 2L * sp * (ld + 1);
+    double* B0 = M + (long)sp * ld;
+    ok = launch_dgemm_batched(s, B0, stride, (int)ld, M, stride, (int)ld, work, (long)sp * sp, sp, m2, m2_last, sp,
+                              sp, sp, nm, 1.0);
+    ok = ok && launch_dgemm_batched(s, B0 + sp, stride, (int)ld, work, (long)sp * sp, sp, B0, stride, (int)ld, m2,
+                                    m2_last, m2, m2_last, sp, nm, -1.0);
   }
   if (!ok && msg && msg->empty()) *msg = "dense triangular inverse failed";
   return ok;

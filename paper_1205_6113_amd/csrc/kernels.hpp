@@ -239,6 +239,14 @@ void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool x
 void launch_dense_lower_t(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* g, void* y,
                           const int* done, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_to_type(hipStream_t s, long n, const double* a, void* y, bool fp32);
+// O[z] = alpha * L[z] R[z] (FP64, row-major, matrix cores) for z < nb: L[z] rows x inner
+// (row stride ldl), R[z] inner x cols (ldr), O[z] rows x cols (ldo); entry z's operands
+// start z * sl, z * sr, z * so elements after entry 0's; the last entry has rows_last
+// rows and inner_last inner indices. O[z] must not overlap any operand. Returns false
+// on invalid sizes or a failed launch (dense_gemm.hip).
+bool launch_dgemm_batched(hipStream_t s, const double* L, long sl, int ldl, const double* R, long sr, int ldr,
+                          double* O, long so, int ldo, int rows, int rows_last, int inner, int inner_last, int cols,
+                          int nb, double alpha);
 void launch_transpose(hipStream_t s, int n, const void* X, void* Y, bool fp32);
 
 // Persistent block-pipelined triangular solve over packed rows (sweep.hip). x must

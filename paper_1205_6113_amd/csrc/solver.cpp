@@ -1001,10 +1001,15 @@ static double blockdense_bytes(const std::vector<int>& parts, int B) {
 static constexpr double kDenseMaxBytes = 64e9;
 static constexpr int kDenseTransRows = 16384;
 
+// Scratch of dense_tri_inverse for n rows: the products W = B A^{-1} of all pairs of
+// one span length at once (sp x sp each, the last pair's rows fewer).
 static long dense_work_need(int n) {
   long w = 1;
-  for (int sp = 128; sp < n; sp *= 2)
-    for (int a = 0; a + sp < n; a += 2 * sp) w = std::max(w, (long)sp * (std::min(a + 2 * sp, n) - a - sp));
+  for (int sp = 128; sp < n; sp *= 2) {
+    long t = 0;
+    for (int a = 0; a + sp < n; a += 2 * sp) t += (long)sp * (std::min(a + 2 * sp, n) - a - sp);
+    w = std::max(w, t);
+  }
   return w;
 }
 
