@@ -521,6 +521,9 @@ def main():
                    "levels": info["nlev"], "level_n": info["n"], "level_nnz": info["nnz"],
                    "level_depth": info["depth"], "level_smoother": info["smoother"],
                    "level_block_rows": info["block_rows"],
+                   "level_inverse_bytes": info["inverse_bytes"],
+                   "inverse_bytes_total": int(sum(info["inverse_bytes"])),
+                   "matrix_bytes_total": int(sum(12 * z + 4 * (m + 1) for m, z in zip(info["n"], info["nnz"]))),
                    "method_bytes_per_solve": method_solve, "form_bytes_per_solve": form_solve,
                    "precision": args.precision},
         "roofline": roofline,

@@ -197,10 +197,18 @@ cpc_status cpc_hierarchy_info(cpc_handle h, int32_t* nlev, int32_t* n_l, int64_t
 /* How the Gauss-Seidel smoother of Algorithm 3.2 is applied on level `level`:
  * *kind = 0 level-scheduled triangular sweeps, 1 products with the explicit inverse of
  * D+L (forward sweep) and its transpose (backward sweep, D+U = (D+L)^T for symmetric
- * A), -1 the level is not smoothed (coarsest). *block_rows (may be null): rows per
- * workgroup block of the level's sweep schedules (also used by ILU(0) on level 0).
- * CPC_E_ARG for a level out of range. */
+ * A), 2 block substitution with explicit inverses of the diagonal blocks of D+L, -1 the
+ * level is not smoothed (coarsest). *block_rows (may be null): rows per workgroup block
+ * of the level's sweep schedules (also used by ILU(0) on level 0), or per diagonal block
+ * of the block substitution. CPC_E_ARG for a level out of range. */
 cpc_status cpc_smoother_kind(cpc_handle h, int32_t level, int32_t* kind, int32_t* block_rows);
+
+/* Device memory (bytes) that the explicit inverses of level `level`'s Gauss-Seidel
+ * smoother take (same passage as cpc_smoother_kind): the inverse of D+L and its stored
+ * transpose, or the diagonal-block inverses and their transposes (kind 1 or 2, row
+ * stride padded as the products read it, FP32 with CPC_FP32_PRECOND); 0 for sweeps and
+ * for the coarsest level. CPC_E_ARG for a null pointer or a level out of range. */
+cpc_status cpc_smoother_bytes(cpc_handle h, int32_t level, int64_t* bytes);
 
 /* Copy level `level`'s matrix A_l to host CSR arrays (row_ptr[n_l+1], col_idx and
  * val of nnz_l entries). */

@@ -25,7 +25,7 @@ EXPORTS = ("cpc_default_options", "cpc_setup", "cpc_solve", "cpc_solve_with", "c
            "cpc_hierarchy_info", "cpc_get_level", "cpc_get_prolongation", "cpc_get_ilu", "cpc_get_stats",
            "cpc_neg_outer_on_pattern", "cpc_time_kernel", "cpc_destroy", "cpc_last_error", "cpc_tpfa_pattern",
            "cpc_tpfa_values", "cpc_tpfa_logk_grad", "cpc_set_operator_values", "cpc_setup_batch",
-           "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind", "cpc_get_ilu_factor", "cpc_solve_noalloc",
+           "cpc_solve_batch", "cpc_batch_info", "cpc_smoother_kind", "cpc_smoother_bytes", "cpc_get_ilu_factor", "cpc_solve_noalloc",
            "cpc_spgemm")
 KERNEL = {"spmv_pq": 0, "fgs": 1, "bgs": 2, "ilu_l": 3, "ilu_u": 4, "residual": 5, "restrict": 6, "prolong": 7,
           "vcycle": 8, "precond": 9, "iteration": 10, "dense_gemv": 11, "sweep": 12}
@@ -88,6 +88,8 @@ def load():
     lib.cpc_hierarchy_info.restype = I32
     lib.cpc_smoother_kind.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     lib.cpc_smoother_kind.restype = I32
+    lib.cpc_smoother_bytes.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int64)]
+    lib.cpc_smoother_bytes.restype = I32
     lib.cpc_get_level.argtypes = [P, I32, P, P, P]
     lib.cpc_get_level.restype = I32
     lib.cpc_get_prolongation.argtypes = [P, I32, ctypes.POINTER(ctypes.c_int64), P, P, P, P]

@@ -131,6 +131,7 @@ struct BlockDense {
   const int* Lrid = nullptr;       // level row of each row of Loff / Uoff (device)
   const int* Urid = nullptr;
   double entries = 0.0;            // stored inverse entries (byte model)
+  double stored_bytes = 0.0;       // device bytes of the inverses and their transposes
   std::vector<void*> owned;
   int nblk() const { return (int)start.size(); }
 };
@@ -158,6 +159,7 @@ struct Level {
   void* t = nullptr;  // right-hand side of the backward sweep
   // explicit inverses of D+L of the smoothed systems, where they are faster than sweeps
   DenseTriDev dtri{};
+  double dense_bytes = 0.0;  // device bytes of those inverses (and transposes)
   void* dense_M = nullptr;     // held here until the setup tuner keeps or drops it
   void* dense_MT = nullptr;    // its transpose (small systems), same ownership
   std::vector<void*> dense_owned;  // the kept inverse (and transpose)
@@ -1114,6 +1116,7 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
   }
   L.dense_M = M;
   L.dense_entries = ent;
+  L.dense_bytes = (double)(h->f32 ? sizeof(float) : sizeof(double)) * (double)tot * (dt.MT ? 2.0 : 1.0);
 }
 
 // Iterations to launch before the next read of the convergence state when no fixed
@@ -1408,6 +1411,7 @@ static bool build_blockdense(cpc_solver* h, Level& L, const HostCsr& sub, int B)
   if (hipMemsetAsync(MT, 0, es * tot, h->stream) != hipSuccess) return drop();  // zero padding columns
   for (int b = 0; b < K; ++b)
     launch_transpose(h->stream, bd.rows[b], (const char*)M + es * bd.moff[b], (char*)MT + es * bd.moff[b], h->f32);
+  bd.stored_bytes = 2.0 * (double)es * (double)tot;
   // row items of each step, the forward steps' and the backward steps' in lists of their own
   std::vector<int4> itf, itb;
   bd.fitem.push_back(0);
@@ -3033,6 +3037,16 @@ cpc_status cpc_smoother_kind(cpc_handle h, int32_t level, int32_t* kind, int32_t
   if (L.nS <= 0 || level + 1 == (int32_t)h->lev.size()) *kind = -1;
   else *kind = L.dense_smooth ? 1 : (L.bdense ? 2 : 0);
   if (block_rows && L.bdense) *block_rows = L.bd.B;
+  return CPC_OK;
+}
+
+cpc_status cpc_smoother_bytes(cpc_handle h, int32_t level, int64_t* bytes) {
+  if (!h || !bytes) return set_err(CPC_E_ARG, "null argument");
+  if (level < 0 || level >= (int32_t)h->lev.size()) return set_err(CPC_E_ARG, "level out of range");
+  const Level& L = h->lev[level];
+  double b = 0.0;
+  if (L.nS > 0 && level + 1 < (int32_t)h->lev.size()) b = L.bdense ? L.bd.stored_bytes : (L.dense_smooth ? L.dense_bytes : 0.0);
+  *bytes = (int64_t)b;
   return CPC_OK;
 }
 

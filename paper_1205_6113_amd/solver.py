@@ -171,15 +171,18 @@ class Solver:
         depth = np.zeros(cap, np.int32)
         check(self._lib.cpc_hierarchy_info(self._h, ctypes.byref(nlev), _ptr(n_l), _ptr(nnz_l), _ptr(depth)))
         k = nlev.value
-        kinds, rows = [], []
+        kinds, rows, inv_bytes = [], [], []
         for d in range(k):
             kind = ctypes.c_int32(0)
             br = ctypes.c_int32(0)
+            nb = ctypes.c_int64(0)
             check(self._lib.cpc_smoother_kind(self._h, d, ctypes.byref(kind), ctypes.byref(br)))
+            check(self._lib.cpc_smoother_bytes(self._h, d, ctypes.byref(nb)))
             kinds.append({-1: "none", 0: "sweep", 1: "dense", 2: "block"}[kind.value])
             rows.append(br.value)
+            inv_bytes.append(nb.value)
         return {"nlev": k, "n": n_l[:k].tolist(), "nnz": nnz_l[:k].tolist(), "depth": depth[:k].tolist(),
-                "smoother": kinds, "block_rows": rows}
+                "smoother": kinds, "block_rows": rows, "inverse_bytes": inv_bytes}
 
     def level(self, level: int):
         info = self.hierarchy()

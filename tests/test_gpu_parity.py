@@ -264,14 +264,31 @@ def test_neg_outer_on_pattern(cases):
     assert np.array_equal(g, -lam[rows] * x[p.col])
 
 
+def _dense_ld(n):
+    ld = (n + 3) & ~3
+    return ld + 8 if ld % 512 == 0 else ld
+
+
 def test_smoother_kinds_follow_the_option(cases):
     """Levels of at most 16384 rows are smoothed through explicit inverses exactly when
-    asked ("always"); never when told not to; the coarsest level is not smoothed."""
+    asked ("always"); never when told not to; the coarsest level is not smoothed. The
+    inverses' reported device memory is that of the stored FP64 squares (padded row
+    stride) and their transposes, zero for sweeps."""
     for k, (p, R, dense, _) in small_cases().items():
         info = cases[k][2].hierarchy()
         kinds = info["smoother"]
         assert kinds[-1] == "none", k
+        assert info["inverse_bytes"][-1] == 0, k
         for d in range(info["nlev"] - 1):
+            n = info["n"][d]
+            if kinds[d] == "sweep":
+                assert info["inverse_bytes"][d] == 0, (k, d)
+            elif kinds[d] == "dense":
+                assert info["inverse_bytes"][d] == 2 * 8 * n * _dense_ld(n), (k, d)
+            else:
+                B = info["block_rows"][d]
+                sizes = [B] * (n // B) + ([n % B] if n % B else [])
+                assert info["inverse_bytes"][d] == sum(2 * 8 * m * _dense_ld(m) for m in sizes), (k, d)
             if dense == "never":
                 assert kinds[d] == "sweep", (k, d)
             elif dense == "always":
