@@ -232,6 +232,54 @@ def test_single_unknown_and_one_level():
         assert relerr(x.cpu().numpy(), xr) <= 1e-12
 
 
+def test_diagonal_and_disconnected_systems():
+    """Degenerate inputs of the coarsening: a diagonal matrix (no couplings, so Gauss-
+    Seidel and ILU(0) are exact and B_co = A^{-1}: one iteration) and a matrix of
+    disconnected two-point-flux blocks; hierarchy sizes, iterations and x against the
+    oracle."""
+    cpc = _cpc()
+    n = 5000
+    rng = np.random.default_rng(1)
+    rp = np.arange(n + 1, dtype=np.int32)
+    ci = np.arange(n, dtype=np.int32)
+    v = 1.0 + rng.random(n)
+    b = rng.standard_normal(n)
+    h = oracle.Hierarchy(n, rp, ci, v)
+    ref = h.pcg(oracle.PREC_COMBINED, b, 1e-10, 100)
+    with cpc.Solver(n, rp, ci, v) as s:
+        assert s.hierarchy()["n"] == [m for m, _ in h.level_sizes()]
+        x, it, rel, st = s.solve(dev(b), tol=1e-10)
+        assert st == 0 and it == ref["iters"] == 1
+        assert relerr(x.cpu().numpy(), b / v) <= 1e-15
+    # 40 disconnected 5 x 5 x 2 blocks in one matrix, each block's values scaled
+    q = gen.scaled_config(5, 0.05)
+    k = 40
+    rows, cols, vals = [], [], []
+    for j in range(k):
+        r = np.repeat(np.arange(q.n), np.diff(q.row_ptr)) + j * q.n
+        rows.append(r)
+        cols.append(q.col.astype(np.int64) + j * q.n)
+        vals.append(q.val * (1.0 + 0.1 * j))
+    rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+    N = k * q.n
+    crp = np.zeros(N + 1, np.int32)
+    np.add.at(crp, rows + 1, 1)
+    crp = np.cumsum(crp).astype(np.int32)
+    cci = cols.astype(np.int32)
+    bb = rng.standard_normal(N)
+    h2 = oracle.Hierarchy(N, crp, cci, vals)
+    ref2 = h2.pcg(oracle.PREC_COMBINED, bb, 1e-10, 1000)
+    with cpc.Solver(N, crp, cci, vals) as s:
+        assert s.hierarchy()["n"] == [m for m, _ in h2.level_sizes()]
+        x, it, rel, st = s.solve(dev(bb), tol=1e-10)
+        assert st == 0 and ref2["status"] == 0
+        if it != ref2["iters"]:  # the parity protocol's crossing rule
+            assert abs(it - ref2["iters"]) == 1
+            assert abs(ref2["hist"][min(it, ref2["iters"])] - 1e-10) <= 1e-12 * 1e-10
+        x2, it2, _, _ = s.solve(dev(bb), tol=0.0, maxit=ref2["iters"])
+        assert relerr(x2.cpu().numpy(), ref2["x"]) <= 1e-10
+
+
 def test_combined_is_symmetric_positive_on_device(cases):
     """Theorem 2.1 on the device operator: <B u, v> = <u, B v>, u^T B u > 0."""
     p, h, s = cases["c3s"]
