@@ -987,18 +987,21 @@ static double blockdense_cap() {
   return std::min(96e9, 0.6 * (double)free_b);
 }
 
-// Bytes of the block form with B-row blocks over the row ranges `parts` (each cut on
-// its own, the last block of a range short): 8 per inverse entry, inverse and
-// transpose. One forward plus one backward solve reads all of them once, so at the
-// HBM peak of 8 TB/s that pair takes at least bytes / 8e12 seconds.
-static double blockdense_bytes(const std::vector<int>& parts, int B) {
-  double bytes = 0.0;
+// Sum of the squares of the block sizes of the block form with B-row blocks over the
+// row ranges `parts` (each cut on its own, the last block of a range short). The form
+// stores each block's inverse and its transpose as FP64 squares first (16 bytes per
+// entry of the sum: the memory bound), and one forward plus one backward solve reads
+// the lower triangle of the one and the upper triangle of the other, at least an
+// entry's width per entry of the sum, so at the HBM peak of 8 TB/s that pair takes at
+// least width x sum / 8e12 seconds.
+static double blockdense_squares(const std::vector<int>& parts, int B) {
+  double sq = 0.0;
   for (size_t p = 0; p + 1 < parts.size(); ++p) {
     const double s = parts[p + 1] - parts[p];
     const double full = std::floor(s / B), tail = s - full * B;
-    bytes += 16.0 * (full * B * (double)B + tail * tail);
+    sq += full * B * (double)B + tail * tail;
   }
-  return bytes;
+  return sq;
 }
 static constexpr double kDenseMaxBytes = 64e9;
 static constexpr int kDenseTransRows = 16384;
@@ -1586,7 +1589,9 @@ static void tune_sweeps(cpc_solver* h) {
                                         ? L.parts
                                         : std::vector<int>{0, L.sweep_rows};
     // lower bound (ms) of one forward + backward block solve: its inverses read at the HBM peak
-    auto bd_floor = [&](int B) { return (float)(blockdense_bytes(lparts, B) / 8e12 * 1e3); };
+    const double ewidth = h->f32 ? 4.0 : 8.0;
+    auto bd_floor = [&](int B) { return (float)(ewidth * blockdense_squares(lparts, B) / 8e12 * 1e3); };
+    auto bd_mem = [&](int B) { return 16.0 * blockdense_squares(lparts, B); };
     int qB = 4096;
     const double cap = blockdense_cap();
     float ts = 0.f;
@@ -1594,9 +1599,9 @@ static void tune_sweeps(cpc_solver* h) {
       ts = gs_cost();
       // the look decides only when the form is 1.5x ahead: a block size whose inverses
       // alone take longer to read than ts / 1.5 cannot do that
-      while (qB > 1024 && (blockdense_bytes(lparts, qB) > cap || 1.5f * bd_floor(qB) >= ts)) qB /= 2;
+      while (qB > 1024 && (bd_mem(qB) > cap || 1.5f * bd_floor(qB) >= ts)) qB /= 2;
     }
-    if (try_r && bd_ok && !L.dense_smooth && qB < L.sweep_rows && blockdense_bytes(lparts, qB) <= cap &&
+    if (try_r && bd_ok && !L.dense_smooth && qB < L.sweep_rows && bd_mem(qB) <= cap &&
         1.5f * bd_floor(qB) < ts) {
       progress(h, "level " + std::to_string(d) + ": block substitution with " + std::to_string(qB) + "-row blocks");
       if (build_blockdense(h, L, sub, qB)) {
@@ -1726,14 +1731,17 @@ static void tune_sweeps(cpc_solver* h) {
           std::swap(keep.bd, L.bd);
         }
       };
-      // block sizes from the middle out; 1024 and 8192 only where the model
-      // t(B) = a / B + c B fitted to the 2048 and 4096 timings predicts a gain
+      // block sizes from the middle out; 8192 only where the model t(B) = a / B + c B
+      // fitted to the 2048 and 4096 timings predicts a gain, 1024 unless 4096 beat 2048
+      // (in a batch, where each step takes a block of every system, the times do not
+      // follow that model on the small side)
       for (int B : {4096, 2048, 8192, 1024}) {
         if (B >= L.sweep_rows) continue;
         if (L.bdense && L.bd.B == B) continue;  // kept from the quick look
         if (!(bd_floor(B) < gbest)) continue;   // reading its inverses alone takes longer
         if (bd_time.count(B) && !(bd_time[B] < gbest)) continue;  // timed in the quick look
-        if ((B == 8192 || B == 1024) && bd_time.count(2048) && bd_time.count(4096)) {
+        if (B == 1024 && bd_time.count(2048) && bd_time.count(4096) && bd_time[4096] < bd_time[2048]) continue;
+        if (B == 8192 && bd_time.count(2048) && bd_time.count(4096)) {
           const double t2 = bd_time[2048], t4 = bd_time[4096];
           const double c = (2.0 * t4 - t2) / (2.0 * 4096.0 - 2048.0);  // from t2 = a/2048 + 2048c, t4 = a/4096 + 4096c
           const double a = (t2 - 2048.0 * c) * 2048.0;
