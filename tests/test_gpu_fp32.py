@@ -58,3 +58,34 @@ def test_fp32_preconditioner_reaches_fp64_accuracy(case):
     assert tr <= p.tol * 1.05
     assert it32 <= it64 + 1
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("form", ["never", "always", "block"])
+def test_fp32_every_smoother_form(form):
+    """The FP32 preconditioner with each Gauss-Seidel form forced (level-scheduled
+    sweeps only, whole-level explicit inverses where they fit, block substitution
+    with 2048-row blocks): the combined operator within 1e-6 of the FP64 oracle and
+    the solve to the FP64 oracle's solution within 1e-10, as above."""
+    import paper_1205_6113_amd as cpc
+    p = gen.scaled_config(2, 0.3)
+    h = oracle.Hierarchy(p.n, p.row_ptr, p.col, p.val)
+    ro = h.pcg(oracle.PREC_COMBINED, p.b, p.tol, 10000)
+    b = torch.as_tensor(p.b, device="cuda")
+    with cpc.Solver(p.n, p.row_ptr, p.col, p.val, precision="fp32", dense_smoother=form) as s:
+        kinds = s.hierarchy()["smoother"]
+        want = {"never": "sweep", "always": "dense", "block": "block"}[form]
+        assert want in kinds, kinds
+        r = np.random.default_rng(3).standard_normal(p.n)
+        z = s.apply("combined", torch.as_tensor(r, device="cuda")).cpu().numpy()
+        zr = h.apply(oracle.PREC_COMBINED, r)
+        err_op = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+        x, it, rel, st = s.solve(b, tol=p.tol)
+    assert st == 0
+    x = x.cpu().numpy()
+    err = np.linalg.norm(x - ro["x"]) / np.linalg.norm(ro["x"])
+    print(f"[fp32] form {form} ({kinds}): operator error {err_op:.3e}, iters {it} (oracle {ro['iters']}), "
+          f"x err {err:.3e}", flush=True)
+    assert err_op <= 1e-6
+    assert _true_relres(p, x) <= p.tol * 1.05
+    assert it <= ro["iters"] + 1
+    assert err <= 1e-10
