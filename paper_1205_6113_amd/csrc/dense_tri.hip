@@ -140,44 +140,60 @@ __device__ __forceinline__ void item_products(const char* __restrict__ Mb, const
   using VT = typename V::T;
   constexpr int W = V::N, H = kHalfRows, D = row_steps<MT>();
   static_assert(!FV || sizeof(XT) == sizeof(MT), "vector input reads assume input and inverse of one type");
+  // one step's loads: the four row vectors at list entry vd (the first entry again past
+  // the list) and the input entries there; sel 1: group A, 0: group B, -1: past the list
+  auto load_step = [&](int vd, int vfirst, VT (&mr)[H], XT (&fr)[W], double& sl) {
+    const int v = vd < len ? vd : vfirst;
+    const bool ina = v < la;
+    const int c = ina ? sa + v : sb + (v - la);
+    const unsigned oc = (unsigned)c * (unsigned)sizeof(VT);
+#pragma unroll
+    for (int r = 0; r < H; ++r) mr[r] = V::load(Mb + ((ina ? oa[r] : ob[r]) + oc));
+    if constexpr (FV) {
+      using FT = typename Vec16<XT>::T;
+      const FT t = *reinterpret_cast<const FT*>(fb + oc);
+#pragma unroll
+      for (int k = 0; k < W; ++k) fr[k] = t[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < W; ++k)
+        fr[k] = *reinterpret_cast<const XT*>(fb + (unsigned)min(c * W + k, n - 1) * (unsigned)sizeof(XT));
+    }
+    sl = vd < len ? (ina ? 1.0 : 0.0) : -1.0;
+  };
+  auto use_step = [&](const VT (&mr)[H], const XT (&fr)[W], double sl) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const double fk = (double)fr[k];
+      const double fka = sl == 1.0 ? fk : 0.0, fkb = sl == 0.0 ? fk : 0.0;
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        const double e = V::at(mr[r], k);
+        acc[r] = fma(e, fka, acc[r]);
+        acc[H + r] = fma(e, fkb, acc[H + r]);
+      }
+    }
+  };
   for (int v0 = threadIdx.x; v0 < len; v0 += D * kNT) {
     VT m[D][H];
     XT fv[D][W];
-    double sel[D];  // 1: group A, 0: group B, -1: past the list
+    double sel[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int vd = v0 + d * kNT;
-      const int v = vd < len ? vd : v0;  // a step past the list reads the first one again
-      const bool ina = v < la;
-      const int c = ina ? sa + v : sb + (v - la);
-      const unsigned oc = (unsigned)c * (unsigned)sizeof(VT);
+    for (int d = 0; d < D; ++d) load_step(v0 + d * kNT, v0, m[d], fv[d], sel[d]);
+    // when fewer than kNT entries would be left for another round (two per item of a
+    // 4096-row block: its groups read n + 4 columns), the lanes they fall on load them
+    // with this batch instead of in a dependent second round
+    const int rest = len - (v0 - (int)threadIdx.x) - D * kNT;  // uniform
+    const bool tail_round = rest > 0 && rest <= kNT;
+    VT mt[H];
+    XT ft[W];
+    double st = -1.0;
+    if (tail_round && v0 + D * kNT < len) load_step(v0 + D * kNT, v0, mt, ft, st);
 #pragma unroll
-      for (int r = 0; r < H; ++r) m[d][r] = V::load(Mb + ((ina ? oa[r] : ob[r]) + oc));
-      if constexpr (FV) {
-        using FT = typename Vec16<XT>::T;
-        const FT t = *reinterpret_cast<const FT*>(fb + oc);
-#pragma unroll
-        for (int k = 0; k < W; ++k) fv[d][k] = t[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < W; ++k)
-          fv[d][k] = *reinterpret_cast<const XT*>(fb + (unsigned)min(c * W + k, n - 1) * (unsigned)sizeof(XT));
-      }
-      sel[d] = vd < len ? (ina ? 1.0 : 0.0) : -1.0;
-    }
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-#pragma unroll
-      for (int k = 0; k < W; ++k) {
-        const double fk = (double)fv[d][k];
-        const double fka = sel[d] == 1.0 ? fk : 0.0, fkb = sel[d] == 0.0 ? fk : 0.0;
-#pragma unroll
-        for (int r = 0; r < H; ++r) {
-          const double e = V::at(m[d][r], k);
-          acc[r] = fma(e, fka, acc[r]);
-          acc[H + r] = fma(e, fkb, acc[H + r]);
-        }
-      }
+    for (int d = 0; d < D; ++d) use_step(m[d], fv[d], sel[d]);
+    if (tail_round) {
+      if (v0 + D * kNT < len) use_step(mt, ft, st);
+      break;
     }
   }
 }
