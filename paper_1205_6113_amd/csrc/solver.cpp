@@ -1582,7 +1582,8 @@ static void tune_sweeps(cpc_solver* h) {
     // quick look: where block substitution already beats the sweeps by half, tuning the
     // sweeps' block size cannot change the outcome and is skipped (the block form stays
     // as the candidate to beat). Blocks of 4096 rows, or of 2048 / 1024 where the larger
-    // inverses would not fit the form's memory bound (batch levels of a million rows).
+    // inverses would not fit the form's memory bound or could not be read fast enough
+    // to be that far ahead (batch levels of a million rows).
     std::map<int, float> bd_time;  // measured block-substitution candidates
     bool skip_r = false;
     const std::vector<int> lparts = (!L.parts.empty() && L.parts.front() == 0 && L.parts.back() == L.sweep_rows)
