@@ -121,9 +121,11 @@ struct Vec16 {
   __device__ static double at(const T& v, int k) { return (double)v[k]; }
 };
 
-// Entries of the flat vector list a thread loads before it uses any of them: 8 x (4 row
-// vectors + 2 input entries) in FP64, 4 x (4 + 4) in FP32 (a vector spans twice the
-// columns), about 200 registers, two waves per SIMD.
+// Entries of the flat vector list a thread loads before it uses any of them, at most: 8 x
+// (4 row vectors + 2 input entries) in FP64, 4 x (4 + 4) in FP32 (a vector spans twice
+// the columns), about 200 registers, two waves per SIMD. Launches over smaller systems
+// take fewer steps per batch (row_steps_for), so that no thread issues loads of steps
+// past its list.
 template <typename MT>
 constexpr int row_steps() { return sizeof(MT) == 8 ? 8 : 4; }
 
@@ -132,13 +134,13 @@ constexpr int row_steps() { return sizeof(MT) == 8 ? 8 : 4; }
 // vector are read as one 16-byte vector, which needs the system's part of the input
 // 16-byte aligned and n a multiple of the vector width (every vector then lies inside
 // it); otherwise they are read one by one, the index clamped to the system.
-template <bool FV, typename MT, typename XT>
+template <bool FV, typename MT, typename XT, int D>
 __device__ __forceinline__ void item_products(const char* __restrict__ Mb, const char* __restrict__ fb, int n,
                                               int sa, int la, int sb, int len, const unsigned (&oa)[kHalfRows],
                                               const unsigned (&ob)[kHalfRows], double (&acc)[2 * kHalfRows]) {
   using V = Vec16<MT>;
   using VT = typename V::T;
-  constexpr int W = V::N, H = kHalfRows, D = row_steps<MT>();
+  constexpr int W = V::N, H = kHalfRows;
   static_assert(!FV || sizeof(XT) == sizeof(MT), "vector input reads assume input and inverse of one type");
   // one step's loads: the four row vectors at list entry vd (the first entry again past
   // the list) and the input entries there; sel 1: group A, 0: group B, -1: past the list
@@ -220,7 +222,7 @@ __device__ __forceinline__ void item_products(const char* __restrict__ Mb, const
 // then the four waves' sums.
 // At most two waves per SIMD: the compiler may then keep a whole batch of loads in
 // registers (it otherwise schedules for eight waves and issues one load at a time).
-template <bool UPPER, typename MT, typename XT>
+template <bool UPPER, typename MT, typename XT, int D>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) void gemv_tri_rows_kernel(
     DenseTriDev dt, const XT* __restrict__ f, XT* __restrict__ y, const int* __restrict__ done) {
   using V = Vec16<MT>;
@@ -275,9 +277,9 @@ __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
   for (int r = 0; r < 2 * H; ++r) acc[r] = 0.0;
   if ((reinterpret_cast<unsigned long>(fs) & 15) == 0 && n % W == 0)
-    item_products<true, MT, XT>(Mb, fb, n, sa, la, sb, len, oa, ob, acc);
+    item_products<true, MT, XT, D>(Mb, fb, n, sa, la, sb, len, oa, ob, acc);
   else
-    item_products<false, MT, XT>(Mb, fb, n, sa, la, sb, len, oa, ob, acc);
+    item_products<false, MT, XT, D>(Mb, fb, n, sa, la, sb, len, oa, ob, acc);
   wave_sums(acc);  // valid in lane 0
   if (lane == 0)
 #pragma unroll
@@ -364,16 +366,39 @@ void dense_row_items(int sys, int n, std::vector<int4>& items) {
   }
 }
 
+// Steps per batch for a launch whose largest system has n rows: an item's list holds
+// about (n + 4) / W vectors (its two groups' columns), and a batch of D steps plus the
+// same-batch tail takes (D + 1) x 256 of them; the fewest steps that cover the list in
+// one batch, at most row_steps (larger systems take several batches).
+template <typename T>
+static int row_steps_for(int n) {
+  constexpr int W = 16 / (int)sizeof(T);
+  const int len = n > 0 ? (n + 4 + W - 1) / W : 1 << 30;
+  int d = 1;
+  while (d < row_steps<T>() && (d + 1) * kNT < len) d *= 2;
+  return d;
+}
+
+template <bool UP, typename T, int D>
+static void rows_launch_d(hipStream_t s, const DenseTriDev& dt, const void* f, void* y, const int* done,
+                          hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0 && ev1)
+    hipExtLaunchKernelGGL(gemv_tri_rows_kernel<UP, T, T, D>, dim3(dt.nitem_n), dim3(kNT), 0, s, ev0, ev1, 0, dt,
+                          (const T*)f, (T*)y, done);
+  else
+    gemv_tri_rows_kernel<UP, T, T, D><<<dt.nitem_n, kNT, 0, s>>>(dt, (const T*)f, (T*)y, done);
+}
+
 // One row-product launch; with events, the dispatch itself stamps its start and end
 // into them (measurement only).
 template <bool UP, typename T>
 static void rows_launch(hipStream_t s, const DenseTriDev& dt, const void* f, void* y, const int* done,
                         hipEvent_t ev0, hipEvent_t ev1) {
-  if (ev0 && ev1)
-    hipExtLaunchKernelGGL(gemv_tri_rows_kernel<UP, T, T>, dim3(dt.nitem_n), dim3(kNT), 0, s, ev0, ev1, 0, dt,
-                          (const T*)f, (T*)y, done);
-  else
-    gemv_tri_rows_kernel<UP, T, T><<<dt.nitem_n, kNT, 0, s>>>(dt, (const T*)f, (T*)y, done);
+  const int d = row_steps_for<T>(dt.one_n > 0 ? dt.one_n : dt.max_n);
+  if (d == 1) rows_launch_d<UP, T, 1>(s, dt, f, y, done, ev0, ev1);
+  else if (d == 2) rows_launch_d<UP, T, 2>(s, dt, f, y, done, ev0, ev1);
+  else if (d == 4) rows_launch_d<UP, T, 4>(s, dt, f, y, done, ev0, ev1);
+  else rows_launch_d<UP, T, row_steps<T>()>(s, dt, f, y, done, ev0, ev1);
 }
 
 void launch_dense_lower(hipStream_t s, const DenseTriDev& dt, bool mfp32, bool xfp32, const void* f, void* y,

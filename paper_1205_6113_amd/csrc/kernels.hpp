@@ -212,6 +212,7 @@ struct DenseTriDev {
   int one_voff;
   long one_moff;
   int one_sys;     // the system index (of mask) of a one_n launch
+  int max_n = 0;   // rows of the launch's largest system (0: unknown), for the product's steps per batch
   SysMask mask{};  // by system index of the list (a block of the block-dense form)
 };
 // Row stride of a stored n x n inverse: n rounded up to a multiple of 4 elements, so

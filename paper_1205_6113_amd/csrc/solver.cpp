@@ -1082,6 +1082,7 @@ static void build_dense(cpc_solver* h, Level& L, const std::vector<int>& ns, con
     }
   }
   DenseTriDev& dt = L.dtri;
+  dt.max_n = *std::max_element(ns.begin(), ns.end());
   dt.n = dupload(ns, h->owned, h->stream);
   dt.moff = dupload(moff, h->owned, h->stream);
   dt.voff = dupload(voffs, h->owned, h->stream);
@@ -1489,6 +1490,8 @@ static DenseTriDev bd_step(const Level& L, bool upper, int t) {
   dt.item_n = (upper ? bd.items_b : bd.items_f) + item[t];
   dt.nitem_n = item[t + 1] - item[t];
   dt.one_n = 0;
+  dt.max_n = 0;
+  for (int q = step[t]; q < step[t + 1]; ++q) dt.max_n = std::max(dt.max_n, bd.rows[upper ? bd.bblk[q] : q]);
   if (step[t + 1] - step[t] == 1) {  // one block: its rows and offsets need no table reads
     const int b = upper ? bd.bblk[step[t]] : step[t];
     dt.one_n = bd.rows[b];
